@@ -1,0 +1,356 @@
+"""The HOPU convection operator, mass matrix, substeps, diagnostics and
+adjoints (oracle; test infrastructure only).  Plain definitions evaluated in
+physical coordinates, element and facet loops vectorised over batches.
+
+Residual (conservative volume form; the paper writes the volume term in the
+advective form (grad u u) . v, eq. (upwind) and eq. (hopudefinition); the two
+differ by -sum_T int (div u)(u . v), zero for divergence-free u):
+
+  r_i(u) = - sum_T int_T (u x u) : grad phi_i dx
+           + sum_{E in F^I} int_E (u.n) <u> . [[phi_i]]
+                              + 1/2 |u.n| (I - Pi^l)[[u]] . (I - Pi^l)[[phi_i]] ds
+
+with (a x b):grad v = sum a_i b_j d_j v_i, n the outward normal of the element
+called T, [[f]] = f^T - f^T', <f> = (f^T + f^T')/2 (section 2.1) and Pi^l the
+facet-wise L2 projection onto polynomials of degree <= l computed with the
+facet rule (section 3.2); l = -1 means Pi = 0 (standard upwind, eq. (upwind)),
+l = k means Pi = I (central flux).
+"""
+import numpy as np
+import scipy.sparse as sps
+import scipy.sparse.linalg as spla
+
+TERM_VOLUME, TERM_CENTRAL, TERM_UPWIND = 1, 2, 4
+TERM_ALL = 7
+
+
+# ------------------------------------------------------------------ facets
+def _facet_batches(sp, size=2048):
+    t = sp.topo
+    for s in range(0, t.n_facets, size):
+        yield np.arange(s, min(t.n_facets, s + size))
+
+
+def _facet_traces(sp, fb):
+    """Physical basis traces of both neighbours at the facet points and
+    the facet geometry: phiT, phiT2 [B][nqf][n][d], n [B][d], ds [B][nqf]."""
+    t = sp.topo
+    T, T2 = t.facet_elems[fb, 0], t.facet_elems[fb, 1]
+    i, i2 = t.facet_local[fb, 0], t.facet_local[fb, 1]
+    phiT = np.empty((len(fb), len(sp.wsq), sp.n, sp.dim))
+    phiT2 = np.empty_like(phiT)
+    for loc in range(sp.dim + 1):
+        m = i == loc
+        if m.any():
+            phiT[m] = sp.phys_vals(T[m], sp.ref_face[loc])
+        m = i2 == loc
+        if m.any():
+            phiT2[m] = sp.phys_vals(T2[m], sp.ref_face[loc])
+    nvec = (t.sigma[T, i] / t.NF_norm[T, i])[:, None] * t.NF[T, i]
+    ds = t.NF_norm[T, i][:, None] * sp.wsq[None, :]
+    return T, T2, phiT, phiT2, nvec, ds
+
+
+def _projector(sp, lf):
+    """Matrices P_f [B][nqf][nqf] of the discrete L2 projection onto facet
+    polynomials of degree <= l_f:  (P f)_q = sum_{deg psi_j <= l} psi_j(q)
+    sum_q' w_q' psi_j(q') f_q'."""
+    psi, w = sp.psi_q, sp.wsq
+    mask = (sp.psi_deg[None, :] <= lf[:, None]).astype(float)  # [B][nf]
+    return np.einsum("qj,bj,pj,p->bqp", psi, mask, psi, w)
+
+
+def residual(sp, x, l, terms=TERM_ALL):
+    t = sp.topo
+    r = np.zeros(sp.n_dof)
+    if terms & TERM_VOLUME:
+        for eb in sp.batches(t.n_elems, sp.elem_batch_size()):
+            xl = sp.local(x, eb)
+            phi = sp.phys_vals(eb, sp.ref_vals)
+            gphi = sp.phys_grads(eb, sp.ref_grads)
+            u = np.einsum("bqid,bi->bqd", phi, xl)
+            wdx = sp.wq[None, :] * np.abs(t.detJ[eb])[:, None]
+            val = np.einsum("bq,bqa,bqc,bqiac->bi", wdx, u, u, gphi)
+            sp.scatter(r, eb, -val)
+    if terms & (TERM_CENTRAL | TERM_UPWIND):
+        lf_all = sp.facet_l(l)
+        for fb in _facet_batches(sp):
+            T, T2, phiT, phiT2, nvec, ds = _facet_traces(sp, fb)
+            uT = np.einsum("bqid,bi->bqd", phiT, sp.local(x, T))
+            uT2 = np.einsum("bqid,bi->bqd", phiT2, sp.local(x, T2))
+            avg = 0.5 * (uT + uT2)
+            jump = uT - uT2
+            un = np.einsum("bqd,bd->bq", avg, nvec)
+            rT = np.zeros((len(fb), sp.n))
+            rT2 = np.zeros((len(fb), sp.n))
+            if terms & TERM_CENTRAL:
+                g = un[:, :, None] * avg
+                rT += np.einsum("bq,bqd,bqid->bi", ds, g, phiT)
+                rT2 -= np.einsum("bq,bqd,bqid->bi", ds, g, phiT2)
+            if terms & TERM_UPWIND:
+                P = _projector(sp, lf_all[fb])
+                jp = jump - np.einsum("bqp,bpd->bqd", P, jump)
+                tT = phiT - np.einsum("bqp,bpid->bqid", P, phiT)    # (I-Pi) phi^T
+                tT2 = phiT2 - np.einsum("bqp,bpid->bqid", P, phiT2)
+                a = 0.5 * np.abs(un) * ds
+                rT += np.einsum("bq,bqd,bqid->bi", a, jp, tT)
+                rT2 -= np.einsum("bq,bqd,bqid->bi", a, jp, tT2)
+            sp.scatter(r, T, rT)
+            sp.scatter(r, T2, rT2)
+    return r
+
+
+def residual_advective(sp, x, l, upwind=True):
+    """The paper's form, eq. (hopudefinition):
+    sum_T int (grad u u).v - sum_E int (u.n)[[u]].<v> + upwind term."""
+    t = sp.topo
+    r = np.zeros(sp.n_dof)
+    for eb in sp.batches(t.n_elems, sp.elem_batch_size()):
+        xl = sp.local(x, eb)
+        phi = sp.phys_vals(eb, sp.ref_vals)
+        gphi = sp.phys_grads(eb, sp.ref_grads)
+        u = np.einsum("bqid,bi->bqd", phi, xl)
+        gu = np.einsum("bqiac,bi->bqac", gphi, xl)   # d_c u_a
+        conv = np.einsum("bqac,bqc->bqa", gu, u)
+        wdx = sp.wq[None, :] * np.abs(t.detJ[eb])[:, None]
+        sp.scatter(r, eb, np.einsum("bq,bqa,bqia->bi", wdx, conv, phi))
+    lf_all = sp.facet_l(l)
+    for fb in _facet_batches(sp):
+        T, T2, phiT, phiT2, nvec, ds = _facet_traces(sp, fb)
+        uT = np.einsum("bqid,bi->bqd", phiT, sp.local(x, T))
+        uT2 = np.einsum("bqid,bi->bqd", phiT2, sp.local(x, T2))
+        jump = uT - uT2
+        un = np.einsum("bqd,bd->bq", 0.5 * (uT + uT2), nvec)
+        g = -(un * ds)[:, :, None] * jump
+        rT = 0.5 * np.einsum("bqd,bqid->bi", g, phiT)
+        rT2 = 0.5 * np.einsum("bqd,bqid->bi", g, phiT2)
+        if upwind:
+            P = _projector(sp, lf_all[fb])
+            jp = jump - np.einsum("bqp,bpd->bqd", P, jump)
+            tT = phiT - np.einsum("bqp,bpid->bqid", P, phiT)
+            tT2 = phiT2 - np.einsum("bqp,bpid->bqid", P, phiT2)
+            a = 0.5 * np.abs(un) * ds
+            rT += np.einsum("bq,bqd,bqid->bi", a, jp, tT)
+            rT2 -= np.einsum("bq,bqd,bqid->bi", a, jp, tT2)
+        sp.scatter(r, T, rT)
+        sp.scatter(r, T2, rT2)
+    return r
+
+
+# ------------------------------------------------------------------ mass
+def mass_matrix(sp):
+    """M_ij = int phi_i . phi_j (the paper's M_uu = M / dt, section 2.3)."""
+    cache = getattr(sp, "_mass", None)
+    if cache is not None:
+        return cache
+    t = sp.topo
+    rows, cols, vals = [], [], []
+    for eb in sp.batches(t.n_elems, max(1, sp.elem_batch_size() * sp.dim)):
+        phi = sp.phys_vals(eb, sp.ref_vals)
+        wdx = sp.wq[None, :] * np.abs(t.detJ[eb])[:, None]
+        Me = np.einsum("bq,bqid,bqjd->bij", wdx, phi, phi)
+        g = sp.gdof[eb]
+        gi = np.broadcast_to(g[:, :, None], Me.shape)
+        gj = np.broadcast_to(g[:, None, :], Me.shape)
+        m = (gi >= 0) & (gj >= 0)
+        rows.append(gi[m])
+        cols.append(gj[m])
+        vals.append(Me[m])
+    M = sps.coo_matrix((np.concatenate(vals), (np.concatenate(rows),
+                        np.concatenate(cols))), shape=(sp.n_dof, sp.n_dof)).tocsr()
+    sp._mass = M
+    return M
+
+
+def mass_solve(sp, r):
+    """w = M^{-1} r: sparse LU for small spaces, CG to 1e-15 otherwise."""
+    M = mass_matrix(sp)
+    if sp.n_dof <= 200000:
+        lu = getattr(sp, "_mass_lu", None)
+        if lu is None:
+            lu = spla.splu(M.tocsc())
+            sp._mass_lu = lu
+        return lu.solve(r)
+    d = M.diagonal()
+    pre = spla.LinearOperator(M.shape, matvec=lambda v: v / d)
+    w, info = spla.cg(M, r, rtol=1e-15, atol=0.0, maxiter=5000, M=pre)
+    if info != 0:
+        raise RuntimeError("oracle CG did not converge")
+    return w
+
+
+# ------------------------------------------------------------ substeps
+def substep(sp, x, dt, l):
+    """u <- u - dt M^{-1} r(u): the explicit convection part of step 1
+    (eq. (MCS_step1) with M_uu = M/dt)."""
+    return x - dt * mass_solve(sp, residual(sp, x, l))
+
+
+def substeps(sp, x0, dt, n_steps, l, keep=False):
+    xs = [x0]
+    x = x0
+    for _ in range(n_steps):
+        x = substep(sp, x, dt, l)
+        if keep:
+            xs.append(x)
+    return xs if keep else x
+
+
+# ------------------------------------------------------------ diagnostics
+def energy(sp, x):
+    return 0.5 * float(x @ (mass_matrix(sp) @ x))
+
+
+def divergence_l2(sp, x):
+    t = sp.topo
+    acc = 0.0
+    for eb in sp.batches(t.n_elems, sp.elem_batch_size()):
+        gphi = sp.phys_grads(eb, sp.ref_grads)
+        gu = np.einsum("bqiac,bi->bqac", gphi, sp.local(x, eb))
+        div = np.einsum("bqaa->bq", gu)
+        acc += float(np.sum(sp.wq[None, :] * np.abs(t.detJ[eb])[:, None] * div ** 2))
+    return np.sqrt(acc)
+
+
+def dissipation(sp, x, l):
+    """D = sum_E int_E 1/2 |u.n| |(I - Pi^l)[[u]]|^2 ds."""
+    lf_all = sp.facet_l(l)
+    acc = 0.0
+    for fb in _facet_batches(sp):
+        T, T2, phiT, phiT2, nvec, ds = _facet_traces(sp, fb)
+        uT = np.einsum("bqid,bi->bqd", phiT, sp.local(x, T))
+        uT2 = np.einsum("bqid,bi->bqd", phiT2, sp.local(x, T2))
+        jump = uT - uT2
+        un = np.einsum("bqd,bd->bq", 0.5 * (uT + uT2), nvec)
+        P = _projector(sp, lf_all[fb])
+        jp = jump - np.einsum("bqp,bpd->bqd", P, jump)
+        acc += float(np.sum(0.5 * np.abs(un) * ds * np.sum(jp ** 2, -1)))
+    return acc
+
+
+# ------------------------------------------------------------ adjoints
+def vjp(sp, x, mu, l):
+    """(J_r(u)^T mu)_j = d/du_j sum_i mu_i r_i(u), with mu_h = sum mu_i phi_i:
+      - sum_T int phi_j . (grad mu_h + grad mu_h^T) u
+      + sum_E int (phi_j.n) s + (u.n) <phi_j>.[[mu_h]]
+                  + 1/2 |u.n| (I-Pi)[[phi_j]] . (I-Pi)[[mu_h]]
+      s = <u>.[[mu_h]] + 1/2 sgn(u.n) (I-Pi)[[u]] . (I-Pi)[[mu_h]], sgn(0) = 0;
+    phi_j . n is single valued and equals <phi_j> . n."""
+    t = sp.topo
+    out = np.zeros(sp.n_dof)
+    for eb in sp.batches(t.n_elems, sp.elem_batch_size()):
+        phi = sp.phys_vals(eb, sp.ref_vals)
+        gphi = sp.phys_grads(eb, sp.ref_grads)
+        u = np.einsum("bqid,bi->bqd", phi, sp.local(x, eb))
+        gm = np.einsum("bqiac,bi->bqac", gphi, sp.local(mu, eb))  # d_c mu_a
+        v = np.einsum("bqac,bqc->bqa", gm, u) + np.einsum("bqca,bqc->bqa", gm, u)
+        wdx = sp.wq[None, :] * np.abs(t.detJ[eb])[:, None]
+        sp.scatter(out, eb, -np.einsum("bq,bqa,bqia->bi", wdx, v, phi))
+    lf_all = sp.facet_l(l)
+    for fb in _facet_batches(sp):
+        T, T2, phiT, phiT2, nvec, ds = _facet_traces(sp, fb)
+        uT = np.einsum("bqid,bi->bqd", phiT, sp.local(x, T))
+        uT2 = np.einsum("bqid,bi->bqd", phiT2, sp.local(x, T2))
+        mT = np.einsum("bqid,bi->bqd", phiT, sp.local(mu, T))
+        mT2 = np.einsum("bqid,bi->bqd", phiT2, sp.local(mu, T2))
+        avg = 0.5 * (uT + uT2)
+        un = np.einsum("bqd,bd->bq", avg, nvec)
+        P = _projector(sp, lf_all[fb])
+        ju = uT - uT2
+        jm = mT - mT2
+        jup = ju - np.einsum("bqp,bpd->bqd", P, ju)
+        jmp = jm - np.einsum("bqp,bpd->bqd", P, jm)
+        s = np.sum(avg * jm, -1) + 0.5 * np.sign(un) * np.sum(jup * jmp, -1)
+        tT = phiT - np.einsum("bqp,bpid->bqid", P, phiT)
+        tT2 = phiT2 - np.einsum("bqp,bpid->bqid", P, phiT2)
+        phin_T = np.einsum("bqid,bd->bqi", phiT, nvec)
+        phin_T2 = np.einsum("bqid,bd->bqi", phiT2, nvec)
+        rT = 0.5 * np.einsum("bq,bqi->bi", ds * s, phin_T)
+        rT2 = 0.5 * np.einsum("bq,bqi->bi", ds * s, phin_T2)
+        rT += 0.5 * np.einsum("bq,bqd,bqid->bi", ds * un, jm, phiT)
+        rT2 += 0.5 * np.einsum("bq,bqd,bqid->bi", ds * un, jm, phiT2)
+        a = 0.5 * np.abs(un) * ds
+        rT += np.einsum("bq,bqd,bqid->bi", a, jmp, tT)
+        rT2 -= np.einsum("bq,bqd,bqid->bi", a, jmp, tT2)
+        sp.scatter(out, T, rT)
+        sp.scatter(out, T2, rT2)
+    return out
+
+
+def mass_apply(sp, x):
+    return mass_matrix(sp) @ x
+
+
+def chain_vjp(sp, x0, dt, n_steps, l, lam_N):
+    """Reverse pass of u_{n+1} = u_n - dt M^{-1} r(u_n):
+    lam_n = lam_{n+1} - dt J_r(u_n)^T M^{-1} lam_{n+1}; returns lam_0."""
+    xs = substeps(sp, x0, dt, n_steps, l, keep=True)
+    lam = lam_N.copy()
+    for s in range(n_steps - 1, -1, -1):
+        mu = mass_solve(sp, lam)
+        lam = lam - dt * vjp(sp, xs[s], mu, l)
+    return lam
+
+
+# ------------------------------------------------------ assembled matrices
+def assemble_picard(sp, w, l, terms=TERM_ALL):
+    """Dense C(w)_ij = c(w; phi_j, phi_i): the residual's bilinear form with
+    convecting field w (reading of the garbled C_uu, section 2.3), built by
+    double loops over physical basis products.  Tiny meshes only."""
+    t = sp.topo
+    N = sp.n_dof
+    C = np.zeros((N, N))
+    for e in range(t.n_elems):
+        eb = np.array([e])
+        phi = sp.phys_vals(eb, sp.ref_vals)[0]
+        gphi = sp.phys_grads(eb, sp.ref_grads)[0]
+        u = np.einsum("qid,i->qd", phi, sp.local(w, eb)[0])
+        wdx = sp.wq * abs(t.detJ[e])
+        g = sp.gdof[e]
+        if terms & TERM_VOLUME:
+            for a_ in range(sp.n):
+                for b_ in range(sp.n):
+                    if g[a_] < 0 or g[b_] < 0:
+                        continue
+                    # -int (phi_j x u) : grad phi_i
+                    v = -np.sum(wdx * np.einsum("qa,qc,qac->q", phi[:, b_], u, gphi[:, a_]))
+                    C[g[a_], g[b_]] += v
+    lf_all = sp.facet_l(l)
+    for f in range(t.n_facets):
+        fb = np.array([f])
+        T, T2, phiT, phiT2, nvec, ds = _facet_traces(sp, fb)
+        phiT, phiT2, nvec, ds = phiT[0], phiT2[0], nvec[0], ds[0]
+        uT = np.einsum("qid,i->qd", phiT, sp.local(w, T)[0])
+        uT2 = np.einsum("qid,i->qd", phiT2, sp.local(w, T2)[0])
+        un = (0.5 * (uT + uT2)) @ nvec
+        P = _projector(sp, lf_all[fb])[0]
+        gT, gT2 = sp.gdof[T[0]], sp.gdof[T2[0]]
+        # basis functions as global functions on the facet: jump / average
+        idx = sorted(set(gT[gT >= 0]) | set(gT2[gT2 >= 0]))
+        tr1, tr2 = {}, {}
+        for gg in idx:
+            a1 = np.zeros((len(ds), sp.dim))
+            a2 = np.zeros((len(ds), sp.dim))
+            for loc in np.nonzero(gT == gg)[0]:
+                a1 += phiT[:, loc]
+            for loc in np.nonzero(gT2 == gg)[0]:
+                a2 += phiT2[:, loc]
+            tr1[gg], tr2[gg] = a1, a2
+        for gi in idx:
+            ji = tr1[gi] - tr2[gi]
+            jip = ji - P @ ji
+            for gj in idx:
+                aj = 0.5 * (tr1[gj] + tr2[gj])
+                jj = tr1[gj] - tr2[gj]
+                jjp = jj - P @ jj
+                v = 0.0
+                if terms & TERM_CENTRAL:
+                    v += np.sum(ds * un * np.sum(aj * ji, -1))
+                if terms & TERM_UPWIND:
+                    v += np.sum(ds * 0.5 * np.abs(un) * np.sum(jjp * jip, -1))
+                C[gi, gj] += v
+    return C
+
+
+def assemble_mass_dense(sp):
+    return mass_matrix(sp).toarray()
