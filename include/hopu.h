@@ -1,0 +1,177 @@
+/* hopu.h -- C ABI of the MI355X HOPU explicit-convection library.
+ *
+ * What the library computes (Lederer, Mooslechner, Schoeberl, "High-order
+ * projection-based upwind method for simulation of transitional turbulent
+ * flows"):
+ *   - the velocity space V_h of normal-continuous piecewise vector
+ *     polynomials of degree k on affine simplices (section 2.2, eq.
+ *     (disc_velspace); read as BDM_k, the full P^k per element), with
+ *     normal velocity zero on wall facets;
+ *   - the convection residual r(u)_i = c_h^HOPU(u, u, phi_i) of section 3.2,
+ *     eq. (hopudefinition), in conservative volume form:
+ *       r_i = - sum_T int_T (u x u) : grad phi_i
+ *             + sum_{E in F^I} int_E (u.n) <u>.[[phi_i]]
+ *               + 1/2 |u.n| (I - Pi^l)[[u]] . (I - Pi^l)[[phi_i]]
+ *     (Pi^l: facet-wise L2 projection onto degree <= l; l = -1 gives the
+ *     standard upwind of eq. (upwind), l = k the central flux);
+ *   - the velocity mass matrix M (M_uu = M/dt in the matrix form of the
+ *     splitting, section 2.3) and its inverse by PCG with the element-wise
+ *     BDDC preconditioner without primal constraints, R blockdiag(M_T)^-1 R^t,
+ *     R the averaging operator (section 2.3);
+ *   - explicit convection substeps u <- u - dt M^-1 r(u) (the explicit part
+ *     of step 1, eq. (MCS_step1));
+ *   - transpose Jacobians of r and of the substep chain.
+ *
+ * Coefficient vectors ("global layout"): FP64, length n_dof =
+ *   [interior-facet block: facets in lexicographic order of their sorted
+ *    vertex-id tuple, n_facet_dof each] ++ [element block: elements in input
+ *    order, n_interior_dof each].
+ * Facet DoF j of facet F: int over the reference facet of (u . n_F) psi_j,
+ * n_F the unit normal (x_b - x_a) x (x_c - x_a) (3D) or rot(x_b - x_a) (2D)
+ * from the facet's vertices in ascending id order, psi_j orthonormal facet
+ * polynomials; interior DoFs: moments of the contravariant Piola pull-back
+ * against gradients of monomials and Koszul fields, scaled by
+ * |det J|^{-(d-1)/d}.  Residual vectors are dual vectors in the same layout.
+ *
+ * Conventions for every call:
+ *   - returns hopu_status; never aborts; HIP errors map to HOPU_EHIP with the
+ *     HIP error string in hopu_last_error();
+ *   - vectors marked "dev" are HIP device pointers (for example a torch
+ *     tensor's data_ptr() on ROCm) owned by the caller; "host" pointers are
+ *     host memory owned by the caller;
+ *   - work is queued on the context's stream; calls marked "syncs" wait for
+ *     it before returning; others are asynchronous;
+ *   - a context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef HOPU_H
+#define HOPU_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hopu_ctx_s* hopu_ctx;
+
+typedef enum {
+  HOPU_OK = 0,
+  HOPU_EINVAL = -1,       /* bad argument (null pointer, k out of range, ...) */
+  HOPU_EMESH = -2,        /* malformed mesh: repeated vertex, det J = 0,
+                             facet in > 2 elements, too few periodic cells */
+  HOPU_ENOMEM = -3,       /* device allocation failed */
+  HOPU_EHIP = -4,         /* HIP runtime error */
+  HOPU_ENOCONV = -5,      /* PCG did not reach the tolerance in max_it */
+  HOPU_EUNSUPPORTED = -6  /* valid request this build does not implement */
+} hopu_status;
+
+typedef enum {
+  HOPU_FP64 = 0,       /* all contractions in FP64 (MFMA f64) */
+  HOPU_FP32_MFMA = 1   /* basis contractions on FP32 MFMA with FP32 accumulation
+                          inside a tile and FP64 across tiles; state, mass
+                          inverse and diagnostics stay FP64 */
+} hopu_precision;
+
+enum { HOPU_TERM_VOLUME = 1, HOPU_TERM_CENTRAL = 2, HOPU_TERM_UPWIND = 4, HOPU_TERM_ALL = 7 };
+
+/* Build the space: dim 2|3, order k 1..5 (k=6 returns HOPU_EUNSUPPORTED),
+ * elem_vid host int64 [n_elems][dim+1] vertex ids with periodic images
+ * identified; elem_xyz host double [n_elems][dim+1][dim] unwrapped vertex
+ * coordinates of each element; hip_stream a hipStream_t (NULL = default).
+ * Host work: topology, geometry, tables; then device allocation and copies.
+ * Syncs. */
+hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elems,
+                        const int64_t* elem_vid, const double* elem_xyz,
+                        void* hip_stream);
+
+/* Sizes of the space; any output pointer may be NULL. */
+hopu_status hopu_sizes(hopu_ctx ctx, int64_t* n_dof, int64_t* n_facets,
+                       int64_t* n_wall_facets, int* n_loc, int* n_facet_dof,
+                       int* n_interior_dof);
+
+/* HOPU projection degree (section 3.2): l_global in -1..k applies to every
+ * facet; l_per_facet_dev (dev int8 [n_facets], nullable) overrides it per
+ * facet.  The pointer is kept and read by later calls. */
+hopu_status hopu_set_upwind(hopu_ctx ctx, int l_global, const int8_t* l_per_facet_dev);
+
+/* PCG controls for mass solves inside substeps and their adjoints:
+ * stop when sqrt(r.z) <= rtol sqrt(b.Pb) (preconditioned residual norm);
+ * check_every: iterations between host reads of the convergence flag. */
+hopu_status hopu_set_solver(hopu_ctx ctx, double rtol, int max_it, int check_every);
+
+/* r = C(u) u: the convection residual (dual vector).  u, r dev [n_dof].
+ * terms: bitmask of HOPU_TERM_*.  Asynchronous. */
+hopu_status hopu_convection_apply(hopu_ctx ctx, const double* u, double* r,
+                                  int terms, hopu_precision prec);
+
+/* y = M u (dev [n_dof] each).  Asynchronous. */
+hopu_status hopu_mass_apply(hopu_ctx ctx, const double* u, double* y);
+
+/* w = M^-1 r by PCG (FP64).  w dev [n_dof] holds the initial guess on entry.
+ * rtol <= 0 selects the context default; *iters (host, nullable) receives the
+ * iteration count.  Syncs.  HOPU_ENOCONV if max_it is reached. */
+hopu_status hopu_mass_solve(hopu_ctx ctx, const double* r, double* w,
+                            double rtol, int max_it, int* iters);
+
+/* n_steps explicit substeps u <- u - dt M^-1 r(u), in place on u (dev).
+ * diag_dev (dev double [n_steps+1][5], nullable): per state energy
+ * 1/2 u.Mu, ||div u||_L2, upwind dissipation, PCG iterations of the solve
+ * that produced it, final preconditioned relative residual.  Syncs. */
+hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_steps,
+                          hopu_precision prec, double* diag_dev);
+
+/* out = J_r(u)^T mu (dev [n_dof] each).  Asynchronous. */
+hopu_status hopu_convection_vjp(hopu_ctx ctx, const double* u, const double* mu,
+                                double* out, hopu_precision prec);
+
+/* Reverse pass of n_steps substeps from u0: lam_0 = (d u_N / d u_0)^T lam_N.
+ * Checkpoints every ckpt_every states and recomputes each segment.
+ * ws dev workspace of ws_bytes >= hopu_substeps_vjp_workspace() bytes.
+ * Syncs. */
+int64_t hopu_substeps_vjp_workspace(hopu_ctx ctx, int n_steps, int ckpt_every);
+hopu_status hopu_substeps_vjp(hopu_ctx ctx, const double* u0, double dt, int n_steps,
+                              int ckpt_every, const double* lam_N, double* lam_0,
+                              hopu_precision prec, void* ws, int64_t ws_bytes);
+
+/* Energy 1/2 u.Mu, ||div u_h||_L2 and the upwind dissipation
+ * sum_E int 1/2 |u.n| |(I-Pi^l)[[u]]|^2 (host scalars, nullable).  Syncs. */
+hopu_status hopu_diagnostics(hopu_ctx ctx, const double* u, double* energy,
+                             double* div_l2, double* dissipation);
+
+/* Interpolation of a field sampled by the caller.  hopu_interp_points writes
+ * the physical sample points for a rule of n1d points per direction:
+ * pts_facet dev [n_facets][n1d^(d-1)][d], pts_vol dev [n_elems][n1d^d][d].
+ * hopu_interpolate turns field values at those points (same shapes) into
+ * coefficients u (dev [n_dof]) with the DoF functionals. */
+hopu_status hopu_interp_points(hopu_ctx ctx, int n1d, double* pts_facet, double* pts_vol);
+hopu_status hopu_interpolate(hopu_ctx ctx, int n1d, const double* vals_facet,
+                             const double* vals_vol, double* u);
+
+/* Evaluate u at reference points: ref_pts host [n_pts][d],
+ * vals dev [n_elems][n_pts][d].  Asynchronous. */
+hopu_status hopu_eval(hopu_ctx ctx, const double* u, int n_pts,
+                      const double* ref_pts, double* vals);
+
+/* Message of the last failed call on ctx (or of the last failed
+ * hopu_create when ctx is NULL); valid until the next call. */
+const char* hopu_last_error(hopu_ctx ctx);
+
+/* Frees everything the context owns.  NULL-safe. */
+void hopu_destroy(hopu_ctx ctx);
+
+/* ---- host-only inspection (no HIP calls; used by CPU tests) ------------
+ * hopu_host_tables: reference tables for (dim, k): which = 0 volume points
+ * [nqv][d], 1 volume weights, 2 V [nqv][nP] (internal modal basis), 3 facet
+ * points [nqf][d-1], 4 facet weights, 5 psi [nqf][nf], 6 D [n][n],
+ * 7 Dinv [n][n].  Writes at most cap doubles; returns the count or < 0.
+ * hopu_host_mesh: topology/geometry of a mesh: which = 0 fid int32
+ * [E][d+1], 1 nbr int32, 2 nbr_face (as int32), 3 geometry double
+ * [E][32], 4 facet_elem int32 [F][2], 5 batches int32 [nb][16]. */
+int64_t hopu_host_tables(int dim, int k, int which, double* out, int64_t cap);
+int64_t hopu_host_mesh(int dim, int64_t n_elems, const int64_t* elem_vid,
+                       const double* elem_xyz, int which, void* out, int64_t cap);
+int64_t hopu_host_sizes(int dim, int k, int which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

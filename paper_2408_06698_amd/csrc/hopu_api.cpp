@@ -1,0 +1,642 @@
+// C ABI of the HOPU convection library: context, argument checks, dispatch
+// by (dim, k), the PCG mass solve and the substep driver.
+#include "../../include/hopu.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "aux.hpp"
+#include "host_tables.hpp"
+#include "kernels.hpp"
+#include "launch.hpp"
+#include "vec.hpp"
+
+using namespace hopu;
+
+struct hopu_ctx_s {
+  int dim = 0, k = 0;
+  Sizes sz;
+  FragDims fd;
+  hipStream_t stream = nullptr;
+  int64_t n_dof = 0;
+  MeshData mesh;
+  Batches bat;
+  DevMesh dm;
+  DevTables<double> tb64;
+  DevTables<float> tb32;
+  const double *mass_in = nullptr, *mass_out = nullptr, *prec_in = nullptr, *prec_out = nullptr;
+  const double* vol_dV64 = nullptr;
+  double* xyz = nullptr;
+  // workspaces
+  double* m64 = nullptr;
+  float* m32 = nullptr;
+  double* slot = nullptr;
+  double* part = nullptr;   // partial sums (max(NPART, nb, waves))
+  int64_t npart = 0;
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *rc = nullptr;
+  double* sc = nullptr;
+  int* flag = nullptr;      // [0] converged, [1] iterations
+  int* hflag = nullptr;     // pinned host copy
+  std::vector<void*> allocs;
+  int lglob = -1;
+  const int8_t* lfac = nullptr;
+  double rtol = 1e-13;
+  int max_it = 500, check_every = 4;
+  std::string err;
+};
+
+static std::string g_create_err;
+
+#define HCHECK(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);         \
+      return HOPU_EHIP;                                                     \
+    }                                                                       \
+  } while (0)
+
+template <typename T>
+static hopu_status dev_alloc(hopu_ctx ctx, T** p, size_t count) {
+  if (count == 0) count = 1;
+  const char* fail = std::getenv("HOPU_TEST_FAIL_ALLOC");
+  if (fail && std::atoi(fail) == 1) {
+    ctx->err = "device allocation refused (HOPU_TEST_FAIL_ALLOC)";
+    return HOPU_ENOMEM;
+  }
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, count * sizeof(T));
+  if (e != hipSuccess) {
+    ctx->err = std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes: " + hipGetErrorString(e);
+    return HOPU_ENOMEM;
+  }
+  ctx->allocs.push_back(v);
+  *p = (T*)v;
+  return HOPU_OK;
+}
+
+template <typename T>
+static hopu_status upload(hopu_ctx ctx, const T** dst, const std::vector<T>& src) {
+  T* d = nullptr;
+  hopu_status st = dev_alloc(ctx, &d, src.size());
+  if (st) return st;
+  if (!src.empty()) HCHECK(hipMemcpyAsync(d, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+  *dst = d;
+  return HOPU_OK;
+}
+
+static std::vector<float> to_f32(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+#define DISPATCH(DIM, K, ...)                              \
+  switch ((DIM) * 10 + (K)) {                               \
+    case 21: { constexpr int D = 2, KK = 1; __VA_ARGS__; } break;  \
+    case 22: { constexpr int D = 2, KK = 2; __VA_ARGS__; } break;  \
+    case 23: { constexpr int D = 2, KK = 3; __VA_ARGS__; } break;  \
+    case 24: { constexpr int D = 2, KK = 4; __VA_ARGS__; } break;  \
+    case 31: { constexpr int D = 3, KK = 1; __VA_ARGS__; } break;  \
+    case 32: { constexpr int D = 3, KK = 2; __VA_ARGS__; } break;  \
+    case 33: { constexpr int D = 3, KK = 3; __VA_ARGS__; } break;  \
+    case 34: { constexpr int D = 3, KK = 4; __VA_ARGS__; } break;  \
+    case 35: { constexpr int D = 3, KK = 5; __VA_ARGS__; } break;  \
+    default: break;                                         \
+  }
+
+static bool supported(int dim, int k) { return (dim == 2 && k >= 1 && k <= 4) || (dim == 3 && k >= 1 && k <= 5); }
+
+static hopu_status fail(hopu_ctx ctx, hopu_status st, const std::string& msg) {
+  ctx->err = msg;
+  return st;
+}
+
+static void refresh_dm(hopu_ctx ctx) {
+  ctx->dm.lfac = ctx->lfac;
+  ctx->dm.lglob = ctx->lglob;
+}
+
+extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elems, const int64_t* elem_vid,
+                                   const double* elem_xyz, void* hip_stream) {
+  if (!out) { g_create_err = "out is NULL"; return HOPU_EINVAL; }
+  *out = nullptr;
+  if (dim != 2 && dim != 3) { g_create_err = "dim must be 2 or 3"; return HOPU_EINVAL; }
+  if (k < 1 || k > 6) { g_create_err = "k must be in 1..6"; return HOPU_EINVAL; }
+  if (!supported(dim, k)) { g_create_err = "order not built into this library (3D k<=5, 2D k<=4)"; return HOPU_EUNSUPPORTED; }
+  if (n_elems <= 0 || !elem_vid || !elem_xyz) { g_create_err = "empty mesh or NULL mesh arrays"; return HOPU_EINVAL; }
+  if (n_elems > (int64_t)INT32_MAX / 2) { g_create_err = "too many elements"; return HOPU_EINVAL; }
+  hopu_ctx ctx = new hopu_ctx_s();
+  ctx->dim = dim;
+  ctx->k = k;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->sz = make_sizes(dim, k);
+  ctx->fd = frag_dims(ctx->sz);
+  ctx->lglob = k - 1;
+  std::string err;
+  if (!build_mesh(dim, n_elems, elem_vid, elem_xyz, ctx->mesh, err)) {
+    g_create_err = err;
+    delete ctx;
+    return HOPU_EMESH;
+  }
+  // |det J|^{(d-1)/d} for the interior DoF scaling
+  for (int64_t e = 0; e < n_elems; ++e) {
+    double* g = &ctx->mesh.geo[e * GEO_STRIDE];
+    long double ad = fabsl((long double)g[GEO_DET]);
+    g[GEO_SI] = (double)(dim == 2 ? sqrtl(ad) : powl(cbrtl(ad), 2.0L));
+  }
+  make_batches(ctx->mesh, ctx->bat);
+  RefTables rt;
+  if (!make_ref_tables(dim, k, rt, err)) {
+    g_create_err = err;
+    delete ctx;
+    return HOPU_EINVAL;
+  }
+  FragTables f64, f32;
+  make_frag_tables(rt, ROWMAP_F64, f64);
+  make_frag_tables(rt, ROWMAP_F32, f32);
+  const Sizes& s = ctx->sz;
+  ctx->n_dof = ctx->mesh.F * s.nf + n_elems * s.nint;
+  hopu_status st = HOPU_OK;
+#define TRY(x)                         \
+  do {                                 \
+    st = (x);                          \
+    if (st) goto fail_create;          \
+  } while (0)
+  {
+    const double* dgeo;
+    const int32_t *dfid, *dnbr, *dfe, *dbe, *dbs;
+    const int8_t* dfl;
+    TRY(upload(ctx, &dgeo, ctx->mesh.geo));
+    TRY(upload(ctx, &dfid, ctx->mesh.fid));
+    TRY(upload(ctx, &dnbr, ctx->mesh.nbr));
+    TRY(upload(ctx, &dfe, ctx->mesh.facet_elem));
+    TRY(upload(ctx, &dfl, ctx->mesh.facet_local));
+    TRY(upload(ctx, &dbe, ctx->bat.elem));
+    TRY(upload(ctx, &dbs, ctx->bat.sig));
+    const double* dxyz;
+    TRY(upload(ctx, &dxyz, ctx->mesh.xyz));
+    ctx->xyz = (double*)dxyz;
+    ctx->dm = DevMesh{dgeo, dfid, dnbr, dfe, dfl, dbe, dbs, nullptr, n_elems, ctx->mesh.F, ctx->bat.nb, ctx->lglob};
+    // tables
+    const double *wv, *wf;
+    const int* pdeg;
+    TRY(upload(ctx, &wv, rt.wv));
+    TRY(upload(ctx, &wf, rt.wf));
+    TRY(upload(ctx, &pdeg, rt.psi_deg));
+    auto up64 = [&](const double** d, const std::vector<double>& v) { return upload(ctx, d, v); };
+    auto up32 = [&](const float** d, const std::vector<double>& v) { return upload(ctx, d, to_f32(v)); };
+    DevTables<double>& a = ctx->tb64;
+    DevTables<float>& b = ctx->tb32;
+    TRY(up64(&a.modal, f64.modal)); TRY(up32(&b.modal, f32.modal));
+    TRY(up64(&a.vol_V, f64.vol_V)); TRY(up32(&b.vol_V, f32.vol_V));
+    TRY(up64(&a.vol_dVT, f64.vol_dVT)); TRY(up32(&b.vol_dVT, f32.vol_dVT));
+    TRY(up64(&a.vol_dV, f64.vol_dV)); TRY(up32(&b.vol_dV, f32.vol_dV));
+    TRY(up64(&a.vol_VT, f64.vol_VT)); TRY(up32(&b.vol_VT, f32.vol_VT));
+    TRY(up64(&a.fac_Tr, f64.fac_Tr)); TRY(up32(&b.fac_Tr, f32.fac_Tr));
+    TRY(up64(&a.fac_TrT, f64.fac_TrT)); TRY(up32(&b.fac_TrT, f32.fac_TrT));
+    TRY(up64(&a.fac_K, f64.fac_K)); TRY(up32(&b.fac_K, f32.fac_K));
+    TRY(up64(&a.fac_Psi, f64.fac_Psi)); TRY(up32(&b.fac_Psi, f32.fac_Psi));
+    TRY(up64(&a.fac_PsiT, f64.fac_PsiT)); TRY(up32(&b.fac_PsiT, f32.fac_PsiT));
+    TRY(up64(&a.fac_KT, f64.fac_KT)); TRY(up32(&b.fac_KT, f32.fac_KT));
+    TRY(up64(&a.dual, f64.dual)); TRY(up32(&b.dual, f32.dual));
+    a.wv = b.wv = wv;
+    a.wf = b.wf = wf;
+    a.psi_deg = b.psi_deg = pdeg;
+    TRY(up64(&ctx->mass_in, f64.mass_in));
+    TRY(up64(&ctx->mass_out, f64.mass_out));
+    TRY(up64(&ctx->prec_in, f64.prec_in));
+    TRY(up64(&ctx->prec_out, f64.prec_out));
+    ctx->vol_dV64 = a.vol_dV;
+    // workspaces
+    const int64_t E = n_elems, n = ctx->n_dof;
+    TRY(dev_alloc(ctx, &ctx->m64, (size_t)E * s.nm));
+    TRY(dev_alloc(ctx, &ctx->m32, (size_t)E * s.nm));
+    TRY(dev_alloc(ctx, &ctx->slot, (size_t)E * s.nfl));
+    ctx->npart = std::max<int64_t>(std::max<int64_t>(NPART, ctx->bat.nb), (E + 15) / 16);
+    TRY(dev_alloc(ctx, &ctx->part, (size_t)ctx->npart));
+    TRY(dev_alloc(ctx, &ctx->r, (size_t)n));
+    TRY(dev_alloc(ctx, &ctx->z, (size_t)n));
+    TRY(dev_alloc(ctx, &ctx->p, (size_t)n));
+    TRY(dev_alloc(ctx, &ctx->q, (size_t)n));
+    TRY(dev_alloc(ctx, &ctx->w, (size_t)n));
+    TRY(dev_alloc(ctx, &ctx->rc, (size_t)n));
+    TRY(dev_alloc(ctx, &ctx->sc, SC_N));
+    TRY(dev_alloc(ctx, &ctx->flag, 4));
+    void* hp = nullptr;
+    if (hipHostMalloc(&hp, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) { st = HOPU_ENOMEM; ctx->err = "hipHostMalloc failed"; goto fail_create; }
+    ctx->hflag = (int*)hp;
+    if (hipMemsetAsync(ctx->w, 0, n * sizeof(double), ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->slot, 0, (size_t)E * s.nfl * sizeof(double), ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      st = HOPU_EHIP;
+      ctx->err = "initial device copies failed";
+      goto fail_create;
+    }
+  }
+  *out = ctx;
+  return HOPU_OK;
+fail_create:
+  g_create_err = ctx->err;
+  hopu_destroy(ctx);
+  return st;
+#undef TRY
+}
+
+extern "C" void hopu_destroy(hopu_ctx ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  if (ctx->hflag) (void)hipHostFree(ctx->hflag);
+  delete ctx;
+}
+
+extern "C" const char* hopu_last_error(hopu_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+extern "C" hopu_status hopu_sizes(hopu_ctx ctx, int64_t* n_dof, int64_t* n_facets, int64_t* n_wall_facets, int* n_loc,
+                                  int* n_facet_dof, int* n_interior_dof) {
+  if (!ctx) return HOPU_EINVAL;
+  if (n_dof) *n_dof = ctx->n_dof;
+  if (n_facets) *n_facets = ctx->mesh.F;
+  if (n_wall_facets) *n_wall_facets = ctx->mesh.W;
+  if (n_loc) *n_loc = ctx->sz.n;
+  if (n_facet_dof) *n_facet_dof = ctx->sz.nf;
+  if (n_interior_dof) *n_interior_dof = ctx->sz.nint;
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_set_upwind(hopu_ctx ctx, int l_global, const int8_t* l_per_facet_dev) {
+  if (!ctx) return HOPU_EINVAL;
+  if (l_global < -1 || l_global > ctx->k) return fail(ctx, HOPU_EINVAL, "l must be in -1..k");
+  ctx->lglob = l_global;
+  ctx->lfac = l_per_facet_dev;
+  refresh_dm(ctx);
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_set_solver(hopu_ctx ctx, double rtol, int max_it, int check_every) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!(rtol > 0) || max_it < 1 || check_every < 1) return fail(ctx, HOPU_EINVAL, "rtol > 0, max_it >= 1, check_every >= 1");
+  ctx->rtol = rtol;
+  ctx->max_it = max_it;
+  ctx->check_every = check_every;
+  return HOPU_OK;
+}
+
+// ------------------------------------------------------------------ internals
+static hopu_status do_modal(hopu_ctx ctx, const double* u, hopu_precision prec) {
+  DISPATCH(ctx->dim, ctx->k, {
+    if (prec == HOPU_FP64) launch_modal<double, D, KK>(ctx->stream, u, ctx->m64, ctx->dm, ctx->tb64.modal);
+    else launch_modal<float, D, KK>(ctx->stream, u, ctx->m32, ctx->dm, ctx->tb32.modal);
+  });
+  return HOPU_OK;
+}
+
+static hopu_status do_apply(hopu_ctx ctx, const double* u, double* r, int terms, hopu_precision prec,
+                            double* diss_part) {
+  hopu_status st = do_modal(ctx, u, prec);
+  if (st) return st;
+  DISPATCH(ctx->dim, ctx->k, {
+    if (prec == HOPU_FP64) launch_elem<double, D, KK>(ctx->stream, ctx->m64, r, ctx->slot, ctx->dm, ctx->tb64, terms, diss_part);
+    else launch_elem<float, D, KK>(ctx->stream, ctx->m32, r, ctx->slot, ctx->dm, ctx->tb32, terms, diss_part);
+  });
+  return HOPU_OK;
+}
+
+static void do_mass(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag) {
+  DISPATCH(ctx->dim, ctx->k, {
+    launch_mass<D, KK>(ctx->stream, mode, x, y, ctx->slot, ctx->dm, mode == 0 ? ctx->mass_in : ctx->prec_in,
+                       mode == 0 ? ctx->mass_out : ctx->prec_out, flag);
+  });
+}
+
+static hopu_status check_prec(hopu_ctx ctx, hopu_precision prec) {
+  if (prec != HOPU_FP64 && prec != HOPU_FP32_MFMA) return fail(ctx, HOPU_EINVAL, "unknown precision");
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_convection_apply(hopu_ctx ctx, const double* u, double* r, int terms, hopu_precision prec) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!u || !r) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  if (terms < 0 || terms > 7) return fail(ctx, HOPU_EINVAL, "terms must be a HOPU_TERM_* mask");
+  if (check_prec(ctx, prec)) return HOPU_EINVAL;
+  refresh_dm(ctx);
+  hopu_status st = do_apply(ctx, u, r, terms, prec, nullptr);
+  if (st) return st;
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_mass_apply(hopu_ctx ctx, const double* u, double* y) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!u || !y) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  do_mass(ctx, 0, u, y, nullptr);
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
+}
+
+// PCG on M with R blockdiag(M_T)^-1 R^t; x holds the initial guess.
+static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, int max_it, int* iters) {
+  const int64_t n = ctx->n_dof;
+  hipStream_t s = ctx->stream;
+  int* fl = ctx->flag;
+  HCHECK(hipMemsetAsync(fl, 0, 4 * sizeof(int), s));
+  // tolerance from b.Pb
+  do_mass(ctx, 1, b, ctx->z, nullptr);
+  vec_dot(s, b, ctx->z, n, ctx->part, nullptr);
+  vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_SET_TOL, rtol, nullptr);
+  // r = b - M x; z = P r; p = z
+  do_mass(ctx, 0, x, ctx->q, nullptr);
+  vec_sub(s, ctx->r, b, ctx->q, n);
+  do_mass(ctx, 1, ctx->r, ctx->z, nullptr);
+  vec_dot(s, ctx->r, ctx->z, n, ctx->part, nullptr);
+  vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_SET_RZ, 0.0, nullptr);
+  HCHECK(hipMemcpyAsync(ctx->p, ctx->z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  int it = 0;
+  bool conv = false;
+  while (it < max_it) {
+    const int chunk = std::min(ctx->check_every, max_it - it);
+    for (int c = 0; c < chunk; ++c) {
+      do_mass(ctx, 0, ctx->p, ctx->q, fl);
+      vec_dot(s, ctx->p, ctx->q, n, ctx->part, fl);
+      vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
+      vec_axpy2(s, x, ctx->r, ctx->p, ctx->q, n, ctx->sc, fl);
+      do_mass(ctx, 1, ctx->r, ctx->z, fl);
+      vec_dot(s, ctx->r, ctx->z, n, ctx->part, fl);
+      vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_BETA, 0.0, nullptr);
+      vec_xpay(s, ctx->p, ctx->z, n, ctx->sc, fl);
+    }
+    it += chunk;
+    HCHECK(hipMemcpyAsync(ctx->hflag, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    if (ctx->hflag[0]) { conv = true; break; }
+  }
+  HCHECK(hipGetLastError());
+  if (iters) *iters = ctx->hflag[1];
+  if (!conv) {
+    ctx->err = "PCG did not reach rtol within max_it iterations";
+    return HOPU_ENOCONV;
+  }
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_mass_solve(hopu_ctx ctx, const double* r, double* w, double rtol, int max_it, int* iters) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!r || !w) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  if (max_it < 1) return fail(ctx, HOPU_EINVAL, "max_it must be >= 1");
+  return pcg(ctx, r, w, rtol > 0 ? rtol : ctx->rtol, max_it, iters);
+}
+
+static hopu_status diag_into(hopu_ctx ctx, const double* u, double* dst /*dev [3]*/, bool have_modal_and_diss,
+                             int64_t ndiss) {
+  // energy and divergence from the FP64 modal coefficients of u
+  hipStream_t s = ctx->stream;
+  if (!have_modal_and_diss) {
+    do_modal(ctx, u, HOPU_FP64);
+  }
+  int64_t nw = 0;
+  DISPATCH(ctx->dim, ctx->k, {
+    launch_energy<D, KK>(s, ctx->m64, ctx->dm, ctx->part);
+    vec_scalar(s, ctx->part, AUX_NPART, ctx->sc, ctx->flag, OP_STORE, 0.0, dst + 0);
+    nw = launch_div<D, KK>(s, ctx->m64, ctx->dm, ctx->vol_dV64, ctx->tb64.wv, ctx->part);
+    vec_scalar(s, ctx->part, (int)nw, ctx->sc, ctx->flag, OP_STORE, 0.0, dst + 1);
+  });
+  (void)ndiss;
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_diagnostics(hopu_ctx ctx, const double* u, double* energy, double* div_l2,
+                                        double* dissipation) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!u) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  refresh_dm(ctx);
+  hipStream_t s = ctx->stream;
+  double* dd = ctx->sc + 6;  // two spare scalar slots are not enough: use z as scratch
+  dd = ctx->z;
+  // dissipation: run the element kernel with facet terms and collect partials
+  hopu_status st = do_apply(ctx, u, ctx->rc, HOPU_TERM_UPWIND, HOPU_FP64, ctx->part);
+  if (st) return st;
+  vec_scalar(s, ctx->part, (int)ctx->bat.nb, ctx->sc, ctx->flag, OP_STORE, 0.0, dd + 2);
+  diag_into(ctx, u, dd, true, 0);
+  double h[3];
+  HCHECK(hipMemcpyAsync(h, dd, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  if (energy) *energy = h[0];
+  if (div_l2) *div_l2 = std::sqrt(std::max(h[1], 0.0));
+  if (dissipation) *dissipation = h[2];
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_steps, hopu_precision prec,
+                                     double* diag_dev) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!u) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  if (n_steps < 0) return fail(ctx, HOPU_EINVAL, "n_steps must be >= 0");
+  if (!(std::isfinite(dt))) return fail(ctx, HOPU_EINVAL, "dt must be finite");
+  if (check_prec(ctx, prec)) return HOPU_EINVAL;
+  refresh_dm(ctx);
+  hipStream_t s = ctx->stream;
+  HCHECK(hipMemsetAsync(ctx->w, 0, ctx->n_dof * sizeof(double), s));
+  for (int st_i = 0; st_i <= n_steps; ++st_i) {
+    const bool last = st_i == n_steps;
+    if (diag_dev) {
+      double* row = diag_dev + (int64_t)st_i * 5;
+      // dissipation of the current state (FP64 facet pass), energy, divergence
+      hopu_status st = do_apply(ctx, u, ctx->rc, HOPU_TERM_UPWIND, HOPU_FP64, ctx->part);
+      if (st) return st;
+      vec_scalar(s, ctx->part, (int)ctx->bat.nb, ctx->sc, ctx->flag, OP_STORE, 0.0, row + 2);
+      double* tmp = ctx->z;
+      diag_into(ctx, u, tmp, true, 0);
+      HCHECK(hipMemcpyAsync(row, tmp, 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (st_i == 0) HCHECK(hipMemsetAsync(row + 3, 0, 2 * sizeof(double), s));
+    }
+    if (last) break;
+    hopu_status st = do_apply(ctx, u, ctx->rc, HOPU_TERM_ALL, prec, nullptr);
+    if (st) return st;
+    int its = 0;
+    st = pcg(ctx, ctx->rc, ctx->w, ctx->rtol, ctx->max_it, &its);
+    if (st) return st;
+    if (diag_dev) vec_copy_diag(s, diag_dev + (int64_t)(st_i + 1) * 5 + 3, ctx->sc, ctx->flag);
+    vec_axpy(s, u, ctx->w, -dt, ctx->n_dof);
+  }
+  HCHECK(hipGetLastError());
+  HCHECK(hipStreamSynchronize(s));
+  return HOPU_OK;
+}
+
+// ------------------------------------------------------------------ interpolation / eval
+extern "C" hopu_status hopu_interp_points(hopu_ctx ctx, int n1d, double* pts_facet, double* pts_vol) {
+  if (!ctx) return HOPU_EINVAL;
+  if (n1d < 1 || n1d > 64) return fail(ctx, HOPU_EINVAL, "n1d must be in 1..64");
+  std::vector<ld> sp, sw, vp, vw;
+  simplex_rule(ctx->dim - 1, n1d, sp, sw);
+  simplex_rule(ctx->dim, n1d, vp, vw);
+  std::vector<double> s(sp.begin(), sp.end()), v(vp.begin(), vp.end());
+  double *ds = nullptr, *dv = nullptr;
+  HCHECK(hipMalloc(&ds, s.size() * 8));
+  HCHECK(hipMalloc(&dv, v.size() * 8));
+  HCHECK(hipMemcpyAsync(ds, s.data(), s.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  HCHECK(hipMemcpyAsync(dv, v.data(), v.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  launch_interp_points(ctx->stream, ctx->dim, (int)sw.size(), ds, (int)vw.size(), dv, ctx->xyz, ctx->dm, pts_facet,
+                       pts_vol);
+  HCHECK(hipStreamSynchronize(ctx->stream));
+  (void)hipFree(ds);
+  (void)hipFree(dv);
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_interpolate(hopu_ctx ctx, int n1d, const double* vals_facet, const double* vals_vol,
+                                        double* u) {
+  if (!ctx) return HOPU_EINVAL;
+  if (n1d < 1 || n1d > 64 || !u || (!vals_facet && ctx->mesh.F > 0) || (!vals_vol && ctx->sz.nint > 0))
+    return fail(ctx, HOPU_EINVAL, "bad interpolation arguments");
+  const int dim = ctx->dim, k = ctx->k;
+  const Sizes& sz = ctx->sz;
+  std::vector<ld> sp, sw, vp, vw;
+  simplex_rule(dim - 1, n1d, sp, sw);
+  simplex_rule(dim, n1d, vp, vw);
+  std::vector<double> ws(sw.begin(), sw.end()), wv(vw.begin(), vw.end());
+  std::vector<double> psi(sw.size() * sz.nf), qm(vw.size() * std::max(1, sz.nint) * dim, 0.0);
+  std::vector<ld> tmp(std::max(sz.nf, std::max(1, sz.nint) * dim));
+  for (size_t q = 0; q < sw.size(); ++q) {
+    facet_psi(dim, k, &sp[q * (dim - 1)], tmp.data());
+    for (int j = 0; j < sz.nf; ++j) psi[q * sz.nf + j] = (double)tmp[j];
+  }
+  if (sz.nint > 0)
+    for (size_t q = 0; q < vw.size(); ++q) {
+      interior_tests(dim, k, &vp[q * dim], tmp.data());
+      for (int m = 0; m < sz.nint * dim; ++m) qm[q * sz.nint * dim + m] = (double)tmp[m];
+    }
+  double *dws, *dwv, *dpsi, *dqm;
+  HCHECK(hipMalloc(&dws, ws.size() * 8));
+  HCHECK(hipMalloc(&dwv, wv.size() * 8));
+  HCHECK(hipMalloc(&dpsi, psi.size() * 8));
+  HCHECK(hipMalloc(&dqm, qm.size() * 8));
+  HCHECK(hipMemcpyAsync(dws, ws.data(), ws.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  HCHECK(hipMemcpyAsync(dwv, wv.data(), wv.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  HCHECK(hipMemcpyAsync(dpsi, psi.data(), psi.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  HCHECK(hipMemcpyAsync(dqm, qm.data(), qm.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  launch_interpolate(ctx->stream, dim, (int)ws.size(), sz.nf, vals_facet, dws, dpsi, (int)wv.size(), sz.nint,
+                     vals_vol, dwv, dqm, ctx->dm, u);
+  HCHECK(hipStreamSynchronize(ctx->stream));
+  (void)hipFree(dws); (void)hipFree(dwv); (void)hipFree(dpsi); (void)hipFree(dqm);
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_eval(hopu_ctx ctx, const double* u, int n_pts, const double* ref_pts, double* vals) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!u || !vals || !ref_pts || n_pts < 1) return fail(ctx, HOPU_EINVAL, "bad eval arguments");
+  const int dim = ctx->dim, k = ctx->k;
+  const Sizes& sz = ctx->sz;
+  DualBasis db;
+  std::string err;
+  if (!make_dual_basis(dim, k, db, err)) return fail(ctx, HOPU_EINVAL, err);
+  std::vector<double> phi((size_t)n_pts * sz.n * dim);
+  std::vector<ld> val(sz.nP), grad(sz.nP * dim);
+  for (int p = 0; p < n_pts; ++p) {
+    ld x[3];
+    for (int a = 0; a < dim; ++a) x[a] = ref_pts[p * dim + a];
+    dubiner(dim, k, x, val.data(), grad.data());
+    for (int j = 0; j < sz.n; ++j)
+      for (int a = 0; a < dim; ++a) {
+        ld s = 0;
+        for (int al = 0; al < sz.nP; ++al) s += db.Dinv[(a * sz.nP + al) * sz.n + j] * val[al];
+        phi[((size_t)p * sz.n + j) * dim + a] = (double)s;
+      }
+  }
+  double* dphi;
+  HCHECK(hipMalloc(&dphi, phi.size() * 8));
+  HCHECK(hipMemcpyAsync(dphi, phi.data(), phi.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  launch_eval(ctx->stream, dim, sz.n, sz.nf, sz.nint, n_pts, u, dphi, ctx->dm, vals);
+  HCHECK(hipStreamSynchronize(ctx->stream));
+  (void)hipFree(dphi);
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
+}
+
+// ------------------------------------------------------------------ host-only inspection
+extern "C" int64_t hopu_host_sizes(int dim, int k, int which) {
+  if ((dim != 2 && dim != 3) || k < 1 || k > 6) return -1;
+  Sizes s = make_sizes(dim, k);
+  switch (which) {
+    case 0: return s.n;
+    case 1: return s.nf;
+    case 2: return s.nint;
+    case 3: return s.nP;
+    case 4: return s.nqv;
+    case 5: return s.nqf;
+    default: return -1;
+  }
+}
+
+extern "C" int64_t hopu_host_tables(int dim, int k, int which, double* out, int64_t cap) {
+  if ((dim != 2 && dim != 3) || k < 1 || k > 6 || (!out && cap > 0)) return -1;
+  RefTables t;
+  std::string err;
+  if (!make_ref_tables(dim, k, t, err)) return -2;
+  const std::vector<double>* v = nullptr;
+  switch (which) {
+    case 0: v = &t.xv; break;
+    case 1: v = &t.wv; break;
+    case 2: v = &t.V; break;
+    case 3: v = &t.sf; break;
+    case 4: v = &t.wf; break;
+    case 5: v = &t.Psi; break;
+    case 6: v = &t.D; break;
+    case 7: v = &t.Dinv; break;
+    default: return -1;
+  }
+  int64_t nwr = std::min<int64_t>(cap, (int64_t)v->size());
+  if (out && nwr > 0) std::memcpy(out, v->data(), nwr * sizeof(double));
+  return (int64_t)v->size();
+}
+
+extern "C" int64_t hopu_host_mesh(int dim, int64_t n_elems, const int64_t* elem_vid, const double* elem_xyz, int which,
+                                  void* out, int64_t cap) {
+  if ((dim != 2 && dim != 3) || n_elems <= 0 || !elem_vid || !elem_xyz) return -1;
+  MeshData m;
+  std::string err;
+  if (!build_mesh(dim, n_elems, elem_vid, elem_xyz, m, err)) return -2;
+  auto put_i32 = [&](const std::vector<int32_t>& v) {
+    if (out) std::memcpy(out, v.data(), std::min<int64_t>(cap, v.size()) * 4);
+    return (int64_t)v.size();
+  };
+  switch (which) {
+    case 0: return put_i32(m.fid);
+    case 1: return put_i32(m.nbr);
+    case 2: return put_i32(std::vector<int32_t>(m.nbr_face.begin(), m.nbr_face.end()));
+    case 3:
+      if (out) std::memcpy(out, m.geo.data(), std::min<int64_t>(cap, m.geo.size()) * 8);
+      return (int64_t)m.geo.size();
+    case 4: return put_i32(m.facet_elem);
+    case 5: {
+      Batches b;
+      make_batches(m, b);
+      return put_i32(b.elem);
+    }
+    default: return -1;
+  }
+}
+
+// ------------------------------------------------------------------ adjoint (stubs until the VJP kernels land)
+extern "C" hopu_status hopu_convection_vjp(hopu_ctx ctx, const double* u, const double* mu, double* out,
+                                           hopu_precision prec) {
+  if (!ctx) return HOPU_EINVAL;
+  (void)u; (void)mu; (void)out; (void)prec;
+  return fail(ctx, HOPU_EUNSUPPORTED, "vjp not built");
+}
+extern "C" int64_t hopu_substeps_vjp_workspace(hopu_ctx ctx, int n_steps, int ckpt_every) {
+  (void)ctx; (void)n_steps; (void)ckpt_every;
+  return HOPU_EUNSUPPORTED;
+}
+extern "C" hopu_status hopu_substeps_vjp(hopu_ctx ctx, const double* u0, double dt, int n_steps, int ckpt_every,
+                                         const double* lam_N, double* lam_0, hopu_precision prec, void* ws,
+                                         int64_t ws_bytes) {
+  if (!ctx) return HOPU_EINVAL;
+  (void)u0; (void)dt; (void)n_steps; (void)ckpt_every; (void)lam_N; (void)lam_0; (void)prec; (void)ws; (void)ws_bytes;
+  return fail(ctx, HOPU_EUNSUPPORTED, "vjp not built");
+}

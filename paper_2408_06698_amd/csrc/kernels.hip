@@ -1,0 +1,629 @@
+// HIP kernels for gfx950.  See kernels.hpp for the batch/tile conventions.
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace hopu {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MF;
+template <> struct MF<double> {
+  typedef d4 V;
+  // v_mfma_f64_16x16x4f64: row 4i+g of the 16x16 output sits in register i
+  // of lane group g.
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int i, int g) { return 4 * i + g; }
+};
+template <> struct MF<float> {
+  typedef f4 V;
+  // v_mfma_f32_16x16x4f32: row 4g+i sits in register i of lane group g.
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int i, int g) { return 4 * g + i; }
+};
+
+template <typename V> __device__ __forceinline__ V vzero() { V v = {0, 0, 0, 0}; return v; }
+
+// Batches are assigned so that consecutive batches land on the same XCD
+// (workgroups are dealt round-robin over the 8 XCDs).
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+  const int64_t per = (nblocks + 7) / 8;
+  int64_t x = bid % 8, s = bid / 8;
+  int64_t full = nblocks % 8 == 0 ? 8 : nblocks % 8;  // XCDs that get `per` blocks
+  if (x < full) return x * per + s;
+  return full * per + (x - full) * (per - 1) + s;
+}
+
+template <int D>
+__device__ __forceinline__ void load_J(const double* g, double J[D][D]) {
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int c = 0; c < D; ++c) J[r][c] = g[r * D + c];
+}
+
+// ------------------------------------------------------------------ modal
+// m_T = Dinv (S_T x_T): dual coefficients -> modal coefficients (rho layout).
+template <typename T, int D, int KK>
+__global__ __launch_bounds__(256) void k_modal(const double* __restrict__ x, T* __restrict__ m,
+                                               DevMesh mesh, const T* __restrict__ frag) {
+  using C = Cfg<D, KK>;
+  using M = MF<T>;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t e = wave * 16 + c;
+  if (wave * 16 >= mesh.E) return;
+  const bool valid = e < mesh.E;
+  const int64_t ee = valid ? e : 0;
+  const double* G = mesh.geo + ee * GEO_STRIDE;
+  const int64_t off = mesh.F * C::NF;
+  T xh[C::NK];
+#pragma unroll
+  for (int kk = 0; kk < C::NK; ++kk) {
+    const int j = 4 * kk + g;
+    double v = 0.0;
+    if (valid && j < C::N) {
+      if (j < C::NFL) {
+        const int f = j / C::NF, jj = j - f * C::NF;
+        const int32_t F = mesh.fid[ee * (D + 1) + f];
+        if (F >= 0) v = x[(int64_t)F * C::NF + jj] * G[GEO_NFN + f];
+      } else {
+        v = x[off + ee * C::NINT + (j - C::NFL)] * G[GEO_SI];
+      }
+    }
+    xh[kk] = (T)v;
+  }
+#pragma unroll
+  for (int mt = 0; mt < C::NMT; ++mt) {
+    typename M::V acc = vzero<typename M::V>();
+#pragma unroll
+    for (int kk = 0; kk < C::NK; ++kk) acc = M::mma(frag[(mt * C::NK + kk) * 64 + lane], xh[kk], acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = 16 * mt + M::row(i, g);
+      if (valid && row < C::NM) m[ee * C::NM + row] = acc[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ element
+// Fused convection residual of a batch of 16 elements:
+//   volume  - int (u x u) : grad phi, in reference form
+//           - sgn(det)/det^2 int (G u^) . (grad^ phi^) u^,  G = J^T J
+//   facets  + int (u.n)<u>.phi + (I - Pi)(1/2|u.n|(I - Pi)[[u]]) . phi
+//           with [[.]] = own - neighbour and n the own outward normal;
+// then r^ = S Dinv^T r_modal.  Facet rows go to per-element slots, interior
+// rows straight to r.
+template <typename T, int D, int KK>
+__global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* __restrict__ r,
+                                              double* __restrict__ rslot, DevMesh mesh,
+                                              DevTables<T> tb, int terms,
+                                              double* __restrict__ diss_part) {
+  using C = Cfg<D, KK>;
+  using M = MF<T>;
+  using V = typename M::V;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int64_t nwave_blocks = (mesh.nb + 3) / 4;
+  const int64_t blk = xcd_remap(blockIdx.x, nwave_blocks);
+  const int64_t b = blk * 4 + (threadIdx.x >> 6);
+  if (b >= mesh.nb) return;
+  const int32_t e = mesh.belem[b * 16 + c];
+  const bool valid = e >= 0;
+  const int64_t ee = valid ? e : mesh.belem[b * 16];
+  const int sig = mesh.bsig[b];
+  const double* Gr = mesh.geo + ee * GEO_STRIDE;
+  double J[D][D];
+  load_J<D>(Gr, J);
+  const double det = Gr[GEO_DET];
+  const double idet = 1.0 / det;
+
+  T mB[D][C::NPK];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int kk = 0; kk < C::NPK; ++kk) mB[a][kk] = m[ee * C::NM + kk * 4 * D + 4 * a + g];
+
+  double acc[D][C::NAT][4];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int at = 0; at < C::NAT; ++at)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[a][at][i] = 0.0;
+
+  // ---------------- volume term
+  if (terms & 1) {
+    double Gm[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int bb = 0; bb < D; ++bb) {
+        double s = 0;
+#pragma unroll
+        for (int r2 = 0; r2 < D; ++r2) s += J[r2][a] * J[r2][bb];
+        Gm[a][bb] = s;
+      }
+    const double sc = -idet * idet * (det > 0 ? 1.0 : -1.0);
+    for (int qt = 0; qt < C::NQVT; ++qt) {
+      V u[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) u[a] = vzero<V>();
+#pragma unroll
+      for (int kk = 0; kk < C::NPK; ++kk) {
+        const T av = tb.vol_V[(qt * C::NPK + kk) * 64 + lane];
+#pragma unroll
+        for (int a = 0; a < D; ++a) u[a] = M::mma(av, mB[a][kk], u[a]);
+      }
+      T F[D][D][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = 16 * qt + M::row(i, g);
+        const double wq = q < C::NQV ? tb.wv[q] : 0.0;
+        double uh[D], gu[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) uh[a] = (double)u[a][i];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double s = 0;
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) s += Gm[a][bb] * uh[bb];
+          gu[a] = s * wq * sc;
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) F[a][bb][i] = (T)(gu[a] * uh[bb]);
+      }
+      V t[D][C::NAT];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int at = 0; at < C::NAT; ++at) t[a][at] = vzero<V>();
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb)
+#pragma unroll
+          for (int at = 0; at < C::NAT; ++at) {
+            const T av = tb.vol_dVT[(((qt * 4 + i) * D + bb) * C::NAT + at) * 64 + lane];
+#pragma unroll
+            for (int a = 0; a < D; ++a) t[a][at] = M::mma(av, F[a][bb][i], t[a][at]);
+          }
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int at = 0; at < C::NAT; ++at)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[a][at][i] += (double)t[a][at][i];
+    }
+  }
+
+  // ---------------- facet terms
+  double diss = 0.0;
+  const bool cen = terms & 2, up = terms & 4;
+  if (cen || up) {
+    for (int f = 0; f <= D; ++f) {
+      const int fp = (sig >> (4 * f)) & 0xF;
+      if (fp == 0xF) continue;  // wall facet for the whole batch: u.n = 0
+      const int32_t en = valid ? mesh.nbr[ee * (D + 1) + f] : (int32_t)ee;
+      const double* Gn = mesh.geo + (int64_t)en * GEO_STRIDE;
+      double Jn[D][D];
+      load_J<D>(Gn, Jn);
+      const double idetn = 1.0 / Gn[GEO_DET];
+      const double nfn = Gr[GEO_NFN + f];
+      double nrm[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) nrm[a] = Gr[GEO_NRM + f * D + a];
+      int lf = mesh.lglob;
+      if (mesh.lfac) lf = valid ? (int)mesh.lfac[mesh.fid[ee * (D + 1) + f]] : -1;
+      T nB[D][C::NPK];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int kk = 0; kk < C::NPK; ++kk) nB[a][kk] = m[(int64_t)en * C::NM + kk * 4 * D + 4 * a + g];
+
+      // moments of the physical jump against psi_j (deg psi_j <= l)
+      T c1[D][C::NFJT][4];
+      if (up) {
+#pragma unroll
+        for (int jt = 0; jt < C::NFJT; ++jt) {
+          V ro[D], rn[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) { ro[a] = vzero<V>(); rn[a] = vzero<V>(); }
+#pragma unroll
+          for (int kk = 0; kk < C::NPK; ++kk) {
+            const T ao = tb.fac_K[((f * C::NFJT + jt) * C::NPK + kk) * 64 + lane];
+            const T an = tb.fac_K[((fp * C::NFJT + jt) * C::NPK + kk) * 64 + lane];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              ro[a] = M::mma(ao, mB[a][kk], ro[a]);
+              rn[a] = M::mma(an, nB[a][kk], rn[a]);
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int j = 16 * jt + M::row(i, g);
+            const bool keep = j < C::NF && tb.psi_deg[j < C::NF ? j : 0] <= lf;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              double s = 0;
+#pragma unroll
+              for (int bb = 0; bb < D; ++bb)
+                s += J[a][bb] * (double)ro[bb][i] * idet - Jn[a][bb] * (double)rn[bb][i] * idetn;
+              c1[a][jt][i] = keep ? (T)s : (T)0;
+            }
+          }
+        }
+      }
+      V c2[D][C::NFJT];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int jt = 0; jt < C::NFJT; ++jt) c2[a][jt] = vzero<V>();
+
+      for (int qt = 0; qt < C::NQFT; ++qt) {
+        V to[D], tn[D], pj[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) { to[a] = vzero<V>(); tn[a] = vzero<V>(); pj[a] = vzero<V>(); }
+#pragma unroll
+        for (int kk = 0; kk < C::NPK; ++kk) {
+          const T ao = tb.fac_Tr[((f * C::NQFT + qt) * C::NPK + kk) * 64 + lane];
+          const T an = tb.fac_Tr[((fp * C::NQFT + qt) * C::NPK + kk) * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            to[a] = M::mma(ao, mB[a][kk], to[a]);
+            tn[a] = M::mma(an, nB[a][kk], tn[a]);
+          }
+        }
+        if (up) {
+#pragma unroll
+          for (int jk = 0; jk < C::NFK; ++jk) {
+            const T ap = tb.fac_Psi[(qt * C::NFK + jk) * 64 + lane];
+#pragma unroll
+            for (int a = 0; a < D; ++a) pj[a] = M::mma(ap, c1[a][jk / 4][jk % 4], pj[a]);
+          }
+        }
+        T h[D][4], aw[D][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int q = 16 * qt + M::row(i, g);
+          const double wq = q < C::NQF ? tb.wf[q] : 0.0;
+          double uo[D], un[D], avg[D], jp[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            double so = 0, sn = 0;
+#pragma unroll
+            for (int bb = 0; bb < D; ++bb) { so += J[a][bb] * (double)to[bb][i]; sn += Jn[a][bb] * (double)tn[bb][i]; }
+            uo[a] = so * idet;
+            un[a] = sn * idetn;
+          }
+          double unn = 0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) { avg[a] = 0.5 * (uo[a] + un[a]); unn += avg[a] * nrm[a]; }
+          const double hu = 0.5 * fabs(unn);
+          double gg[D], jj2 = 0;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            jp[a] = (uo[a] - un[a]) - (double)pj[a][i];
+            const double av_ = up ? hu * jp[a] : 0.0;
+            gg[a] = (cen ? unn * avg[a] : 0.0) + av_;
+            aw[a][i] = (T)av_;
+            jj2 += jp[a] * jp[a];
+          }
+          if (up && valid) diss += 0.5 * wq * nfn * hu * jj2;
+          const double sh = wq * nfn * idet;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            double s = 0;
+#pragma unroll
+            for (int bb = 0; bb < D; ++bb) s += J[bb][a] * gg[bb];
+            h[a][i] = (T)(s * sh);
+          }
+        }
+        V t[D][C::NAT];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int at = 0; at < C::NAT; ++at) t[a][at] = vzero<V>();
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int at = 0; at < C::NAT; ++at) {
+            const T av = tb.fac_TrT[(((f * C::NQFT + qt) * 4 + i) * C::NAT + at) * 64 + lane];
+#pragma unroll
+            for (int a = 0; a < D; ++a) t[a][at] = M::mma(av, h[a][i], t[a][at]);
+          }
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int at = 0; at < C::NAT; ++at)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[a][at][i] += (double)t[a][at][i];
+        if (up) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int jt = 0; jt < C::NFJT; ++jt) {
+              const T ap = tb.fac_PsiT[((qt * 4 + i) * C::NFJT + jt) * 64 + lane];
+#pragma unroll
+              for (int a = 0; a < D; ++a) c2[a][jt] = M::mma(ap, aw[a][i], c2[a][jt]);
+            }
+        }
+      }
+      if (up) {
+        // subtract the test of Pi(a): sum_j K_f[j][alpha] |N_F| (J^T c2_j)/det
+        T cc[D][C::NFJT][4];
+#pragma unroll
+        for (int jt = 0; jt < C::NFJT; ++jt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int j = 16 * jt + M::row(i, g);
+            const bool keep = j < C::NF && tb.psi_deg[j < C::NF ? j : 0] <= lf;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              double s = 0;
+#pragma unroll
+              for (int bb = 0; bb < D; ++bb) s += J[bb][a] * (double)c2[bb][jt][i];
+              cc[a][jt][i] = keep ? (T)(-s * nfn * idet) : (T)0;
+            }
+          }
+        V t[D][C::NAT];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int at = 0; at < C::NAT; ++at) t[a][at] = vzero<V>();
+#pragma unroll
+        for (int jk = 0; jk < C::NFK; ++jk)
+#pragma unroll
+          for (int at = 0; at < C::NAT; ++at) {
+            const T av = tb.fac_KT[((f * C::NAT + at) * C::NFK + jk) * 64 + lane];
+#pragma unroll
+            for (int a = 0; a < D; ++a) t[a][at] = M::mma(av, cc[a][jk / 4][jk % 4], t[a][at]);
+          }
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int at = 0; at < C::NAT; ++at)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[a][at][i] += (double)t[a][at][i];
+      }
+    }
+  }
+
+  // ---------------- dual transform and write-out
+  const int64_t off = mesh.F * C::NF;
+#pragma unroll
+  for (int jt = 0; jt < C::NJT; ++jt) {
+    V o = vzero<V>();
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int at = 0; at < C::NAT; ++at)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          o = M::mma(tb.dual[((((jt * D + a) * C::NAT + at) * 4) + i) * 64 + lane], (T)acc[a][at][i], o);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = 16 * jt + M::row(i, g);
+      if (valid && j < C::N) {
+        if (j < C::NFL) rslot[ee * C::NFL + j] = (double)o[i] * Gr[GEO_NFN + j / C::NF];
+        else r[off + ee * C::NINT + (j - C::NFL)] = (double)o[i] * Gr[GEO_SI];
+      }
+    }
+  }
+  if (diss_part) {
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) diss += __shfl_xor(diss, s, 64);
+    if (lane == 0) diss_part[b] = diss;
+  }
+}
+
+// facet rows: r_F = slot(T) + slot(T'), lower element first
+template <int NF, int NFL>
+__global__ void k_assemble(double* __restrict__ r, const double* __restrict__ slot, DevMesh mesh) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= mesh.F * NF) return;
+  const int64_t F = t / NF;
+  const int jj = (int)(t - F * NF);
+  const int32_t e0 = mesh.facet_elem[2 * F], e1 = mesh.facet_elem[2 * F + 1];
+  const int i0 = mesh.facet_local[2 * F], i1 = mesh.facet_local[2 * F + 1];
+  r[t] = slot[(int64_t)e0 * NFL + i0 * NF + jj] + slot[(int64_t)e1 * NFL + i1 * NF + jj];
+}
+
+// ------------------------------------------------------------------ mass
+// MODE 0: y = M_T x_T  = S Dinv^T (G (x) I) Dinv S x_T / |det J|
+// MODE 1: y = (M_T^-1)(1/2 facet rows)  = 1/2 S^-1 D (G^-1 (x) I) D^T S^-1 (1/2) x_T |det J|
+// Facet rows go to slots (summed by k_assemble), interior rows to out.
+template <int D, int KK, int MODE>
+__global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, double* __restrict__ out,
+                                              double* __restrict__ slot, DevMesh mesh,
+                                              const double* __restrict__ fin,
+                                              const double* __restrict__ fout,
+                                              const int* __restrict__ flag) {
+  using C = Cfg<D, KK>;
+  using M = MF<double>;
+  if (flag && *flag) return;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave * 16 >= mesh.E) return;
+  const int64_t e = wave * 16 + c;
+  const bool valid = e < mesh.E;
+  const int64_t ee = valid ? e : 0;
+  const double* Gr = mesh.geo + ee * GEO_STRIDE;
+  const int64_t off = mesh.F * C::NF;
+  double sfac[D + 1];
+#pragma unroll
+  for (int f = 0; f <= D; ++f) sfac[f] = MODE == 0 ? Gr[GEO_NFN + f] : 0.5 / Gr[GEO_NFN + f];
+  const double sint = MODE == 0 ? Gr[GEO_SI] : 1.0 / Gr[GEO_SI];
+  double xh[C::NK];
+#pragma unroll
+  for (int kk = 0; kk < C::NK; ++kk) {
+    const int j = 4 * kk + g;
+    double v = 0.0;
+    if (valid && j < C::N) {
+      if (j < C::NFL) {
+        const int f = j / C::NF, jj = j - f * C::NF;
+        const int32_t F = mesh.fid[ee * (D + 1) + f];
+        if (F >= 0) v = x[(int64_t)F * C::NF + jj] * sfac[f];
+      } else {
+        v = x[off + ee * C::NINT + (j - C::NFL)] * sint;
+      }
+    }
+    xh[kk] = v;
+  }
+  double y[C::NMT][4];
+#pragma unroll
+  for (int mt = 0; mt < C::NMT; ++mt) {
+    d4 acc = vzero<d4>();
+#pragma unroll
+    for (int kk = 0; kk < C::NK; ++kk) acc = M::mma(fin[(mt * C::NK + kk) * 64 + lane], xh[kk], acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[mt][i] = acc[i];
+  }
+  // component mixing: quads rq = blk*D + a hold components a of one alpha block
+  double J[D][D];
+  load_J<D>(Gr, J);
+  const double det = Gr[GEO_DET];
+  double Gm[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int bb = 0; bb < D; ++bb) {
+      double s = 0;
+#pragma unroll
+      for (int r2 = 0; r2 < D; ++r2) s += J[r2][a] * J[r2][bb];
+      Gm[a][bb] = s;
+    }
+  double Gs[D][D];
+  if (MODE == 0) {
+    const double s = 1.0 / fabs(det);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int bb = 0; bb < D; ++bb) Gs[a][bb] = Gm[a][bb] * s;
+  } else {
+    // G^-1 |det| = adj(G)/det(G) |det| = adj(G)/|det|  (det G = det^2)
+    const double s = 1.0 / fabs(det);
+    if (D == 2) {
+      Gs[0][0] = Gm[1][1] * s; Gs[1][1] = Gm[0][0] * s;
+      Gs[0][1] = -Gm[0][1] * s; Gs[1][0] = -Gm[1][0] * s;
+    } else {
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) {
+          const int a1 = (bb + 1) % 3, a2 = (bb + 2) % 3, b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+          Gs[a][bb] = (Gm[a1][b1] * Gm[a2][b2] - Gm[a1][b2] * Gm[a2][b1]) * s;
+        }
+    }
+  }
+  double z[C::NMQ];
+#pragma unroll
+  for (int q = 0; q < C::NMQ; ++q) z[q] = 0.0;
+#pragma unroll
+  for (int blk = 0; blk < C::NPK; ++blk)
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      double s = 0;
+#pragma unroll
+      for (int bb = 0; bb < D; ++bb) {
+        const int rq = blk * D + bb;
+        s += Gs[a][bb] * y[rq / 4][rq % 4];
+      }
+      z[blk * D + a] = s;
+    }
+#pragma unroll
+  for (int jt = 0; jt < C::NJT; ++jt) {
+    d4 o = vzero<d4>();
+#pragma unroll
+    for (int rq = 0; rq < C::NMQ; ++rq) o = M::mma(fout[(jt * C::NMQ + rq) * 64 + lane], z[rq], o);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = 16 * jt + M::row(i, g);
+      if (valid && j < C::N) {
+        if (j < C::NFL) slot[ee * C::NFL + j] = o[i] * sfac[j / C::NF];
+        else out[off + ee * C::NINT + (j - C::NFL)] = o[i] * sint;
+      }
+    }
+  }
+}
+
+template <int NF, int NFL>
+__global__ void k_assemble_flag(double* __restrict__ r, const double* __restrict__ slot, DevMesh mesh,
+                                const int* __restrict__ flag) {
+  if (flag && *flag) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= mesh.F * NF) return;
+  const int64_t F = t / NF;
+  const int jj = (int)(t - F * NF);
+  const int32_t e0 = mesh.facet_elem[2 * F], e1 = mesh.facet_elem[2 * F + 1];
+  const int i0 = mesh.facet_local[2 * F], i1 = mesh.facet_local[2 * F + 1];
+  r[t] = slot[(int64_t)e0 * NFL + i0 * NF + jj] + slot[(int64_t)e1 * NFL + i1 * NF + jj];
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T, int D, int KK>
+void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, const T* frag) {
+  const int64_t waves = (mesh.E + 15) / 16;
+  const int64_t blocks = (waves + 3) / 4;
+  hipLaunchKernelGGL((k_modal<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, x, m, mesh, frag);
+}
+
+template <typename T, int D, int KK>
+void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMesh& mesh,
+                 const DevTables<T>& tb, int terms, double* diss_part) {
+  using C = Cfg<D, KK>;
+  const int64_t blocks = (mesh.nb + 3) / 4;
+  hipLaunchKernelGGL((k_elem<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, m, r, slot, mesh, tb,
+                     terms, diss_part);
+  const int64_t n = mesh.F * C::NF;
+  if (n > 0)
+    hipLaunchKernelGGL((k_assemble<C::NF, C::NFL>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, r,
+                       (const double*)slot, mesh);
+}
+
+template <int D, int KK>
+void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* slot, const DevMesh& mesh,
+                 const double* fin, const double* fout, const int* flag) {
+  using C = Cfg<D, KK>;
+  const int64_t waves = (mesh.E + 15) / 16;
+  const int64_t blocks = (waves + 3) / 4;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
+                       fout, flag);
+  else
+    hipLaunchKernelGGL((k_mass<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
+                       fout, flag);
+  const int64_t n = mesh.F * C::NF;
+  if (n > 0)
+    hipLaunchKernelGGL((k_assemble_flag<C::NF, C::NFL>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       out, (const double*)slot, mesh, flag);
+}
+
+#define HOPU_INST(D, KK)                                                                                     \
+  template void launch_modal<double, D, KK>(hipStream_t, const double*, double*, const DevMesh&,            \
+                                            const double*);                                                 \
+  template void launch_modal<float, D, KK>(hipStream_t, const double*, float*, const DevMesh&,              \
+                                           const float*);                                                   \
+  template void launch_elem<double, D, KK>(hipStream_t, const double*, double*, double*, const DevMesh&,    \
+                                           const DevTables<double>&, int, double*);                         \
+  template void launch_elem<float, D, KK>(hipStream_t, const float*, double*, double*, const DevMesh&,      \
+                                          const DevTables<float>&, int, double*);                           \
+  template void launch_mass<D, KK>(hipStream_t, int, const double*, double*, double*, const DevMesh&,       \
+                                   const double*, const double*, const int*);
+
+HOPU_INST(2, 1)
+HOPU_INST(2, 2)
+HOPU_INST(2, 3)
+HOPU_INST(2, 4)
+HOPU_INST(3, 1)
+HOPU_INST(3, 2)
+HOPU_INST(3, 3)
+HOPU_INST(3, 4)
+HOPU_INST(3, 5)
+
+}  // namespace hopu

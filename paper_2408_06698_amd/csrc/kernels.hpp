@@ -1,0 +1,71 @@
+// Device kernels of the HOPU convection library (gfx950 / CDNA4).
+// One wave64 owns a batch of 16 elements; every basis contraction is a
+// 16x16x4 MFMA whose N dimension runs over those elements.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace hopu {
+
+template <int D, int KK>
+struct Cfg {
+  static constexpr int NP = D == 2 ? (KK + 1) * (KK + 2) / 2 : (KK + 1) * (KK + 2) * (KK + 3) / 6;
+  static constexpr int NPS = (NP + 3) / 4 * 4;
+  static constexpr int NM = D * NPS;
+  static constexpr int N = D * NP;
+  static constexpr int NF = D == 2 ? KK + 1 : (KK + 1) * (KK + 2) / 2;
+  static constexpr int NFL = (D + 1) * NF;
+  static constexpr int NINT = N - NFL;
+  static constexpr int PV = (3 * KK + 1) / 2;
+  static constexpr int PF = (3 * KK + 2) / 2;
+  static constexpr int NQV = D == 2 ? PV * PV : PV * PV * PV;
+  static constexpr int NQF = D == 2 ? PF : PF * PF;
+  static constexpr int NMT = (NM + 15) / 16;
+  static constexpr int NK = (N + 3) / 4;
+  static constexpr int NQVT = (NQV + 15) / 16;
+  static constexpr int NPK = NPS / 4;
+  static constexpr int NAT = (NP + 15) / 16;
+  static constexpr int NQFT = (NQF + 15) / 16;
+  static constexpr int NFJT = (NF + 15) / 16;
+  static constexpr int NFK = 4 * NFJT;
+  static constexpr int NJT = (N + 15) / 16;
+  static constexpr int NMQ = 4 * NMT;
+};
+
+
+// Device pointers to one precision's fragment tables and weights.
+template <typename T>
+struct DevTables {
+  const T* modal;
+  const T* vol_V;
+  const T* vol_dVT;
+  const T* vol_dV;
+  const T* vol_VT;
+  const T* fac_Tr;
+  const T* fac_TrT;
+  const T* fac_K;
+  const T* fac_Psi;
+  const T* fac_PsiT;
+  const T* fac_KT;
+  const T* dual;
+  const double* wv;
+  const double* wf;
+  const int* psi_deg;
+};
+
+struct DevMesh {
+  const double* geo;
+  const int32_t* fid;
+  const int32_t* nbr;
+  const int32_t* facet_elem;
+  const int8_t* facet_local;
+  const int32_t* belem;
+  const int32_t* bsig;
+  const int8_t* lfac;  // nullable
+  int64_t E, F, nb;
+  int lglob;
+};
+
+}  // namespace hopu

@@ -1,0 +1,15 @@
+// Host-callable launchers of the device kernels (instantiated per order).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "kernels.hpp"
+
+namespace hopu {
+template <typename T, int D, int KK>
+void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, const T* frag);
+template <typename T, int D, int KK>
+void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMesh& mesh,
+                 const DevTables<T>& tb, int terms, double* diss_part);
+template <int D, int KK>
+void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* slot, const DevMesh& mesh,
+                 const double* fin, const double* fout, const int* flag);
+}  // namespace hopu

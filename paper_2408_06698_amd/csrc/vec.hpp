@@ -1,0 +1,18 @@
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hopu {
+enum { NPART = 1024 };
+enum { SC_RZ = 0, SC_ALPHA = 1, SC_BETA = 2, SC_TOL2 = 3, SC_BPB = 4, SC_RES = 5, SC_N = 8 };
+enum { OP_SET_TOL = 0, OP_SET_RZ = 1, OP_ALPHA = 2, OP_BETA = 3, OP_STORE = 4, OP_STORE_HALF = 5 };
+void vec_dot(hipStream_t s, const double* a, const double* b, int64_t n, double* part, const int* flag);
+void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag, int op, double arg,
+                double* dst);
+void vec_axpy2(hipStream_t s, double* x, double* r, const double* p, const double* q, int64_t n,
+               const double* sc, const int* flag);
+void vec_xpay(hipStream_t s, double* p, const double* z, int64_t n, const double* sc, const int* flag);
+void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n);
+void vec_axpy(hipStream_t s, double* y, const double* x, double a, int64_t n);
+void vec_copy_diag(hipStream_t s, double* dst, const double* sc, const int* flag);
+}  // namespace hopu

@@ -1,0 +1,131 @@
+// Vector kernels: deterministic two-stage dot products, PCG scalar updates,
+// axpy-type updates, energy and divergence diagnostics.
+#include "vec.hpp"
+
+namespace hopu {
+
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b,
+                                                     int64_t n, double* __restrict__ part, const int* flag) {
+  if (flag && *flag) return;
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += a[i] * b[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Reduce partials in a fixed order and apply a PCG scalar operation.
+__global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part, int np, double* sc, int* flag,
+                                                int op, double arg, double* dst) {
+  if (op != OP_SET_TOL && op != OP_STORE && op != OP_STORE_HALF && flag && *flag) return;
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double v = sh[0];
+  switch (op) {
+    case OP_SET_TOL:  // v = b.Pb
+      sc[SC_TOL2] = arg * arg * v;
+      sc[SC_BPB] = v;
+      flag[0] = 0;
+      flag[1] = 0;
+      break;
+    case OP_SET_RZ:
+      sc[SC_RZ] = v;
+      if (!(v > sc[SC_TOL2])) flag[0] = 1;
+      sc[SC_RES] = sc[SC_BPB] > 0 ? sqrt(fmax(v, 0.0) / sc[SC_BPB]) : 0.0;
+      break;
+    case OP_ALPHA:
+      sc[SC_ALPHA] = sc[SC_RZ] / v;
+      break;
+    case OP_BETA:
+      sc[SC_BETA] = v / sc[SC_RZ];
+      sc[SC_RZ] = v;
+      flag[1] += 1;
+      sc[SC_RES] = sc[SC_BPB] > 0 ? sqrt(fmax(v, 0.0) / sc[SC_BPB]) : 0.0;
+      if (!(v > sc[SC_TOL2])) flag[0] = 1;
+      break;
+    case OP_STORE:
+      *dst = v;
+      break;
+    case OP_STORE_HALF:
+      *dst = 0.5 * v;
+      break;
+    default:
+      break;
+  }
+}
+
+__global__ void k_axpy2(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                        const double* __restrict__ q, int64_t n, const double* sc, const int* flag) {
+  if (*flag) return;
+  const double al = sc[SC_ALPHA];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    x[i] += al * p[i];
+    r[i] -= al * q[i];
+  }
+}
+
+__global__ void k_xpay(double* __restrict__ p, const double* __restrict__ z, int64_t n, const double* sc,
+                       const int* flag) {
+  if (*flag) return;
+  const double be = sc[SC_BETA];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = z[i] + be * p[i];
+}
+
+__global__ void k_sub(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ q,
+                      int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) r[i] = b[i] - q[i];
+}
+
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] += a * x[i];
+}
+
+__global__ void k_copy_diag(double* dst, const double* sc, const int* flag) {
+  dst[0] = (double)flag[1];
+  dst[1] = sc[SC_RES];
+}
+
+static int grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+}
+
+void vec_dot(hipStream_t s, const double* a, const double* b, int64_t n, double* part, const int* flag) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(NPART), dim3(256), 0, s, a, b, n, part, flag);
+}
+void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag, int op, double arg,
+                double* dst) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, s, part, np, sc, flag, op, arg, dst);
+}
+void vec_axpy2(hipStream_t s, double* x, double* r, const double* p, const double* q, int64_t n,
+               const double* sc, const int* flag) {
+  hipLaunchKernelGGL(k_axpy2, dim3(grid_for(n)), dim3(256), 0, s, x, r, p, q, n, sc, flag);
+}
+void vec_xpay(hipStream_t s, double* p, const double* z, int64_t n, const double* sc, const int* flag) {
+  hipLaunchKernelGGL(k_xpay, dim3(grid_for(n)), dim3(256), 0, s, p, z, n, sc, flag);
+}
+void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n) {
+  hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, s, r, b, q, n);
+}
+void vec_axpy(hipStream_t s, double* y, const double* x, double a, int64_t n) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, y, x, a, n);
+}
+void vec_copy_diag(hipStream_t s, double* dst, const double* sc, const int* flag) {
+  hipLaunchKernelGGL(k_copy_diag, dim3(1), dim3(1), 0, s, dst, sc, flag);
+}
+
+}  // namespace hopu

@@ -1,0 +1,172 @@
+"""Python front end of libhopu: a context object over torch device tensors
+and torch.autograd.Functions for the substep chain (backward = the library's
+hand-written adjoint)."""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check, FP64, FP32_MFMA, TERM_ALL
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t):
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 tensor on the GPU")
+    return t
+
+
+class Hopu:
+    """One velocity space on one mesh (see include/hopu.h)."""
+
+    def __init__(self, dim, k, elem_vid, elem_xyz, device="cuda:0", stream=None):
+        self.device = torch.device(device)
+        vid = np.ascontiguousarray(elem_vid, dtype=np.int64)
+        xyz = np.ascontiguousarray(elem_xyz, dtype=np.float64)
+        self.dim, self.k = dim, k
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = L.lib().hopu_create(C.byref(h), dim, k, vid.shape[0],
+                                     vid.ctypes.data_as(C.c_void_p),
+                                     xyz.ctypes.data_as(C.c_void_p),
+                                     C.c_void_p(self.stream.cuda_stream))
+        check(st, None)
+        self.h = h
+        nd, nf, nw = C.c_int64(), C.c_int64(), C.c_int64()
+        nl, nfd, ni = C.c_int(), C.c_int(), C.c_int()
+        check(L.lib().hopu_sizes(h, C.byref(nd), C.byref(nf), C.byref(nw), C.byref(nl),
+                                 C.byref(nfd), C.byref(ni)), h)
+        self.n_dof, self.n_facets, self.n_wall = nd.value, nf.value, nw.value
+        self.n_loc, self.n_facet_dof, self.n_interior_dof = nl.value, nfd.value, ni.value
+        self.n_elems = vid.shape[0]
+        self._lfac = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().hopu_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def zeros(self):
+        return torch.zeros(self.n_dof, dtype=torch.float64, device=self.device)
+
+    def set_upwind(self, l, l_per_facet=None):
+        self._lfac = l_per_facet
+        check(L.lib().hopu_set_upwind(self.h, int(l), _ptr(l_per_facet)), self.h)
+
+    def set_solver(self, rtol=1e-13, max_it=500, check_every=4):
+        check(L.lib().hopu_set_solver(self.h, float(rtol), int(max_it), int(check_every)), self.h)
+
+    def apply(self, u, r=None, terms=TERM_ALL, prec=FP64):
+        r = self.zeros() if r is None else r
+        check(L.lib().hopu_convection_apply(self.h, _ptr(_dev(u)), _ptr(_dev(r)), terms, prec), self.h)
+        return r
+
+    def mass_apply(self, u, y=None):
+        y = self.zeros() if y is None else y
+        check(L.lib().hopu_mass_apply(self.h, _ptr(_dev(u)), _ptr(_dev(y))), self.h)
+        return y
+
+    def mass_solve(self, r, w=None, rtol=0.0, max_it=1000):
+        w = self.zeros() if w is None else w
+        its = C.c_int()
+        check(L.lib().hopu_mass_solve(self.h, _ptr(_dev(r)), _ptr(_dev(w)), float(rtol), int(max_it),
+                                      C.byref(its)), self.h)
+        return w, its.value
+
+    def substeps(self, u, dt, n_steps, prec=FP64, diag=False):
+        d = torch.zeros((n_steps + 1, 5), dtype=torch.float64, device=self.device) if diag else None
+        check(L.lib().hopu_substeps(self.h, _ptr(_dev(u)), float(dt), int(n_steps), prec, _ptr(d)), self.h)
+        return d
+
+    def vjp(self, u, mu, out=None, prec=FP64):
+        out = self.zeros() if out is None else out
+        check(L.lib().hopu_convection_vjp(self.h, _ptr(_dev(u)), _ptr(_dev(mu)), _ptr(_dev(out)), prec), self.h)
+        return out
+
+    def substeps_vjp(self, u0, dt, n_steps, lam_N, ckpt_every=5, prec=FP64):
+        nb = L.lib().hopu_substeps_vjp_workspace(self.h, int(n_steps), int(ckpt_every))
+        if nb < 0:
+            check(int(nb), self.h)
+        ws = torch.empty(max(int(nb), 8), dtype=torch.uint8, device=self.device)
+        lam0 = self.zeros()
+        check(L.lib().hopu_substeps_vjp(self.h, _ptr(_dev(u0)), float(dt), int(n_steps), int(ckpt_every),
+                                        _ptr(_dev(lam_N)), _ptr(lam0), prec, _ptr(ws), int(ws.numel())),
+              self.h)
+        return lam0
+
+    def diagnostics(self, u):
+        e, dv, ds = C.c_double(), C.c_double(), C.c_double()
+        check(L.lib().hopu_diagnostics(self.h, _ptr(_dev(u)), C.byref(e), C.byref(dv), C.byref(ds)), self.h)
+        return e.value, dv.value, ds.value
+
+    def interp_points(self, n1d):
+        d = self.dim
+        nqf = n1d ** (d - 1)
+        nqv = n1d ** d
+        pf = torch.empty((self.n_facets, nqf, d), dtype=torch.float64, device=self.device)
+        pv = torch.empty((self.n_elems, nqv, d), dtype=torch.float64, device=self.device)
+        check(L.lib().hopu_interp_points(self.h, int(n1d), _ptr(pf), _ptr(pv)), self.h)
+        return pf, pv
+
+    def interpolate(self, field, n1d=None):
+        """Coefficients of the canonical interpolant of `field` (callable on
+        [..., d] tensors), sampled at the library's points."""
+        n1d = n1d or (self.k + 2)
+        pf, pv = self.interp_points(n1d)
+        vf = field(pf).contiguous()
+        vv = field(pv).contiguous()
+        u = self.zeros()
+        check(L.lib().hopu_interpolate(self.h, int(n1d), _ptr(vf), _ptr(vv), _ptr(u)), self.h)
+        return u
+
+    def eval(self, u, ref_pts):
+        ref = np.ascontiguousarray(ref_pts, dtype=np.float64)
+        out = torch.empty((self.n_elems, ref.shape[0], self.dim), dtype=torch.float64, device=self.device)
+        check(L.lib().hopu_eval(self.h, _ptr(_dev(u)), ref.shape[0], ref.ctypes.data_as(C.c_void_p), _ptr(out)),
+              self.h)
+        return out
+
+
+class SubstepChain(torch.autograd.Function):
+    """u_N = S^n(u_0) with S(u) = u - dt M^-1 r(u); backward runs the
+    library's checkpointed reverse pass."""
+
+    @staticmethod
+    def forward(ctx, u0, space, dt, n_steps, ckpt_every, prec):
+        u = u0.detach().clone()
+        space.substeps(u, dt, n_steps, prec)
+        ctx.space, ctx.dt, ctx.n, ctx.ck, ctx.prec = space, dt, n_steps, ckpt_every, prec
+        ctx.save_for_backward(u0.detach())
+        return u
+
+    @staticmethod
+    def backward(ctx, g):
+        (u0,) = ctx.saved_tensors
+        lam0 = ctx.space.substeps_vjp(u0, ctx.dt, ctx.n, g.contiguous(), ctx.ck, ctx.prec)
+        return lam0, None, None, None, None, None
+
+
+class MassEnergy(torch.autograd.Function):
+    """E(u) = 1/2 u.Mu with gradient M u."""
+
+    @staticmethod
+    def forward(ctx, u, space):
+        Mu = space.mass_apply(u.detach().contiguous())
+        ctx.save_for_backward(Mu)
+        return 0.5 * torch.dot(u.detach(), Mu)
+
+    @staticmethod
+    def backward(ctx, g):
+        (Mu,) = ctx.saved_tensors
+        return g * Mu, None
