@@ -1,0 +1,221 @@
+"""Benchmark of the explicit HOPU convection substep on one MI355X.
+
+Workload: 3D periodic unit cube [0, 2 pi]^3, 32^3 cubes x 6 tets
+(196,608 tets), BDM velocity order k = 3 (7,864,320 DoFs), 3D Taylor-Green
+field interpolated by the library plus seeded N(0, 1e-3^2) coefficient
+noise, HOPU projection degree l = 2, dt = 5e-4.  One step = one explicit
+substep u <- u - dt M^-1 r(u): the convection apply (dual->modal transform,
+fused element kernel, facet-row assembly), the PCG mass solve (warm-started,
+preconditioned residual 1e-13) and the update, all on the GPU.
+
+Prints one JSON line (metric in DoF-updates/s: n_dof x steps / time).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "convection DoF-updates/s, FP64 vs mixed at ≤1e-6 rel err; % HBM/MFMA roofline"
+PEAK_FP64 = 78.6e12
+PEAK_HBM = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    return ap.parse_args()
+
+
+def flops_model(sz, E, F):
+    """Algorithmic FP64 flops of one convection apply (modal formulation,
+    contract quadrature): per element 4n^2 + 2 nq n (1 + d) + 30 nq, per
+    interior facet 8 nqf n + 8 d nqf dimP^{k-1}(F) + 40 nqf."""
+    d, k, n, nq, nqf = sz["dim"], sz["k"], sz["n"], sz["nqv"], sz["nqf"]
+    dimPf = k * (k + 1) // 2 if d == 3 else k  # dim P^{k-1} on a facet
+    fv = 4 * n * n + 2 * nq * n * (1 + d) + 30 * nq
+    ff = 8 * nqf * n + 8 * d * nqf * dimPf + 40 * nqf
+    return E * fv + F * ff, fv, ff
+
+
+def traffic_from_profiles(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    src = os.path.join(ROOT, "paper_2408_06698_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            a, b = line.split("=", 1)
+            vals[a.strip()] = b.strip()
+    if vals.get("kernels_sha") != sha or kernel_key + "_bytes_per_launch" not in vals:
+        return None
+    return float(vals[kernel_key + "_bytes_per_launch"])
+
+
+def cpu_baseline():
+    """The FP64 oracle as it stands, on a bounded sample: the same recipe on
+    4^3 x 6 = 384 tets (15,360 DoFs), one substep = residual + sparse-LU mass
+    solve + update; 1 warm-up (includes the LU factorisation), median of 3."""
+    import numpy as np
+    import synth
+    from oracle import space as S, operator as O
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [(i.get("internal_api"), i.get("num_threads")) for i in threadpool_info()]
+    except Exception:
+        blas = []
+    mesh, field, cfg = synth.make_config(2, n_override=(4, 4, 4))
+    sp = S.Space(mesh.elem_vid, mesh.elem_xyz, 3)
+    x = sp.interpolate(field, nq1d=5)
+    x = x + 1e-3 * np.random.default_rng(6698 + 2).standard_normal(sp.n_dof)
+    O.substep(sp, x, 5e-4, 2)
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        x = O.substep(sp, x, 5e-4, 2)
+        ts.append(time.perf_counter() - t0)
+    t = sorted(ts)[1]
+    return {"value": sp.n_dof / t, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"C2 recipe on 4^3x6=384 tets, k=3, {sp.n_dof} DoFs; one substep "
+                      f"(numpy einsum + SuperLU, single-threaded; BLAS pools {blas}); median of 3 "
+                      f"= {t:.2f} s per substep",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+    from synth.configs import coefficient_noise
+    from paper_2408_06698_amd.hopu import Hopu
+    from paper_2408_06698_amd import FP64, FP32_MFMA
+
+    mesh, field, cfg = synth.make_config(2)
+    k, l, dt = cfg["k"], cfg["l"], cfg["dt"]
+    h = Hopu(3, k, mesh.elem_vid, mesh.elem_xyz)
+    h.set_upwind(l)
+    h.set_solver(rtol=1e-13, max_it=1000, check_every=8)
+    u0 = h.interpolate(field, n1d=k + 2)
+    u0 += torch.tensor(coefficient_noise(2, h.n_dof, cfg["noise"]), device=u0.device)
+    ndof = h.n_dof
+    sz = dict(dim=3, k=k, n=h.n_loc, nqv=((3 * k + 1) // 2) ** 3, nqf=((3 * k + 2) // 2) ** 2)
+    stream = torch.cuda.current_stream()
+
+    def run(prec, steps, warm):
+        u = u0.clone()
+        if warm:
+            h.substeps(u, dt, warm, prec)
+        u = u0.clone()
+        torch.cuda.synchronize()
+        h.profile(True)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        diag = h.substeps(u, dt, steps, prec, diag=False)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        prof = {kk: h.profile_read(kk) for kk in ("elem", "mass", "prec", "modal")}
+        h.profile(False)
+        return u, ms, prof
+
+    u64, ms64, prof64 = run(FP64, args.steps, args.warmup)
+    value = ndof * args.steps / (ms64 * 1e-3)
+
+    # apply-only timings (FP64 and FP32 MFMA), 20 launches each
+    def apply_ms(prec, reps=20):
+        r = h.zeros()
+        h.apply(u0, r, prec=prec)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            h.apply(u0, r, prec=prec)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+    apply64 = apply_ms(FP64)
+    apply32 = apply_ms(FP32_MFMA)
+
+    # dominant kernel over the timed region
+    tot = {kk: v[1] for kk, v in prof64.items()}
+    dom = max(tot, key=tot.get)
+    E, F = mesh.n_elems, h.n_facets
+    F_apply, fv, ff = flops_model(sz, E, F)
+    n = h.n_loc
+    if dom == "elem":
+        launches, ms = prof64["elem"]
+        avg = ms / max(launches, 1) * 1e-3
+        # element kernel: everything of the apply except the dual->modal GEMM (2n^2) and assembly
+        algo = F_apply - E * 2 * n * n
+        roof = {"kernel": "k_elem (volume + HOPU facet + dual transform)", "bound": "mfma",
+                "achieved": algo / avg / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s"}
+    else:
+        launches, ms = prof64[dom]
+        avg = ms / max(launches, 1) * 1e-3
+        algo = 4.0 * n * n * E + 2.0 * 9 * (n // 3) * E  # two n x n contractions + G mixing
+        roof = {"kernel": f"k_mass ({'mass apply' if dom == 'mass' else 'preconditioner'} sandwich)",
+                "bound": "mfma", "achieved": algo / avg / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["avg_launch_us"] = avg * 1e6
+    roof["launches"] = launches
+    tr = traffic_from_profiles(dom)
+    roof["traffic"] = tr
+    out = {
+        "metric": METRIC, "value": value, "unit": "DoF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms64 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded Taylor-Green + noise)",
+        "config": {"workload": "3d_periodic_tg_k3: [0,2pi]^3 periodic, 32^3x6=196608 tets, BDM k=3, "
+                               "7,864,320 DoFs, TG + N(0,1e-3^2) noise, l=2, dt=5e-4, one substep per step",
+                   "n_dof": ndof, "elements": E, "facets": F},
+        "roofline": roof,
+        "apply_ms_fp64": apply64, "apply_ms_fp32_mfma": apply32,
+        "apply_rate_fp64": ndof / (apply64 * 1e-3), "apply_rate_fp32_mfma": ndof / (apply32 * 1e-3),
+        "apply_frac_fp64_flops": F_apply / (apply64 * 1e-3) / PEAK_FP64,
+        "pcg_iters_per_step": (prof64["mass"][0] - 2 * args.steps) / args.steps if prof64["mass"][0] else None,
+        "kernel_ms_total": {kk: v[1] for kk, v in prof64.items()},
+        "kernel_launches": {kk: v[0] for kk, v in prof64.items()},
+    }
+    if not args.no_mixed:
+        u32, ms32, prof32 = run(FP32_MFMA, args.steps, 1)
+        d = u32 - u64
+        err = float(torch.sqrt(torch.dot(d, h.mass_apply(d)) / torch.dot(u64, h.mass_apply(u64))))
+        out["mixed"] = {"value": ndof * args.steps / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
+                        "rel_err_vs_fp64_M_norm": err, "dtype": "fp32-mfma contractions, f64 state/PCG",
+                        "speedup_substep": ms64 / ms32, "speedup_apply": apply64 / apply32}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -151,6 +151,16 @@ hopu_status hopu_interpolate(hopu_ctx ctx, int n1d, const double* vals_facet,
 hopu_status hopu_eval(hopu_ctx ctx, const double* u, int n_pts,
                       const double* ref_pts, double* vals);
 
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * each launch of the main kernels (for benchmarks and roofline reports).
+ * hopu_profile_enable(ctx, 1, n) starts recording up to n launches (resets
+ * earlier records); (ctx, 0, 0) stops.  hopu_profile_read returns, for one
+ * kernel kind (0 element/convection kernel, 1 mass apply, 2 preconditioner,
+ * 3 dual->modal transform, 4 transpose-Jacobian kernel), the number of
+ * recorded launches and their summed duration in ms.  Both sync. */
+hopu_status hopu_profile_enable(hopu_ctx ctx, int enable, int max_launches);
+hopu_status hopu_profile_read(hopu_ctx ctx, int kind, int64_t* launches, double* total_ms);
+
 /* Message of the last failed call on ctx (or of the last failed
  * hopu_create when ctx is NULL); valid until the next call. */
 const char* hopu_last_error(hopu_ctx ctx);

@@ -35,6 +35,8 @@ SIGNATURES = {
     "hopu_interp_points": (_i, [_p, _i, _p, _p]),
     "hopu_interpolate": (_i, [_p, _i, _p, _p, _p]),
     "hopu_eval": (_i, [_p, _p, _i, _p, _p]),
+    "hopu_profile_enable": (_i, [_p, _i, _i]),
+    "hopu_profile_read": (_i, [_p, _i, _p, _p]),
     "hopu_last_error": (C.c_char_p, [_p]),
     "hopu_destroy": (None, [_p]),
     "hopu_host_tables": (_i64, [_i, _i, _i, _p, _i64]),

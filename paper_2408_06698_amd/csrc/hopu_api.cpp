@@ -48,7 +48,26 @@ struct hopu_ctx_s {
   double rtol = 1e-13;
   int max_it = 500, check_every = 4;
   std::string err;
+  // per-kernel timing with HIP events (hopu_profile_*)
+  int last_its = 0;
+  bool prof = false;
+  std::vector<hipEvent_t> events;       // pool, pairs
+  std::vector<int> ev_kind;             // kernel id per used pair
+  size_t ev_used = 0;
 };
+
+enum { PROF_ELEM = 0, PROF_MASS = 1, PROF_PREC = 2, PROF_MODAL = 3, PROF_VJP = 4, PROF_N = 5 };
+
+static void prof_begin(hopu_ctx ctx, int kind) {
+  if (!ctx->prof || 2 * (ctx->ev_used + 1) > ctx->events.size()) return;
+  (void)hipEventRecord(ctx->events[2 * ctx->ev_used], ctx->stream);
+  ctx->ev_kind[ctx->ev_used] = kind;
+}
+static void prof_end(hopu_ctx ctx) {
+  if (!ctx->prof || 2 * (ctx->ev_used + 1) > ctx->events.size()) return;
+  (void)hipEventRecord(ctx->events[2 * ctx->ev_used + 1], ctx->stream);
+  ++ctx->ev_used;
+}
 
 static std::string g_create_err;
 
@@ -246,8 +265,11 @@ fail_create:
 
 extern "C" void hopu_destroy(hopu_ctx ctx) {
   if (!ctx) return;
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  else (void)hipDeviceSynchronize();
+  if (!ctx->allocs.empty()) {
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+  }
+  for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->hflag) (void)hipHostFree(ctx->hflag);
   delete ctx;
@@ -287,10 +309,12 @@ extern "C" hopu_status hopu_set_solver(hopu_ctx ctx, double rtol, int max_it, in
 
 // ------------------------------------------------------------------ internals
 static hopu_status do_modal(hopu_ctx ctx, const double* u, hopu_precision prec) {
+  prof_begin(ctx, PROF_MODAL);
   DISPATCH(ctx->dim, ctx->k, {
     if (prec == HOPU_FP64) launch_modal<double, D, KK>(ctx->stream, u, ctx->m64, ctx->dm, ctx->tb64.modal);
     else launch_modal<float, D, KK>(ctx->stream, u, ctx->m32, ctx->dm, ctx->tb32.modal);
   });
+  prof_end(ctx);
   return HOPU_OK;
 }
 
@@ -298,18 +322,24 @@ static hopu_status do_apply(hopu_ctx ctx, const double* u, double* r, int terms,
                             double* diss_part) {
   hopu_status st = do_modal(ctx, u, prec);
   if (st) return st;
+  prof_begin(ctx, PROF_ELEM);
   DISPATCH(ctx->dim, ctx->k, {
     if (prec == HOPU_FP64) launch_elem<double, D, KK>(ctx->stream, ctx->m64, r, ctx->slot, ctx->dm, ctx->tb64, terms, diss_part);
     else launch_elem<float, D, KK>(ctx->stream, ctx->m32, r, ctx->slot, ctx->dm, ctx->tb32, terms, diss_part);
   });
+  prof_end(ctx);
+  DISPATCH(ctx->dim, ctx->k, { launch_assemble<D, KK>(ctx->stream, r, ctx->slot, ctx->dm, nullptr); });
   return HOPU_OK;
 }
 
 static void do_mass(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag) {
+  prof_begin(ctx, mode == 0 ? PROF_MASS : PROF_PREC);
   DISPATCH(ctx->dim, ctx->k, {
     launch_mass<D, KK>(ctx->stream, mode, x, y, ctx->slot, ctx->dm, mode == 0 ? ctx->mass_in : ctx->prec_in,
                        mode == 0 ? ctx->mass_out : ctx->prec_out, flag);
   });
+  prof_end(ctx);
+  DISPATCH(ctx->dim, ctx->k, { launch_assemble<D, KK>(ctx->stream, y, ctx->slot, ctx->dm, flag); });
 }
 
 static hopu_status check_prec(hopu_ctx ctx, hopu_precision prec) {
@@ -356,9 +386,14 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
   HCHECK(hipMemcpyAsync(ctx->p, ctx->z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   int it = 0;
   bool conv = false;
+  // the first chunk runs as many iterations as the previous solve needed
+  // (warm-started solves converge in similar counts), then check_every
+  std::vector<size_t> prof_idx;  // profile pairs of each launched iteration
   while (it < max_it) {
-    const int chunk = std::min(ctx->check_every, max_it - it);
+    const int want = (it == 0 && ctx->last_its > 1) ? ctx->last_its - 1 : ctx->check_every;
+    const int chunk = std::min(want, max_it - it);
     for (int c = 0; c < chunk; ++c) {
+      prof_idx.push_back(ctx->ev_used);
       do_mass(ctx, 0, ctx->p, ctx->q, fl);
       vec_dot(s, ctx->p, ctx->q, n, ctx->part, fl);
       vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
@@ -374,7 +409,14 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
     if (ctx->hflag[0]) { conv = true; break; }
   }
   HCHECK(hipGetLastError());
-  if (iters) *iters = ctx->hflag[1];
+  const int done = ctx->hflag[1];
+  // launches queued after convergence returned at once: keep them out of the
+  // per-kernel timing
+  if (ctx->prof)
+    for (size_t i = (size_t)std::max(done, 0); i < prof_idx.size(); ++i)
+      for (size_t e2 = prof_idx[i]; e2 < prof_idx[i] + 2 && e2 < ctx->ev_used; ++e2) ctx->ev_kind[e2] = -1;
+  ctx->last_its = done;
+  if (iters) *iters = done;
   if (!conv) {
     ctx->err = "PCG did not reach rtol within max_it iterations";
     return HOPU_ENOCONV;
@@ -639,4 +681,40 @@ extern "C" hopu_status hopu_substeps_vjp(hopu_ctx ctx, const double* u0, double 
   if (!ctx) return HOPU_EINVAL;
   (void)u0; (void)dt; (void)n_steps; (void)ckpt_every; (void)lam_N; (void)lam_0; (void)prec; (void)ws; (void)ws_bytes;
   return fail(ctx, HOPU_EUNSUPPORTED, "vjp not built");
+}
+
+// ------------------------------------------------------------------ profiling
+extern "C" hopu_status hopu_profile_enable(hopu_ctx ctx, int enable, int max_launches) {
+  if (!ctx) return HOPU_EINVAL;
+  if (enable && max_launches < 1) return fail(ctx, HOPU_EINVAL, "max_launches must be >= 1");
+  HCHECK(hipStreamSynchronize(ctx->stream));
+  if (enable) {
+    size_t need = 2 * (size_t)max_launches;
+    while (ctx->events.size() < need) {
+      hipEvent_t ev;
+      HCHECK(hipEventCreate(&ev));
+      ctx->events.push_back(ev);
+    }
+    ctx->ev_kind.assign(max_launches, -1);
+  }
+  ctx->ev_used = 0;
+  ctx->prof = enable != 0;
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_profile_read(hopu_ctx ctx, int kind, int64_t* launches, double* total_ms) {
+  if (!ctx || kind < 0 || kind >= PROF_N) return HOPU_EINVAL;
+  HCHECK(hipStreamSynchronize(ctx->stream));
+  int64_t n = 0;
+  double tot = 0.0;
+  for (size_t i = 0; i < ctx->ev_used; ++i) {
+    if (ctx->ev_kind[i] != kind) continue;
+    float ms = 0.f;
+    HCHECK(hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]));
+    tot += ms;
+    ++n;
+  }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = tot;
+  return HOPU_OK;
 }

@@ -12,4 +12,6 @@ void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMe
 template <int D, int KK>
 void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* slot, const DevMesh& mesh,
                  const double* fin, const double* fout, const int* flag);
+template <int D, int KK>
+void launch_assemble(hipStream_t s, double* r, const double* slot, const DevMesh& mesh, const int* flag);
 }  // namespace hopu

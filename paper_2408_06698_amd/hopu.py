@@ -130,6 +130,16 @@ class Hopu:
         check(L.lib().hopu_interpolate(self.h, int(n1d), _ptr(vf), _ptr(vv), _ptr(u)), self.h)
         return u
 
+    PROF_KINDS = {"elem": 0, "mass": 1, "prec": 2, "modal": 3, "vjp": 4}
+
+    def profile(self, enable, max_launches=200000):
+        check(L.lib().hopu_profile_enable(self.h, 1 if enable else 0, int(max_launches)), self.h)
+
+    def profile_read(self, kind):
+        n, ms = C.c_int64(), C.c_double()
+        check(L.lib().hopu_profile_read(self.h, self.PROF_KINDS[kind], C.byref(n), C.byref(ms)), self.h)
+        return n.value, ms.value
+
     def eval(self, u, ref_pts):
         ref = np.ascontiguousarray(ref_pts, dtype=np.float64)
         out = torch.empty((self.n_elems, ref.shape[0], self.dim), dtype=torch.float64, device=self.device)
