@@ -35,6 +35,8 @@ struct hopu_ctx_s {
   // workspaces
   double* m64 = nullptr;
   float* m32 = nullptr;
+  double* mu64 = nullptr;   // modal coefficients of the adjoint argument
+  float* mu32 = nullptr;
   double* slot = nullptr;
   double* part = nullptr;   // partial sums (max(NPART, nb, waves))
   int64_t npart = 0;
@@ -232,6 +234,8 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     const int64_t E = n_elems, n = ctx->n_dof;
     TRY(dev_alloc(ctx, &ctx->m64, (size_t)E * s.nm));
     TRY(dev_alloc(ctx, &ctx->m32, (size_t)E * s.nm));
+    TRY(dev_alloc(ctx, &ctx->mu64, (size_t)E * s.nm));
+    TRY(dev_alloc(ctx, &ctx->mu32, (size_t)E * s.nm));
     TRY(dev_alloc(ctx, &ctx->slot, (size_t)E * s.nfl));
     ctx->npart = std::max<int64_t>(std::max<int64_t>(NPART, ctx->bat.nb), (E + 15) / 16);
     TRY(dev_alloc(ctx, &ctx->part, (size_t)ctx->npart));
@@ -308,11 +312,13 @@ extern "C" hopu_status hopu_set_solver(hopu_ctx ctx, double rtol, int max_it, in
 }
 
 // ------------------------------------------------------------------ internals
-static hopu_status do_modal(hopu_ctx ctx, const double* u, hopu_precision prec) {
+static hopu_status do_modal(hopu_ctx ctx, const double* u, hopu_precision prec, bool second = false) {
   prof_begin(ctx, PROF_MODAL);
+  double* d64 = second ? ctx->mu64 : ctx->m64;
+  float* d32 = second ? ctx->mu32 : ctx->m32;
   DISPATCH(ctx->dim, ctx->k, {
-    if (prec == HOPU_FP64) launch_modal<double, D, KK>(ctx->stream, u, ctx->m64, ctx->dm, ctx->tb64.modal);
-    else launch_modal<float, D, KK>(ctx->stream, u, ctx->m32, ctx->dm, ctx->tb32.modal);
+    if (prec == HOPU_FP64) launch_modal<double, D, KK>(ctx->stream, u, d64, ctx->dm, ctx->tb64.modal);
+    else launch_modal<float, D, KK>(ctx->stream, u, d32, ctx->dm, ctx->tb32.modal);
   });
   prof_end(ctx);
   return HOPU_OK;
@@ -664,23 +670,107 @@ extern "C" int64_t hopu_host_mesh(int dim, int64_t n_elems, const int64_t* elem_
   }
 }
 
-// ------------------------------------------------------------------ adjoint (stubs until the VJP kernels land)
+// ------------------------------------------------------------------ adjoint
+static hopu_status do_vjp(hopu_ctx ctx, const double* u, const double* mu, double* out, hopu_precision prec) {
+  do_modal(ctx, u, prec, false);
+  do_modal(ctx, mu, prec, true);
+  prof_begin(ctx, PROF_VJP);
+  DISPATCH(ctx->dim, ctx->k, {
+    if (prec == HOPU_FP64) launch_vjp<double, D, KK>(ctx->stream, ctx->m64, ctx->mu64, out, ctx->slot, ctx->dm, ctx->tb64);
+    else launch_vjp<float, D, KK>(ctx->stream, ctx->m32, ctx->mu32, out, ctx->slot, ctx->dm, ctx->tb32);
+  });
+  prof_end(ctx);
+  DISPATCH(ctx->dim, ctx->k, { launch_assemble<D, KK>(ctx->stream, out, ctx->slot, ctx->dm, nullptr); });
+  return HOPU_OK;
+}
+
 extern "C" hopu_status hopu_convection_vjp(hopu_ctx ctx, const double* u, const double* mu, double* out,
                                            hopu_precision prec) {
   if (!ctx) return HOPU_EINVAL;
-  (void)u; (void)mu; (void)out; (void)prec;
-  return fail(ctx, HOPU_EUNSUPPORTED, "vjp not built");
+  if (!u || !mu || !out) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  if (check_prec(ctx, prec)) return HOPU_EINVAL;
+  refresh_dm(ctx);
+  do_vjp(ctx, u, mu, out, prec);
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
 }
+
+static int64_t n_ckpt(int n_steps, int ck) { return (n_steps + ck - 1) / ck; }
+
 extern "C" int64_t hopu_substeps_vjp_workspace(hopu_ctx ctx, int n_steps, int ckpt_every) {
-  (void)ctx; (void)n_steps; (void)ckpt_every;
-  return HOPU_EUNSUPPORTED;
+  if (!ctx || n_steps < 0 || ckpt_every < 1) return HOPU_EINVAL;
+  // checkpoints hold (state, PCG warm start); a segment buffer; 4 work vectors
+  return (2 * n_ckpt(n_steps, ckpt_every) + ckpt_every + 4) * ctx->n_dof * (int64_t)sizeof(double);
 }
+
+// one explicit substep u <- u - dt M^-1 r(u), warm-starting PCG from w
+static hopu_status substep(hopu_ctx ctx, double* u, double* w, double dt, hopu_precision prec) {
+  hopu_status st = do_apply(ctx, u, ctx->rc, HOPU_TERM_ALL, prec, nullptr);
+  if (st) return st;
+  st = pcg(ctx, ctx->rc, w, ctx->rtol, ctx->max_it, nullptr);
+  if (st) return st;
+  vec_axpy(ctx->stream, u, w, -dt, ctx->n_dof);
+  return HOPU_OK;
+}
+
 extern "C" hopu_status hopu_substeps_vjp(hopu_ctx ctx, const double* u0, double dt, int n_steps, int ckpt_every,
                                          const double* lam_N, double* lam_0, hopu_precision prec, void* ws,
                                          int64_t ws_bytes) {
   if (!ctx) return HOPU_EINVAL;
-  (void)u0; (void)dt; (void)n_steps; (void)ckpt_every; (void)lam_N; (void)lam_0; (void)prec; (void)ws; (void)ws_bytes;
-  return fail(ctx, HOPU_EUNSUPPORTED, "vjp not built");
+  if (!u0 || !lam_N || !lam_0 || !ws) return fail(ctx, HOPU_EINVAL, "NULL pointer");
+  if (n_steps < 0 || ckpt_every < 1 || !std::isfinite(dt)) return fail(ctx, HOPU_EINVAL, "bad step arguments");
+  if (check_prec(ctx, prec)) return HOPU_EINVAL;
+  const int64_t need = hopu_substeps_vjp_workspace(ctx, n_steps, ckpt_every);
+  if (ws_bytes < need) return fail(ctx, HOPU_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+  refresh_dm(ctx);
+  hipStream_t s = ctx->stream;
+  const int64_t n = ctx->n_dof;
+  const size_t vb = n * sizeof(double);
+  const int64_t nck = n_ckpt(n_steps, ckpt_every);
+  double* base = (double*)ws;
+  double* ck_u = base;                       // [nck][n]
+  double* ck_w = ck_u + nck * n;             // [nck][n]
+  double* seg = ck_w + nck * n;              // [ckpt_every][n]
+  double* u = seg + (int64_t)ckpt_every * n; // work state
+  double* lam = u + n;
+  double* muw = lam + n;
+  double* vo = muw + n;
+  // forward: checkpoint (u, w) at every ckpt_every-th state
+  HCHECK(hipMemcpyAsync(u, u0, vb, hipMemcpyDeviceToDevice, s));
+  HCHECK(hipMemsetAsync(ctx->w, 0, vb, s));
+  for (int st_i = 0; st_i < n_steps; ++st_i) {
+    if (st_i % ckpt_every == 0) {
+      const int64_t c = st_i / ckpt_every;
+      HCHECK(hipMemcpyAsync(ck_u + c * n, u, vb, hipMemcpyDeviceToDevice, s));
+      HCHECK(hipMemcpyAsync(ck_w + c * n, ctx->w, vb, hipMemcpyDeviceToDevice, s));
+    }
+    hopu_status st = substep(ctx, u, ctx->w, dt, prec);
+    if (st) return st;
+  }
+  // reverse
+  HCHECK(hipMemcpyAsync(lam, lam_N, vb, hipMemcpyDeviceToDevice, s));
+  HCHECK(hipMemsetAsync(muw, 0, vb, s));
+  for (int64_t c = nck - 1; c >= 0; --c) {
+    const int s0 = (int)(c * ckpt_every), s1 = std::min(n_steps, s0 + ckpt_every);
+    HCHECK(hipMemcpyAsync(seg, ck_u + c * n, vb, hipMemcpyDeviceToDevice, s));
+    HCHECK(hipMemcpyAsync(u, ck_u + c * n, vb, hipMemcpyDeviceToDevice, s));
+    HCHECK(hipMemcpyAsync(ctx->w, ck_w + c * n, vb, hipMemcpyDeviceToDevice, s));
+    for (int st_i = s0; st_i < s1 - 1; ++st_i) {
+      hopu_status st = substep(ctx, u, ctx->w, dt, prec);
+      if (st) return st;
+      HCHECK(hipMemcpyAsync(seg + (int64_t)(st_i - s0 + 1) * n, u, vb, hipMemcpyDeviceToDevice, s));
+    }
+    for (int st_i = s1 - 1; st_i >= s0; --st_i) {
+      hopu_status st = pcg(ctx, lam, muw, ctx->rtol, ctx->max_it, nullptr);
+      if (st) return st;
+      do_vjp(ctx, seg + (int64_t)(st_i - s0) * n, muw, vo, prec);
+      vec_axpy(s, lam, vo, -dt, n);
+    }
+  }
+  HCHECK(hipMemcpyAsync(lam_0, lam, vb, hipMemcpyDeviceToDevice, s));
+  HCHECK(hipGetLastError());
+  HCHECK(hipStreamSynchronize(s));
+  return HOPU_OK;
 }
 
 // ------------------------------------------------------------------ profiling

@@ -14,4 +14,7 @@ void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* 
                  const double* fin, const double* fout, const int* flag);
 template <int D, int KK>
 void launch_assemble(hipStream_t s, double* r, const double* slot, const DevMesh& mesh, const int* flag);
+template <typename T, int D, int KK>
+void launch_vjp(hipStream_t s, const T* mu_u, const T* mu_mu, double* out, double* slot, const DevMesh& mesh,
+                const DevTables<T>& tb);
 }  // namespace hopu

@@ -1,2 +1,404 @@
-// transpose-Jacobian kernels (filled in below)
-#include <hip/hip_runtime.h>
+// Transpose Jacobian of the convection residual, out = J_r(u)^T mu.
+// With mu_h = sum mu_i phi_i, for each basis function phi_j:
+//   - int_T phi_j . (grad mu_h + grad mu_h^T) u
+//   + int_E (phi_j.n) s + (u.n) <phi_j>.[[mu]] + 1/2|u.n| (I-Pi)[[phi_j]].(I-Pi)[[mu]]
+//   s = <u>.[[mu]] + 1/2 sgn(u.n) (I-Pi)[[u]].(I-Pi)[[mu]],  sgn(0) = 0.
+// Each element tests with its own trace from its own side (n its outward
+// normal, [[.]] = own - neighbour): h = 1/2 s n + 1/2 (u.n)[[mu]] + (I-Pi)a,
+// a = 1/2|u.n|(I-Pi)[[mu]]; the neighbour does the same from its side.
+// Batches, tables and fragment layouts are those of the forward kernel.
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace hopu {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct VM;
+template <> struct VM<double> {
+  typedef d4 V;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int i, int g) { return 4 * i + g; }
+};
+template <> struct VM<float> {
+  typedef f4 V;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int i, int g) { return 4 * g + i; }
+};
+template <typename V> __device__ __forceinline__ V vz() { V v = {0, 0, 0, 0}; return v; }
+
+template <typename T, int D, int KK>
+__global__ __launch_bounds__(256) void k_vjp(const T* __restrict__ mu_m, const T* __restrict__ mm_m,
+                                             double* __restrict__ out, double* __restrict__ oslot, DevMesh mesh,
+                                             DevTables<T> tb) {
+  using C = Cfg<D, KK>;
+  using M = VM<T>;
+  using V = typename M::V;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= mesh.nb) return;
+  const int32_t e = mesh.belem[b * 16 + c];
+  const bool valid = e >= 0;
+  const int64_t ee = valid ? e : mesh.belem[b * 16];
+  const int sig = mesh.bsig[b];
+  const double* Gr = mesh.geo + ee * GEO_STRIDE;
+  double J[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int cc = 0; cc < D; ++cc) J[r][cc] = Gr[r * D + cc];
+  const double det = Gr[GEO_DET], idet = 1.0 / det;
+
+  T uB[D][C::NPK], mB[D][C::NPK];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int kk = 0; kk < C::NPK; ++kk) {
+      uB[a][kk] = mu_m[ee * C::NM + kk * 4 * D + 4 * a + g];
+      mB[a][kk] = mm_m[ee * C::NM + kk * 4 * D + 4 * a + g];
+    }
+  double acc[D][C::NAT][4];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int at = 0; at < C::NAT; ++at)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[a][at][i] = 0.0;
+
+  // ---------------- volume: - sgn/det^2 int phi^ . (G (grad^mu^) u^ + (grad^mu^)^T G u^)
+  {
+    double Gm[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int bb = 0; bb < D; ++bb) {
+        double s = 0;
+#pragma unroll
+        for (int r2 = 0; r2 < D; ++r2) s += J[r2][a] * J[r2][bb];
+        Gm[a][bb] = s;
+      }
+    const double sc = -idet * idet * (det > 0 ? 1.0 : -1.0);
+    for (int qt = 0; qt < C::NQVT; ++qt) {
+      V u[D], gm[D][D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        u[a] = vz<V>();
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) gm[a][bb] = vz<V>();
+      }
+#pragma unroll
+      for (int kk = 0; kk < C::NPK; ++kk) {
+        const T av = tb.vol_V[(qt * C::NPK + kk) * 64 + lane];
+#pragma unroll
+        for (int a = 0; a < D; ++a) u[a] = M::mma(av, uB[a][kk], u[a]);
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) {
+          const T ad = tb.vol_dV[((qt * D + bb) * C::NPK + kk) * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < D; ++a) gm[a][bb] = M::mma(ad, mB[a][kk], gm[a][bb]);
+        }
+      }
+      T v[D][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = 16 * qt + M::row(i, g);
+        const double wq = q < C::NQV ? tb.wv[q] : 0.0;
+        double uh[D], gu[D], t1[D], vv[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) uh[a] = (double)u[a][i];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double s = 0, s2 = 0;
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) { s += Gm[a][bb] * uh[bb]; s2 += (double)gm[a][bb][i] * uh[bb]; }
+          gu[a] = s;   // G u^
+          t1[a] = s2;  // (grad^ mu^) u^
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double s = 0, s2 = 0;
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) { s += Gm[a][bb] * t1[bb]; s2 += (double)gm[bb][a][i] * gu[bb]; }
+          vv[a] = (s + s2) * wq * sc;
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) v[a][i] = (T)vv[a];
+      }
+      V t[D][C::NAT];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int at = 0; at < C::NAT; ++at) t[a][at] = vz<V>();
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int at = 0; at < C::NAT; ++at) {
+          const T av = tb.vol_VT[((qt * 4 + i) * C::NAT + at) * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < D; ++a) t[a][at] = M::mma(av, v[a][i], t[a][at]);
+        }
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int at = 0; at < C::NAT; ++at)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[a][at][i] += (double)t[a][at][i];
+    }
+  }
+
+  // ---------------- facets
+  for (int f = 0; f <= D; ++f) {
+    const int fp = (sig >> (4 * f)) & 0xF;
+    if (fp == 0xF) continue;
+    const int32_t en = valid ? mesh.nbr[ee * (D + 1) + f] : (int32_t)ee;
+    const double* Gn = mesh.geo + (int64_t)en * GEO_STRIDE;
+    double Jn[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int cc = 0; cc < D; ++cc) Jn[r][cc] = Gn[r * D + cc];
+    const double idetn = 1.0 / Gn[GEO_DET];
+    const double nfn = Gr[GEO_NFN + f];
+    double nrm[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) nrm[a] = Gr[GEO_NRM + f * D + a];
+    int lf = mesh.lglob;
+    if (mesh.lfac) lf = valid ? (int)mesh.lfac[mesh.fid[ee * (D + 1) + f]] : -1;
+    T nuB[D][C::NPK], nmB[D][C::NPK];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int kk = 0; kk < C::NPK; ++kk) {
+        nuB[a][kk] = mu_m[(int64_t)en * C::NM + kk * 4 * D + 4 * a + g];
+        nmB[a][kk] = mm_m[(int64_t)en * C::NM + kk * 4 * D + 4 * a + g];
+      }
+    // projection moments of [[u]] and [[mu]]
+    T cu[D][C::NFJT][4], cm[D][C::NFJT][4];
+#pragma unroll
+    for (int jt = 0; jt < C::NFJT; ++jt) {
+      V ro[D], rn[D], so[D], sn[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) { ro[a] = vz<V>(); rn[a] = vz<V>(); so[a] = vz<V>(); sn[a] = vz<V>(); }
+#pragma unroll
+      for (int kk = 0; kk < C::NPK; ++kk) {
+        const T ao = tb.fac_K[((f * C::NFJT + jt) * C::NPK + kk) * 64 + lane];
+        const T an = tb.fac_K[((fp * C::NFJT + jt) * C::NPK + kk) * 64 + lane];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          ro[a] = M::mma(ao, uB[a][kk], ro[a]);
+          rn[a] = M::mma(an, nuB[a][kk], rn[a]);
+          so[a] = M::mma(ao, mB[a][kk], so[a]);
+          sn[a] = M::mma(an, nmB[a][kk], sn[a]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = 16 * jt + M::row(i, g);
+        const bool keep = j < C::NF && tb.psi_deg[j < C::NF ? j : 0] <= lf;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double s1 = 0, s2 = 0;
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) {
+            s1 += J[a][bb] * (double)ro[bb][i] * idet - Jn[a][bb] * (double)rn[bb][i] * idetn;
+            s2 += J[a][bb] * (double)so[bb][i] * idet - Jn[a][bb] * (double)sn[bb][i] * idetn;
+          }
+          cu[a][jt][i] = keep ? (T)s1 : (T)0;
+          cm[a][jt][i] = keep ? (T)s2 : (T)0;
+        }
+      }
+    }
+    V c2[D][C::NFJT];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int jt = 0; jt < C::NFJT; ++jt) c2[a][jt] = vz<V>();
+    for (int qt = 0; qt < C::NQFT; ++qt) {
+      V to[D], tn[D], mo[D], mn[D], pu[D], pm[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        to[a] = vz<V>(); tn[a] = vz<V>(); mo[a] = vz<V>(); mn[a] = vz<V>(); pu[a] = vz<V>(); pm[a] = vz<V>();
+      }
+#pragma unroll
+      for (int kk = 0; kk < C::NPK; ++kk) {
+        const T ao = tb.fac_Tr[((f * C::NQFT + qt) * C::NPK + kk) * 64 + lane];
+        const T an = tb.fac_Tr[((fp * C::NQFT + qt) * C::NPK + kk) * 64 + lane];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          to[a] = M::mma(ao, uB[a][kk], to[a]);
+          tn[a] = M::mma(an, nuB[a][kk], tn[a]);
+          mo[a] = M::mma(ao, mB[a][kk], mo[a]);
+          mn[a] = M::mma(an, nmB[a][kk], mn[a]);
+        }
+      }
+#pragma unroll
+      for (int jk = 0; jk < C::NFK; ++jk) {
+        const T ap = tb.fac_Psi[(qt * C::NFK + jk) * 64 + lane];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          pu[a] = M::mma(ap, cu[a][jk / 4][jk % 4], pu[a]);
+          pm[a] = M::mma(ap, cm[a][jk / 4][jk % 4], pm[a]);
+        }
+      }
+      T h[D][4], aw[D][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = 16 * qt + M::row(i, g);
+        const double wq = q < C::NQF ? tb.wf[q] : 0.0;
+        double uo[D], un[D], mo2[D], mn2[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) {
+            s1 += J[a][bb] * (double)to[bb][i];
+            s2 += Jn[a][bb] * (double)tn[bb][i];
+            s3 += J[a][bb] * (double)mo[bb][i];
+            s4 += Jn[a][bb] * (double)mn[bb][i];
+          }
+          uo[a] = s1 * idet; un[a] = s2 * idetn; mo2[a] = s3 * idet; mn2[a] = s4 * idetn;
+        }
+        double unn = 0, s_avg = 0, s_up = 0, jm[D], jmp[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) unn += 0.5 * (uo[a] + un[a]) * nrm[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          jm[a] = mo2[a] - mn2[a];
+          jmp[a] = jm[a] - (double)pm[a][i];
+          const double jup = (uo[a] - un[a]) - (double)pu[a][i];
+          s_avg += 0.5 * (uo[a] + un[a]) * jm[a];
+          s_up += jup * jmp[a];
+        }
+        const double sg = unn > 0 ? 1.0 : (unn < 0 ? -1.0 : 0.0);
+        const double s = s_avg + 0.5 * sg * s_up;
+        const double hu = 0.5 * fabs(unn);
+        double gg[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const double av_ = hu * jmp[a];
+          aw[a][i] = (T)av_;
+          gg[a] = 0.5 * s * nrm[a] + 0.5 * unn * jm[a] + av_;
+        }
+        const double sh = wq * nfn * idet;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double t2 = 0;
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) t2 += J[bb][a] * gg[bb];
+          h[a][i] = (T)(t2 * sh);
+        }
+      }
+      V t[D][C::NAT];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int at = 0; at < C::NAT; ++at) t[a][at] = vz<V>();
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int at = 0; at < C::NAT; ++at) {
+          const T av = tb.fac_TrT[(((f * C::NQFT + qt) * 4 + i) * C::NAT + at) * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < D; ++a) t[a][at] = M::mma(av, h[a][i], t[a][at]);
+        }
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int at = 0; at < C::NAT; ++at)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[a][at][i] += (double)t[a][at][i];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jt = 0; jt < C::NFJT; ++jt) {
+          const T ap = tb.fac_PsiT[((qt * 4 + i) * C::NFJT + jt) * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < D; ++a) c2[a][jt] = M::mma(ap, aw[a][i], c2[a][jt]);
+        }
+    }
+    T cc[D][C::NFJT][4];
+#pragma unroll
+    for (int jt = 0; jt < C::NFJT; ++jt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = 16 * jt + M::row(i, g);
+        const bool keep = j < C::NF && tb.psi_deg[j < C::NF ? j : 0] <= lf;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double s = 0;
+#pragma unroll
+          for (int bb = 0; bb < D; ++bb) s += J[bb][a] * (double)c2[bb][jt][i];
+          cc[a][jt][i] = keep ? (T)(-s * nfn * idet) : (T)0;
+        }
+      }
+    V t[D][C::NAT];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int at = 0; at < C::NAT; ++at) t[a][at] = vz<V>();
+#pragma unroll
+    for (int jk = 0; jk < C::NFK; ++jk)
+#pragma unroll
+      for (int at = 0; at < C::NAT; ++at) {
+        const T av = tb.fac_KT[((f * C::NAT + at) * C::NFK + jk) * 64 + lane];
+#pragma unroll
+        for (int a = 0; a < D; ++a) t[a][at] = M::mma(av, cc[a][jk / 4][jk % 4], t[a][at]);
+      }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int at = 0; at < C::NAT; ++at)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[a][at][i] += (double)t[a][at][i];
+  }
+
+  const int64_t off = mesh.F * C::NF;
+#pragma unroll
+  for (int jt = 0; jt < C::NJT; ++jt) {
+    V o = vz<V>();
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int at = 0; at < C::NAT; ++at)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          o = M::mma(tb.dual[((((jt * D + a) * C::NAT + at) * 4) + i) * 64 + lane], (T)acc[a][at][i], o);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = 16 * jt + M::row(i, g);
+      if (valid && j < C::N) {
+        if (j < C::NFL) oslot[ee * C::NFL + j] = (double)o[i] * Gr[GEO_NFN + j / C::NF];
+        else out[off + ee * C::NINT + (j - C::NFL)] = (double)o[i] * Gr[GEO_SI];
+      }
+    }
+  }
+}
+
+template <typename T, int D, int KK>
+void launch_vjp(hipStream_t s, const T* mu_u, const T* mu_mu, double* out, double* slot, const DevMesh& mesh,
+                const DevTables<T>& tb) {
+  const int64_t blocks = (mesh.nb + 3) / 4;
+  hipLaunchKernelGGL((k_vjp<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, mu_u, mu_mu, out, slot, mesh, tb);
+}
+
+#define HOPU_VJP_INST(D, KK)                                                                                  \
+  template void launch_vjp<double, D, KK>(hipStream_t, const double*, const double*, double*, double*,       \
+                                          const DevMesh&, const DevTables<double>&);                         \
+  template void launch_vjp<float, D, KK>(hipStream_t, const float*, const float*, double*, double*,          \
+                                         const DevMesh&, const DevTables<float>&);
+HOPU_VJP_INST(2, 1)
+HOPU_VJP_INST(2, 2)
+HOPU_VJP_INST(2, 3)
+HOPU_VJP_INST(2, 4)
+HOPU_VJP_INST(3, 1)
+HOPU_VJP_INST(3, 2)
+HOPU_VJP_INST(3, 3)
+HOPU_VJP_INST(3, 4)
+HOPU_VJP_INST(3, 5)
+
+}  // namespace hopu
