@@ -41,6 +41,7 @@ struct hopu_ctx_s {
   double* part = nullptr;   // partial sums (max(NPART, nb, waves))
   int64_t npart = 0;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *rc = nullptr;
+  double* wh[3] = {nullptr, nullptr, nullptr};  // previous substep solutions (newest first)
   double* sc = nullptr;
   int* flag = nullptr;      // [0] converged, [1] iterations
   int* hflag = nullptr;     // pinned host copy
@@ -245,6 +246,7 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(dev_alloc(ctx, &ctx->q, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->w, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->rc, (size_t)n));
+    for (int i = 0; i < 3; ++i) TRY(dev_alloc(ctx, &ctx->wh[i], (size_t)n));
     TRY(dev_alloc(ctx, &ctx->sc, SC_N));
     TRY(dev_alloc(ctx, &ctx->flag, 4));
     void* hp = nullptr;
@@ -486,7 +488,10 @@ extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_s
   if (check_prec(ctx, prec)) return HOPU_EINVAL;
   refresh_dm(ctx);
   hipStream_t s = ctx->stream;
-  HCHECK(hipMemsetAsync(ctx->w, 0, ctx->n_dof * sizeof(double), s));
+  // PCG initial guess: polynomial extrapolation of the previous solutions
+  // (w_{n-1}; 2w_{n-1} - w_{n-2}; 3w_{n-1} - 3w_{n-2} + w_{n-3})
+  double* wh[3] = {ctx->wh[0], ctx->wh[1], ctx->wh[2]};
+  int nh = 0;
   for (int st_i = 0; st_i <= n_steps; ++st_i) {
     const bool last = st_i == n_steps;
     if (diag_dev) {
@@ -503,11 +508,20 @@ extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_s
     if (last) break;
     hopu_status st = do_apply(ctx, u, ctx->rc, HOPU_TERM_ALL, prec, nullptr);
     if (st) return st;
+    double* w = wh[2];
+    if (nh == 0) HCHECK(hipMemsetAsync(w, 0, ctx->n_dof * sizeof(double), s));
+    else if (nh == 1) HCHECK(hipMemcpyAsync(w, wh[0], ctx->n_dof * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else if (nh == 2) vec_comb3(s, w, wh[0], wh[1], 2.0, -1.0, 0.0, ctx->n_dof);
+    else vec_comb3(s, w, wh[0], wh[1], 3.0, -3.0, 1.0, ctx->n_dof);
     int its = 0;
-    st = pcg(ctx, ctx->rc, ctx->w, ctx->rtol, ctx->max_it, &its);
+    st = pcg(ctx, ctx->rc, w, ctx->rtol, ctx->max_it, &its);
     if (st) return st;
     if (diag_dev) vec_copy_diag(s, diag_dev + (int64_t)(st_i + 1) * 5 + 3, ctx->sc, ctx->flag);
-    vec_axpy(s, u, ctx->w, -dt, ctx->n_dof);
+    vec_axpy(s, u, w, -dt, ctx->n_dof);
+    wh[2] = wh[1];
+    wh[1] = wh[0];
+    wh[0] = w;
+    nh = std::min(nh + 1, 3);
   }
   HCHECK(hipGetLastError());
   HCHECK(hipStreamSynchronize(s));

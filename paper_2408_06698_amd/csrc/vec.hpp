@@ -14,5 +14,7 @@ void vec_axpy2(hipStream_t s, double* x, double* r, const double* p, const doubl
 void vec_xpay(hipStream_t s, double* p, const double* z, int64_t n, const double* sc, const int* flag);
 void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n);
 void vec_axpy(hipStream_t s, double* y, const double* x, double a, int64_t n);
+void vec_comb3(hipStream_t s, double* w, const double* h1, const double* h2, double a, double b, double c,
+               int64_t n);
 void vec_copy_diag(hipStream_t s, double* dst, const double* sc, const int* flag);
 }  // namespace hopu

@@ -94,6 +94,13 @@ __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, dou
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] += a * x[i];
 }
 
+// w = a h1 + b h2 + c w (w may hold h3)
+__global__ void k_comb3(double* __restrict__ w, const double* __restrict__ h1, const double* __restrict__ h2,
+                        double a, double b, double c, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    w[i] = a * h1[i] + b * h2[i] + (c != 0.0 ? c * w[i] : 0.0);
+}
+
 __global__ void k_copy_diag(double* dst, const double* sc, const int* flag) {
   dst[0] = (double)flag[1];
   dst[1] = sc[SC_RES];
@@ -123,6 +130,10 @@ void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t
 }
 void vec_axpy(hipStream_t s, double* y, const double* x, double a, int64_t n) {
   hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, y, x, a, n);
+}
+void vec_comb3(hipStream_t s, double* w, const double* h1, const double* h2, double a, double b, double c,
+               int64_t n) {
+  hipLaunchKernelGGL(k_comb3, dim3(grid_for(n)), dim3(256), 0, s, w, h1, h2, a, b, c, n);
 }
 void vec_copy_diag(hipStream_t s, double* dst, const double* sc, const int* flag) {
   hipLaunchKernelGGL(k_copy_diag, dim3(1), dim3(1), 0, s, dst, sc, flag);
