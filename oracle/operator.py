@@ -25,10 +25,30 @@ TERM_ALL = 7
 
 
 # ------------------------------------------------------------------ facets
-def _facet_batches(sp, size=2048):
+def _facet_batches(sp, size=2048, facets=None):
     t = sp.topo
+    if facets is not None:
+        for s in range(0, len(facets), size):
+            yield facets[s:s + size]
+        return
     for s in range(0, t.n_facets, size):
         yield np.arange(s, min(t.n_facets, s + size))
+
+
+def _elem_batches(sp, elems, size):
+    if elems is None:
+        yield from sp.batches(sp.topo.n_elems, size)
+        return
+    for s in range(0, len(elems), size):
+        yield elems[s:s + size]
+
+
+def _facets_of(sp, elems):
+    """Interior facets touching the given elements (sorted)."""
+    if elems is None:
+        return None
+    f = sp.topo.elem_facet[elems].ravel()
+    return np.unique(f[f >= 0])
 
 
 def _facet_traces(sp, fb):
@@ -60,11 +80,14 @@ def _projector(sp, lf):
     return np.einsum("qj,bj,pj,p->bqp", psi, mask, psi, w)
 
 
-def residual(sp, x, l, terms=TERM_ALL):
+def residual(sp, x, l, terms=TERM_ALL, elems=None):
+    """elems (optional): evaluate only the volume terms of these elements and
+    the facet terms of their facets; rows of their interior DoFs, and of
+    facets whose two elements are both listed, are then complete."""
     t = sp.topo
     r = np.zeros(sp.n_dof)
     if terms & TERM_VOLUME:
-        for eb in sp.batches(t.n_elems, sp.elem_batch_size()):
+        for eb in _elem_batches(sp, elems, sp.elem_batch_size()):
             xl = sp.local(x, eb)
             phi = sp.phys_vals(eb, sp.ref_vals)
             gphi = sp.phys_grads(eb, sp.ref_grads)
@@ -74,7 +97,7 @@ def residual(sp, x, l, terms=TERM_ALL):
             sp.scatter(r, eb, -val)
     if terms & (TERM_CENTRAL | TERM_UPWIND):
         lf_all = sp.facet_l(l)
-        for fb in _facet_batches(sp):
+        for fb in _facet_batches(sp, facets=_facets_of(sp, elems)):
             T, T2, phiT, phiT2, nvec, ds = _facet_traces(sp, fb)
             uT = np.einsum("bqid,bi->bqd", phiT, sp.local(x, T))
             uT2 = np.einsum("bqid,bi->bqd", phiT2, sp.local(x, T2))
@@ -229,16 +252,17 @@ def dissipation(sp, x, l):
 
 
 # ------------------------------------------------------------ adjoints
-def vjp(sp, x, mu, l):
+def vjp(sp, x, mu, l, elems=None):
     """(J_r(u)^T mu)_j = d/du_j sum_i mu_i r_i(u), with mu_h = sum mu_i phi_i:
       - sum_T int phi_j . (grad mu_h + grad mu_h^T) u
       + sum_E int (phi_j.n) s + (u.n) <phi_j>.[[mu_h]]
                   + 1/2 |u.n| (I-Pi)[[phi_j]] . (I-Pi)[[mu_h]]
       s = <u>.[[mu_h]] + 1/2 sgn(u.n) (I-Pi)[[u]] . (I-Pi)[[mu_h]], sgn(0) = 0;
-    phi_j . n is single valued and equals <phi_j> . n."""
+    phi_j . n is single valued and equals <phi_j> . n.  `elems` restricts the
+    loops as in residual()."""
     t = sp.topo
     out = np.zeros(sp.n_dof)
-    for eb in sp.batches(t.n_elems, sp.elem_batch_size()):
+    for eb in _elem_batches(sp, elems, sp.elem_batch_size()):
         phi = sp.phys_vals(eb, sp.ref_vals)
         gphi = sp.phys_grads(eb, sp.ref_grads)
         u = np.einsum("bqid,bi->bqd", phi, sp.local(x, eb))
@@ -247,7 +271,7 @@ def vjp(sp, x, mu, l):
         wdx = sp.wq[None, :] * np.abs(t.detJ[eb])[:, None]
         sp.scatter(out, eb, -np.einsum("bq,bqa,bqia->bi", wdx, v, phi))
     lf_all = sp.facet_l(l)
-    for fb in _facet_batches(sp):
+    for fb in _facet_batches(sp, facets=_facets_of(sp, elems)):
         T, T2, phiT, phiT2, nvec, ds = _facet_traces(sp, fb)
         uT = np.einsum("bqid,bi->bqd", phiT, sp.local(x, T))
         uT2 = np.einsum("bqid,bi->bqd", phiT2, sp.local(x, T2))
