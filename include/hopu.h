@@ -155,8 +155,9 @@ hopu_status hopu_eval(hopu_ctx ctx, const double* u, int n_pts,
  * each launch of the main kernels (for benchmarks and roofline reports).
  * hopu_profile_enable(ctx, 1, n) starts recording up to n launches (resets
  * earlier records); (ctx, 0, 0) stops.  hopu_profile_read returns, for one
- * kernel kind (0 element/convection kernel, 1 mass apply, 2 preconditioner,
- * 3 dual->modal transform, 4 transpose-Jacobian kernel), the number of
+ * kernel kind (0 element/convection kernel, 1 mass apply inside PCG,
+ * 2 preconditioner inside PCG, 3 dual->modal transform, 4 transpose-Jacobian
+ * kernel, 5 mass/preconditioner applies outside the PCG loop), the number of
  * recorded launches and their summed duration in ms.  Both sync. */
 hopu_status hopu_profile_enable(hopu_ctx ctx, int enable, int max_launches);
 hopu_status hopu_profile_read(hopu_ctx ctx, int kind, int64_t* launches, double* total_ms);

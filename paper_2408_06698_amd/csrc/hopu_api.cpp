@@ -59,7 +59,7 @@ struct hopu_ctx_s {
   size_t ev_used = 0;
 };
 
-enum { PROF_ELEM = 0, PROF_MASS = 1, PROF_PREC = 2, PROF_MODAL = 3, PROF_VJP = 4, PROF_N = 5 };
+enum { PROF_ELEM = 0, PROF_MASS = 1, PROF_PREC = 2, PROF_MODAL = 3, PROF_VJP = 4, PROF_PLAIN = 5, PROF_N = 6 };
 
 static void prof_begin(hopu_ctx ctx, int kind) {
   if (!ctx->prof || 2 * (ctx->ev_used + 1) > ctx->events.size()) return;
@@ -340,8 +340,8 @@ static hopu_status do_apply(hopu_ctx ctx, const double* u, double* r, int terms,
   return HOPU_OK;
 }
 
-static void do_mass(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag) {
-  prof_begin(ctx, mode == 0 ? PROF_MASS : PROF_PREC);
+static void do_mass(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag, bool in_loop = false) {
+  prof_begin(ctx, in_loop ? (mode == 0 ? PROF_MASS : PROF_PREC) : PROF_PLAIN);
   DISPATCH(ctx->dim, ctx->k, {
     launch_mass<D, KK>(ctx->stream, mode, x, y, ctx->slot, ctx->dm, mode == 0 ? ctx->mass_in : ctx->prec_in,
                        mode == 0 ? ctx->mass_out : ctx->prec_out, flag);
@@ -402,11 +402,11 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
     const int chunk = std::min(want, max_it - it);
     for (int c = 0; c < chunk; ++c) {
       prof_idx.push_back(ctx->ev_used);
-      do_mass(ctx, 0, ctx->p, ctx->q, fl);
+      do_mass(ctx, 0, ctx->p, ctx->q, fl, true);
       vec_dot(s, ctx->p, ctx->q, n, ctx->part, fl);
       vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
       vec_axpy2(s, x, ctx->r, ctx->p, ctx->q, n, ctx->sc, fl);
-      do_mass(ctx, 1, ctx->r, ctx->z, fl);
+      do_mass(ctx, 1, ctx->r, ctx->z, fl, true);
       vec_dot(s, ctx->r, ctx->z, n, ctx->part, fl);
       vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_BETA, 0.0, nullptr);
       vec_xpay(s, ctx->p, ctx->z, n, ctx->sc, fl);

@@ -1,8 +1,12 @@
 // HIP kernels for gfx950.  See kernels.hpp for the batch/tile conventions.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "launch.hpp"
 
 namespace hopu {
+
+static constexpr int64_t MASS_BLOCKS = 512;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -426,28 +430,25 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
 // MODE 0: y = M_T x_T  = S Dinv^T (G (x) I) Dinv S x_T / |det J|
 // MODE 1: y = (M_T^-1)(1/2 facet rows)  = 1/2 S^-1 D (G^-1 (x) I) D^T S^-1 (1/2) x_T |det J|
 // Facet rows go to slots (summed by k_assemble), interior rows to out.
+// Each wave walks batches of 16 elements with a grid stride and gathers the
+// next batch while the MFMAs of the current one run.
 template <int D, int KK, int MODE>
-__global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, double* __restrict__ out,
-                                              double* __restrict__ slot, DevMesh mesh,
-                                              const double* __restrict__ fin,
-                                              const double* __restrict__ fout,
-                                              const int* __restrict__ flag) {
+__device__ __forceinline__ void mass_gather(const double* __restrict__ x, const DevMesh& mesh, int64_t wave, int g,
+                                            int c, double (&xh)[Cfg<D, KK>::NK]) {
   using C = Cfg<D, KK>;
-  using M = MF<double>;
-  if (flag && *flag) return;
-  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wave * 16 >= mesh.E) return;
   const int64_t e = wave * 16 + c;
   const bool valid = e < mesh.E;
   const int64_t ee = valid ? e : 0;
   const double* Gr = mesh.geo + ee * GEO_STRIDE;
   const int64_t off = mesh.F * C::NF;
+  int32_t fid[D + 1];
   double sfac[D + 1];
 #pragma unroll
-  for (int f = 0; f <= D; ++f) sfac[f] = MODE == 0 ? Gr[GEO_NFN + f] : 0.5 / Gr[GEO_NFN + f];
+  for (int f = 0; f <= D; ++f) {
+    fid[f] = mesh.fid[ee * (D + 1) + f];
+    sfac[f] = MODE == 0 ? Gr[GEO_NFN + f] : 0.5 / Gr[GEO_NFN + f];
+  }
   const double sint = MODE == 0 ? Gr[GEO_SI] : 1.0 / Gr[GEO_SI];
-  double xh[C::NK];
 #pragma unroll
   for (int kk = 0; kk < C::NK; ++kk) {
     const int j = 4 * kk + g;
@@ -455,20 +456,35 @@ __global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, doub
     if (valid && j < C::N) {
       if (j < C::NFL) {
         const int f = j / C::NF, jj = j - f * C::NF;
-        const int32_t F = mesh.fid[ee * (D + 1) + f];
-        if (F >= 0) v = x[(int64_t)F * C::NF + jj] * sfac[f];
+        if (fid[f] >= 0) v = x[(int64_t)fid[f] * C::NF + jj] * sfac[f];
       } else {
         v = x[off + ee * C::NINT + (j - C::NFL)] * sint;
       }
     }
     xh[kk] = v;
   }
+}
+
+// one batch: xh gathered, outputs written
+template <int D, int KK, int MODE>
+__device__ __forceinline__ void mass_batch(const double (&xh)[Cfg<D, KK>::NK], double* __restrict__ out,
+                                           double* __restrict__ slot, const DevMesh& mesh,
+                                           const double* __restrict__ fi, const double* __restrict__ fo,
+                                           int64_t wave, int lane) {
+  using C = Cfg<D, KK>;
+  using M = MF<double>;
+  const int g = lane >> 4, c = lane & 15;
+  const int64_t off = mesh.F * C::NF;
+  const int64_t e = wave * 16 + c;
+  const bool valid = e < mesh.E;
+  const int64_t ee = valid ? e : 0;
+  const double* Gr = mesh.geo + ee * GEO_STRIDE;
   double y[C::NMT][4];
 #pragma unroll
   for (int mt = 0; mt < C::NMT; ++mt) {
     d4 acc = vzero<d4>();
 #pragma unroll
-    for (int kk = 0; kk < C::NK; ++kk) acc = M::mma(fin[(mt * C::NK + kk) * 64 + lane], xh[kk], acc);
+    for (int kk = 0; kk < C::NK; ++kk) acc = M::mma(fi[(mt * C::NK + kk) * 64 + lane], xh[kk], acc);
 #pragma unroll
     for (int i = 0; i < 4; ++i) y[mt][i] = acc[i];
   }
@@ -487,33 +503,31 @@ __global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, doub
       Gm[a][bb] = s;
     }
   double Gs[D][D];
+  const double sd = 1.0 / fabs(det);
   if (MODE == 0) {
-    const double s = 1.0 / fabs(det);
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int bb = 0; bb < D; ++bb) Gs[a][bb] = Gm[a][bb] * s;
+      for (int bb = 0; bb < D; ++bb) Gs[a][bb] = Gm[a][bb] * sd;
   } else {
     // G^-1 |det| = adj(G)/det(G) |det| = adj(G)/|det|  (det G = det^2)
-    const double s = 1.0 / fabs(det);
     if (D == 2) {
-      Gs[0][0] = Gm[1][1] * s; Gs[1][1] = Gm[0][0] * s;
-      Gs[0][1] = -Gm[0][1] * s; Gs[1][0] = -Gm[1][0] * s;
+      Gs[0][0] = Gm[1][1] * sd; Gs[1][1] = Gm[0][0] * sd;
+      Gs[0][1] = -Gm[0][1] * sd; Gs[1][0] = -Gm[1][0] * sd;
     } else {
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int bb = 0; bb < D; ++bb) {
           const int a1 = (bb + 1) % 3, a2 = (bb + 2) % 3, b1 = (a + 1) % 3, b2 = (a + 2) % 3;
-          Gs[a][bb] = (Gm[a1][b1] * Gm[a2][b2] - Gm[a1][b2] * Gm[a2][b1]) * s;
+          Gs[a][bb] = (Gm[a1][b1] * Gm[a2][b2] - Gm[a1][b2] * Gm[a2][b1]) * sd;
         }
     }
   }
-  double z[C::NMQ];
+  // in place: quads blk*D .. blk*D + D-1 only mix among themselves
 #pragma unroll
-  for (int q = 0; q < C::NMQ; ++q) z[q] = 0.0;
-#pragma unroll
-  for (int blk = 0; blk < C::NPK; ++blk)
+  for (int blk = 0; blk < C::NPK; ++blk) {
+    double t[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       double s = 0;
@@ -522,13 +536,20 @@ __global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, doub
         const int rq = blk * D + bb;
         s += Gs[a][bb] * y[rq / 4][rq % 4];
       }
-      z[blk * D + a] = s;
+      t[a] = s;
     }
+#pragma unroll
+    for (int a = 0; a < D; ++a) y[(blk * D + a) / 4][(blk * D + a) % 4] = t[a];
+  }
+  double sfac[D + 1];
+#pragma unroll
+  for (int f = 0; f <= D; ++f) sfac[f] = MODE == 0 ? Gr[GEO_NFN + f] : 0.5 / Gr[GEO_NFN + f];
+  const double sint = MODE == 0 ? Gr[GEO_SI] : 1.0 / Gr[GEO_SI];
 #pragma unroll
   for (int jt = 0; jt < C::NJT; ++jt) {
     d4 o = vzero<d4>();
 #pragma unroll
-    for (int rq = 0; rq < C::NMQ; ++rq) o = M::mma(fout[(jt * C::NMQ + rq) * 64 + lane], z[rq], o);
+    for (int rq = 0; rq < C::NMQ; ++rq) o = M::mma(fo[(jt * C::NMQ + rq) * 64 + lane], y[rq / 4][rq % 4], o);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int j = 16 * jt + M::row(i, g);
@@ -536,6 +557,69 @@ __global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, doub
         if (j < C::NFL) slot[ee * C::NFL + j] = o[i] * sfac[j / C::NF];
         else out[off + ee * C::NINT + (j - C::NFL)] = o[i] * sint;
       }
+    }
+  }
+}
+
+// one batch per wave
+template <int D, int KK, int MODE>
+__global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, double* __restrict__ out,
+                                              double* __restrict__ slot, DevMesh mesh,
+                                              const double* __restrict__ fin,
+                                              const double* __restrict__ fout,
+                                              const int* __restrict__ flag) {
+  if (flag && *flag) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave * 16 >= mesh.E) return;
+  double xh[Cfg<D, KK>::NK];
+  mass_gather<D, KK, MODE>(x, mesh, wave, lane >> 4, lane & 15, xh);
+  mass_batch<D, KK, MODE>(xh, out, slot, mesh, fin, fout, wave, lane);
+}
+
+// Persistent variant for orders whose two tables fit in LDS: each block
+// copies the tables to LDS once, then its waves walk batches with a grid
+// stride and gather the next batch while the current batch's MFMAs run
+// (table fragments come from LDS, so the in-order vector-memory counter only
+// tracks the gathers).
+template <int D, int KK>
+constexpr int mass_lds_doubles() {
+  using C = Cfg<D, KK>;
+  return (C::NMT * C::NK + C::NJT * C::NMQ) * 64;
+}
+
+template <int D, int KK, int MODE>
+__global__ __launch_bounds__(256) void k_mass_lds(const double* __restrict__ x, double* __restrict__ out,
+                                                  double* __restrict__ slot, DevMesh mesh,
+                                                  const double* __restrict__ fin,
+                                                  const double* __restrict__ fout,
+                                                  const int* __restrict__ flag) {
+  using C = Cfg<D, KK>;
+  extern __shared__ double lds[];
+  if (flag && *flag) return;  // uniform over the launch
+  constexpr int NIN = C::NMT * C::NK * 64;
+  constexpr int NTOT = mass_lds_doubles<D, KK>();
+  for (int i = threadIdx.x; i < NTOT; i += 256) lds[i] = i < NIN ? fin[i] : fout[i - NIN];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int64_t nw = (mesh.E + 15) / 16;
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave >= nw) return;
+  double xh[C::NK];
+  mass_gather<D, KK, MODE>(x, mesh, wave, g, c, xh);
+  for (; wave < nw; wave += stride) {
+    double xn[C::NK];
+    const bool more = wave + stride < nw;
+    if (more) mass_gather<D, KK, MODE>(x, mesh, wave + stride, g, c, xn);
+    // opaque base: keeps the fragment reads inside the loop instead of
+    // hoisting all of them into registers
+    int base = 0;
+    asm volatile("" : "+s"(base));
+    mass_batch<D, KK, MODE>(xh, out, slot, mesh, lds + base, lds + base + NIN, wave, lane);
+    if (more) {
+#pragma unroll
+      for (int kk = 0; kk < C::NK; ++kk) xh[kk] = xn[kk];
     }
   }
 }
@@ -586,13 +670,25 @@ void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* 
                  const double* fin, const double* fout, const int* flag) {
   using C = Cfg<D, KK>;
   const int64_t waves = (mesh.E + 15) / 16;
-  const int64_t blocks = (waves + 3) / 4;
-  if (mode == 0)
-    hipLaunchKernelGGL((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
-                       fout, flag);
-  else
-    hipLaunchKernelGGL((k_mass<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
-                       fout, flag);
+  constexpr size_t lds_bytes = (size_t)mass_lds_doubles<D, KK>() * sizeof(double);
+  if (lds_bytes <= 64 * 1024) {
+    // two resident blocks per CU (the tables take up to 64 KB of LDS each)
+    const int64_t blocks = std::min<int64_t>((waves + 3) / 4, MASS_BLOCKS);
+    if (mode == 0)
+      hipLaunchKernelGGL((k_mass_lds<D, KK, 0>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, slot, mesh,
+                         fin, fout, flag);
+    else
+      hipLaunchKernelGGL((k_mass_lds<D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, slot, mesh,
+                         fin, fout, flag);
+  } else {
+    const int64_t blocks = (waves + 3) / 4;
+    if (mode == 0)
+      hipLaunchKernelGGL((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
+                         fout, flag);
+    else
+      hipLaunchKernelGGL((k_mass<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
+                         fout, flag);
+  }
   (void)sizeof(C);
 }
 

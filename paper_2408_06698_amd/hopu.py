@@ -130,7 +130,7 @@ class Hopu:
         check(L.lib().hopu_interpolate(self.h, int(n1d), _ptr(vf), _ptr(vv), _ptr(u)), self.h)
         return u
 
-    PROF_KINDS = {"elem": 0, "mass": 1, "prec": 2, "modal": 3, "vjp": 4}
+    PROF_KINDS = {"elem": 0, "mass": 1, "prec": 2, "modal": 3, "vjp": 4, "plain": 5}
 
     def profile(self, enable, max_launches=200000):
         check(L.lib().hopu_profile_enable(self.h, 1 if enable else 0, int(max_launches)), self.h)
