@@ -340,14 +340,24 @@ static hopu_status do_apply(hopu_ctx ctx, const double* u, double* r, int terms,
   return HOPU_OK;
 }
 
-static void do_mass(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag, bool in_loop = false) {
+// y = M x (mode 0) or the preconditioner (mode 1).  Without `dot_w` the facet
+// rows are assembled at once; with it, facet rows are assembled together with
+// the partial sums of dot_w . y (PCG inner products).
+static void do_mass(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag, bool in_loop = false,
+                    const double* dot_w = nullptr) {
   prof_begin(ctx, in_loop ? (mode == 0 ? PROF_MASS : PROF_PREC) : PROF_PLAIN);
   DISPATCH(ctx->dim, ctx->k, {
     launch_mass<D, KK>(ctx->stream, mode, x, y, ctx->slot, ctx->dm, mode == 0 ? ctx->mass_in : ctx->prec_in,
                        mode == 0 ? ctx->mass_out : ctx->prec_out, flag);
   });
   prof_end(ctx);
-  DISPATCH(ctx->dim, ctx->k, { launch_assemble<D, KK>(ctx->stream, y, ctx->slot, ctx->dm, flag); });
+  if (dot_w) {
+    DISPATCH(ctx->dim, ctx->k, {
+      launch_asm_dot<D, KK>(ctx->stream, y, ctx->slot, dot_w, ctx->dm, ctx->n_dof, flag, ctx->part, NPART);
+    });
+  } else {
+    DISPATCH(ctx->dim, ctx->k, { launch_assemble<D, KK>(ctx->stream, y, ctx->slot, ctx->dm, flag); });
+  }
 }
 
 static hopu_status check_prec(hopu_ctx ctx, hopu_precision prec) {
@@ -402,12 +412,10 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
     const int chunk = std::min(want, max_it - it);
     for (int c = 0; c < chunk; ++c) {
       prof_idx.push_back(ctx->ev_used);
-      do_mass(ctx, 0, ctx->p, ctx->q, fl, true);
-      vec_dot(s, ctx->p, ctx->q, n, ctx->part, fl);
+      do_mass(ctx, 0, ctx->p, ctx->q, fl, true, ctx->p);
       vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
       vec_axpy2(s, x, ctx->r, ctx->p, ctx->q, n, ctx->sc, fl);
-      do_mass(ctx, 1, ctx->r, ctx->z, fl, true);
-      vec_dot(s, ctx->r, ctx->z, n, ctx->part, fl);
+      do_mass(ctx, 1, ctx->r, ctx->z, fl, true, ctx->r);
       vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_BETA, 0.0, nullptr);
       vec_xpay(s, ctx->p, ctx->z, n, ctx->sc, fl);
     }

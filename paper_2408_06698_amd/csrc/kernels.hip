@@ -152,6 +152,7 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
         Gm[a][bb] = s;
       }
     const double sc = -idet * idet * (det > 0 ? 1.0 : -1.0);
+#pragma unroll 1
     for (int qt = 0; qt < C::NQVT; ++qt) {
       V u[D];
 #pragma unroll
@@ -210,6 +211,7 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
   double diss = 0.0;
   const bool cen = terms & 2, up = terms & 4;
   if (cen || up) {
+#pragma unroll 1
     for (int f = 0; f <= D; ++f) {
       const int fp = (sig >> (4 * f)) & 0xF;
       if (fp == 0xF) continue;  // wall facet for the whole batch: u.n = 0
@@ -269,6 +271,7 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
 #pragma unroll
         for (int jt = 0; jt < C::NFJT; ++jt) c2[a][jt] = vzero<V>();
 
+#pragma unroll 1
       for (int qt = 0; qt < C::NQFT; ++qt) {
         V to[D], tn[D], pj[D];
 #pragma unroll
@@ -638,7 +641,47 @@ __global__ void k_assemble_flag(double* __restrict__ r, const double* __restrict
   r[t] = slot[(int64_t)e0 * NFL + i0 * NF + jj] + slot[(int64_t)e1 * NFL + i1 * NF + jj];
 }
 
+// Facet rows v_F = slot(T) + slot(T') plus the per-block partial of w . v over
+// all rows (interior rows of v were written by the element kernel).
+template <int NF, int NFL>
+__global__ __launch_bounds__(256) void k_asm_dot(double* __restrict__ v, const double* __restrict__ slot,
+                                                 const double* __restrict__ w, DevMesh mesh, int64_t n,
+                                                 const int* __restrict__ flag, double* __restrict__ part) {
+  if (*flag) return;
+  __shared__ double sh[256];
+  const int64_t nf = mesh.F * NF;
+  double s = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
+    double val;
+    if (t < nf) {
+      const int64_t F = t / NF;
+      const int jj = (int)(t - F * NF);
+      const int32_t e0 = mesh.facet_elem[2 * F], e1 = mesh.facet_elem[2 * F + 1];
+      const int i0 = mesh.facet_local[2 * F], i1 = mesh.facet_local[2 * F + 1];
+      val = slot[(int64_t)e0 * NFL + i0 * NF + jj] + slot[(int64_t)e1 * NFL + i1 * NF + jj];
+      v[t] = val;
+    } else {
+      val = v[t];
+    }
+    s += w[t] * val;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 // ------------------------------------------------------------------ launchers
+template <int D, int KK>
+void launch_asm_dot(hipStream_t s, double* v, const double* slot, const double* w, const DevMesh& mesh, int64_t n,
+                    const int* flag, double* part, int nblocks) {
+  using C = Cfg<D, KK>;
+  hipLaunchKernelGGL((k_asm_dot<C::NF, C::NFL>), dim3(nblocks), dim3(256), 0, s, v, slot, w, mesh, n, flag, part);
+}
+
 template <typename T, int D, int KK>
 void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, const T* frag) {
   const int64_t waves = (mesh.E + 15) / 16;
@@ -703,7 +746,9 @@ void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* 
                                           const DevTables<float>&, int, double*);                           \
   template void launch_mass<D, KK>(hipStream_t, int, const double*, double*, double*, const DevMesh&,       \
                                    const double*, const double*, const int*);                               \
-  template void launch_assemble<D, KK>(hipStream_t, double*, const double*, const DevMesh&, const int*);
+  template void launch_assemble<D, KK>(hipStream_t, double*, const double*, const DevMesh&, const int*);      \
+  template void launch_asm_dot<D, KK>(hipStream_t, double*, const double*, const double*, const DevMesh&,     \
+                                      int64_t, const int*, double*, int);
 
 HOPU_INST(2, 1)
 HOPU_INST(2, 2)

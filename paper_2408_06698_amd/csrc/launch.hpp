@@ -17,4 +17,7 @@ void launch_assemble(hipStream_t s, double* r, const double* slot, const DevMesh
 template <typename T, int D, int KK>
 void launch_vjp(hipStream_t s, const T* mu_u, const T* mu_mu, double* out, double* slot, const DevMesh& mesh,
                 const DevTables<T>& tb);
+template <int D, int KK>
+void launch_asm_dot(hipStream_t s, double* v, const double* slot, const double* w, const DevMesh& mesh, int64_t n,
+                    const int* flag, double* part, int nblocks);
 }  // namespace hopu

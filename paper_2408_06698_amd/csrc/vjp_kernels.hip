@@ -83,6 +83,7 @@ __global__ __launch_bounds__(256) void k_vjp(const T* __restrict__ mu_m, const T
         Gm[a][bb] = s;
       }
     const double sc = -idet * idet * (det > 0 ? 1.0 : -1.0);
+#pragma unroll 1
     for (int qt = 0; qt < C::NQVT; ++qt) {
       V u[D], gm[D][D];
 #pragma unroll
@@ -152,6 +153,7 @@ __global__ __launch_bounds__(256) void k_vjp(const T* __restrict__ mu_m, const T
   }
 
   // ---------------- facets
+#pragma unroll 1
   for (int f = 0; f <= D; ++f) {
     const int fp = (sig >> (4 * f)) & 0xF;
     if (fp == 0xF) continue;
@@ -218,6 +220,7 @@ __global__ __launch_bounds__(256) void k_vjp(const T* __restrict__ mu_m, const T
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int jt = 0; jt < C::NFJT; ++jt) c2[a][jt] = vz<V>();
+#pragma unroll 1
     for (int qt = 0; qt < C::NQFT; ++qt) {
       V to[D], tn[D], mo[D], mn[D], pu[D], pm[D];
 #pragma unroll
