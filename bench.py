@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="after the run, copy a 1 GiB device buffer (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -212,6 +214,12 @@ def main():
         out["mixed"] = {"value": ndof * args.steps / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
                         "rel_err_vs_fp64_M_norm": err, "dtype": "fp32-mfma contractions, f64 state/PCG",
                         "speedup_substep": ms64 / ms32, "speedup_apply": apply64 / apply32}
+    if args.copy_calib:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=u0.device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = src.numel() * 8
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
