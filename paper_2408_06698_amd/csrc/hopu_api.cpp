@@ -14,6 +14,7 @@
 #include "host_tables.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
+#include "launch_events.hpp"
 #include "vec.hpp"
 
 using namespace hopu;
@@ -61,14 +62,30 @@ struct hopu_ctx_s {
 
 enum { PROF_ELEM = 0, PROF_MASS = 1, PROF_PREC = 2, PROF_MODAL = 3, PROF_VJP = 4, PROF_PLAIN = 5, PROF_N = 6 };
 
+namespace hopu {
+static thread_local LaunchEvents tl_events;
+static thread_local bool tl_armed = false;
+LaunchEvents* take_launch_events() {
+  if (!tl_armed) return nullptr;
+  tl_armed = false;
+  return &tl_events;
+}
+void arm_launch_events(hipEvent_t start, hipEvent_t stop) {
+  tl_events = LaunchEvents{start, stop};
+  tl_armed = true;
+}
+void disarm_launch_events() { tl_armed = false; }
+}  // namespace hopu
+
+// the next launch through HOPU_LAUNCH records its dispatch into a pair
 static void prof_begin(hopu_ctx ctx, int kind) {
   if (!ctx->prof || 2 * (ctx->ev_used + 1) > ctx->events.size()) return;
-  (void)hipEventRecord(ctx->events[2 * ctx->ev_used], ctx->stream);
+  arm_launch_events(ctx->events[2 * ctx->ev_used], ctx->events[2 * ctx->ev_used + 1]);
   ctx->ev_kind[ctx->ev_used] = kind;
 }
 static void prof_end(hopu_ctx ctx) {
   if (!ctx->prof || 2 * (ctx->ev_used + 1) > ctx->events.size()) return;
-  (void)hipEventRecord(ctx->events[2 * ctx->ev_used + 1], ctx->stream);
+  disarm_launch_events();
   ++ctx->ev_used;
 }
 

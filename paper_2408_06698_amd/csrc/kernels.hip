@@ -3,6 +3,7 @@
 
 #include "kernels.hpp"
 #include "launch.hpp"
+#include "launch_events.hpp"
 
 namespace hopu {
 
@@ -686,7 +687,7 @@ template <typename T, int D, int KK>
 void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, const T* frag) {
   const int64_t waves = (mesh.E + 15) / 16;
   const int64_t blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((k_modal<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, x, m, mesh, frag);
+  HOPU_LAUNCH((k_modal<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, x, m, mesh, frag);
 }
 
 template <typename T, int D, int KK>
@@ -694,7 +695,7 @@ void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMe
                  const DevTables<T>& tb, int terms, double* diss_part) {
   using C = Cfg<D, KK>;
   const int64_t blocks = (mesh.nb + 3) / 4;
-  hipLaunchKernelGGL((k_elem<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, m, r, slot, mesh, tb,
+  HOPU_LAUNCH((k_elem<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, m, r, slot, mesh, tb,
                      terms, diss_part);
   (void)sizeof(C);
 }
@@ -718,18 +719,18 @@ void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* 
     // two resident blocks per CU (the tables take up to 64 KB of LDS each)
     const int64_t blocks = std::min<int64_t>((waves + 3) / 4, MASS_BLOCKS);
     if (mode == 0)
-      hipLaunchKernelGGL((k_mass_lds<D, KK, 0>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, slot, mesh,
+      HOPU_LAUNCH((k_mass_lds<D, KK, 0>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, slot, mesh,
                          fin, fout, flag);
     else
-      hipLaunchKernelGGL((k_mass_lds<D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, slot, mesh,
+      HOPU_LAUNCH((k_mass_lds<D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, slot, mesh,
                          fin, fout, flag);
   } else {
     const int64_t blocks = (waves + 3) / 4;
     if (mode == 0)
-      hipLaunchKernelGGL((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
+      HOPU_LAUNCH((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
                          fout, flag);
     else
-      hipLaunchKernelGGL((k_mass<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
+      HOPU_LAUNCH((k_mass<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
                          fout, flag);
   }
   (void)sizeof(C);

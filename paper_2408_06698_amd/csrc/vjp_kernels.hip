@@ -9,6 +9,7 @@
 // Batches, tables and fragment layouts are those of the forward kernel.
 #include "kernels.hpp"
 #include "launch.hpp"
+#include "launch_events.hpp"
 
 namespace hopu {
 
@@ -386,7 +387,7 @@ template <typename T, int D, int KK>
 void launch_vjp(hipStream_t s, const T* mu_u, const T* mu_mu, double* out, double* slot, const DevMesh& mesh,
                 const DevTables<T>& tb) {
   const int64_t blocks = (mesh.nb + 3) / 4;
-  hipLaunchKernelGGL((k_vjp<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, mu_u, mu_mu, out, slot, mesh, tb);
+  HOPU_LAUNCH((k_vjp<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, mu_u, mu_mu, out, slot, mesh, tb);
 }
 
 #define HOPU_VJP_INST(D, KK)                                                                                  \
