@@ -93,6 +93,26 @@ hopu_status hopu_sizes(hopu_ctx ctx, int64_t* n_dof, int64_t* n_facets,
  * facet.  The pointer is kept and read by later calls. */
 hopu_status hopu_set_upwind(hopu_ctx ctx, int l_global, const int8_t* l_per_facet_dev);
 
+/* Adaptive HOPU order (end of section 3.2).  The jump indicator of a facet
+ * is eta_E = int_E |(I - Pi^l)[[u]]| ds / int_E |<u>| ds with the facet's
+ * current order l; given thresholds eta_0 < ... < eta_k (eta_{k+1} = 1) the
+ * order becomes l = i for eta_i < eta <= eta_{i+1}, -1 (standard upwind) for
+ * eta <= eta_0 and k for eta > 1.  A facet with <u> = 0 gets eta = 0 if its
+ * projected jump is zero, else +inf.
+ * hopu_jump_indicator: eta per interior facet, eta_dev dev double [n_facets].
+ * hopu_set_adaptive: every > 0 enables the adaptive order with host
+ *   thresholds[k+1] and initial order l_initial for every facet (the context
+ *   owns the per-facet order array); hopu_substeps then recomputes the orders
+ *   from the current state before every `every`-th substep (steps 0, every,
+ *   ...).  every <= 0 disables it; hopu_set_upwind also disables it.
+ * hopu_adapt_upwind: recompute the orders from u now. */
+hopu_status hopu_jump_indicator(hopu_ctx ctx, const double* u, double* eta_dev);
+hopu_status hopu_set_adaptive(hopu_ctx ctx, int every, int n_thresholds, const double* thresholds, int l_initial);
+hopu_status hopu_adapt_upwind(hopu_ctx ctx, const double* u);
+/* Copy the context's current per-facet orders (adaptive mode) to l_dev
+ * (dev int8 [n_facets]).  Asynchronous. */
+hopu_status hopu_get_facet_orders(hopu_ctx ctx, int8_t* l_dev);
+
 /* PCG controls for mass solves inside substeps and their adjoints:
  * stop when sqrt(r.z) <= rtol sqrt(b.Pb) (preconditioned residual norm);
  * check_every: iterations between host reads of the convergence flag. */

@@ -378,3 +378,52 @@ def assemble_picard(sp, w, l, terms=TERM_ALL):
 
 def assemble_mass_dense(sp):
     return mass_matrix(sp).toarray()
+
+
+# ------------------------------------------------------ adaptive HOPU order
+def jump_indicator(sp, x, l):
+    """Facet jump indicator of the adaptive HOPU order (end of section 3.2):
+    eta_E = int_E |(I - Pi^l)[[u]]| ds / int_E |<u>| ds (Euclidean norms),
+    evaluated with the facet rule and the facet's current l.  A facet with
+    <u> = 0 everywhere gets eta = 0 if its projected jump is zero, else +inf."""
+    lf_all = sp.facet_l(l)
+    eta = np.empty(sp.topo.n_facets)
+    for fb in _facet_batches(sp):
+        T, T2, phiT, phiT2, nvec, ds = _facet_traces(sp, fb)
+        uT = np.einsum("bqid,bi->bqd", phiT, sp.local(x, T))
+        uT2 = np.einsum("bqid,bi->bqd", phiT2, sp.local(x, T2))
+        jump = uT - uT2
+        P = _projector(sp, lf_all[fb])
+        jp = jump - np.einsum("bqp,bpd->bqd", P, jump)
+        num = np.sum(ds * np.linalg.norm(jp, axis=-1), -1)
+        den = np.sum(ds * np.linalg.norm(0.5 * (uT + uT2), axis=-1), -1)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            e = np.where(den > 0, num / np.where(den > 0, den, 1.0), np.where(num > 0, np.inf, 0.0))
+        eta[fb] = e
+    return eta
+
+
+def adapt_order(eta, thresholds, k):
+    """l_loc from eta and thresholds eta_0 < ... < eta_k (eta_{k+1} = 1):
+    eta_i < eta <= eta_{i+1} gives l = i; eta <= eta_0 gives -1 (standard
+    upwind); eta > 1 gives k."""
+    th = list(thresholds) + [1.0]
+    assert len(th) == k + 2
+    out = np.full(eta.shape, -1, dtype=np.int64)
+    for i in range(k + 1):
+        out[(eta > th[i]) & (eta <= th[i + 1])] = i
+    out[eta > 1.0] = k
+    return out
+
+
+def substeps_adaptive(sp, x0, dt, n_steps, thresholds, every=10, l0=-1):
+    """Substeps with the adaptive order: before every `every`-th step the
+    facet orders are recomputed from the jump indicator of the current state
+    (evaluated with the orders in use, initially l0)."""
+    l = np.full(sp.topo.n_facets, l0, dtype=np.int64)
+    x = x0
+    for s in range(n_steps):
+        if s % every == 0:
+            l = adapt_order(jump_indicator(sp, x, l), thresholds, sp.k)
+        x = substep(sp, x, dt, l)
+    return x, l

@@ -24,6 +24,10 @@ SIGNATURES = {
     "hopu_sizes": (_i, [_p, _p, _p, _p, _p, _p, _p]),
     "hopu_set_upwind": (_i, [_p, _i, _p]),
     "hopu_set_solver": (_i, [_p, _d, _i, _i]),
+    "hopu_jump_indicator": (_i, [_p, _p, _p]),
+    "hopu_set_adaptive": (_i, [_p, _i, _i, _p, _i]),
+    "hopu_adapt_upwind": (_i, [_p, _p]),
+    "hopu_get_facet_orders": (_i, [_p, _p]),
     "hopu_convection_apply": (_i, [_p, _p, _p, _i, _i]),
     "hopu_mass_apply": (_i, [_p, _p, _p]),
     "hopu_mass_solve": (_i, [_p, _p, _p, _d, _i, _p]),

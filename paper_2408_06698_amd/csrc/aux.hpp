@@ -17,4 +17,6 @@ void launch_interpolate(hipStream_t s, int D, int nqs, int nf, const double* vf,
                         const double* qm, const DevMesh& mesh, double* x);
 void launch_eval(hipStream_t s, int D, int n, int nf, int nint, int np, const double* x, const double* phi,
                  const DevMesh& mesh, double* out);
+void launch_adapt(hipStream_t s, const double* eta_nd, int64_t F, const double* thr, int k, int8_t* lfac,
+                  double* eta_out);
 }  // namespace hopu

@@ -192,7 +192,40 @@ __global__ void k_eval(int D, int n, int nf, int nint, int np, const double* __r
   }
 }
 
+// Adaptive HOPU order: eta = num/den per facet and l from the thresholds
+// eta_0 < ... < eta_k (eta_{k+1} = 1): eta_i < eta <= eta_{i+1} -> i,
+// eta <= eta_0 -> -1, eta > 1 -> k.  den = 0 gives eta = 0 (num = 0) or +inf.
+struct Thresholds {
+  double t[8];
+  int k;
+};
+__global__ void k_adapt(const double* __restrict__ eta_nd, int64_t F, Thresholds th, int8_t* __restrict__ lfac,
+                        double* __restrict__ eta_out) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  const double num = eta_nd[2 * f], den = eta_nd[2 * f + 1];
+  const double eta = den > 0 ? num / den : (num > 0 ? INFINITY : 0.0);
+  if (eta_out) eta_out[f] = eta;
+  if (!lfac) return;
+  int l = -1;
+  for (int i = 0; i <= th.k; ++i) {
+    const double hi = i < th.k ? th.t[i + 1] : 1.0;
+    if (eta > th.t[i] && eta <= hi) l = i;
+  }
+  if (eta > 1.0) l = th.k;
+  lfac[f] = (int8_t)l;
+}
+
 // ------------------------------------------------------------------ launchers
+void launch_adapt(hipStream_t s, const double* eta_nd, int64_t F, const double* thr, int k, int8_t* lfac,
+                  double* eta_out) {
+  Thresholds th;
+  for (int i = 0; i < 8; ++i) th.t[i] = i <= k && thr ? thr[i] : 0.0;
+  th.k = k;
+  if (F > 0)
+    hipLaunchKernelGGL(k_adapt, dim3((unsigned)((F + 255) / 256)), dim3(256), 0, s, eta_nd, F, th, lfac, eta_out);
+}
+
 template <int D, int KK>
 void launch_energy(hipStream_t s, const double* m, const DevMesh& mesh, double* part) {
   hipLaunchKernelGGL((k_energy<D, KK>), dim3(AUX_NPART), dim3(256), 0, s, m, mesh, part);

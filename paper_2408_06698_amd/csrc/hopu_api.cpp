@@ -54,6 +54,11 @@ struct hopu_ctx_s {
   std::string err;
   // per-kernel timing with HIP events (hopu_profile_*)
   int last_its = 0;
+  // adaptive HOPU order
+  int8_t* own_lfac = nullptr;   // [F] facet orders owned by the context
+  double* eta_nd = nullptr;     // [F][2] jump-indicator numerator/denominator
+  int adapt_every = 0;
+  double thr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   bool prof = false;
   std::vector<hipEvent_t> events;       // pool, pairs
   std::vector<int> ev_kind;             // kernel id per used pair
@@ -265,6 +270,8 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(dev_alloc(ctx, &ctx->rc, (size_t)n));
     for (int i = 0; i < 3; ++i) TRY(dev_alloc(ctx, &ctx->wh[i], (size_t)n));
     TRY(dev_alloc(ctx, &ctx->sc, SC_N));
+    TRY(dev_alloc(ctx, &ctx->own_lfac, (size_t)ctx->mesh.F));
+    TRY(dev_alloc(ctx, &ctx->eta_nd, (size_t)(2 * ctx->mesh.F)));
     TRY(dev_alloc(ctx, &ctx->flag, 4));
     void* hp = nullptr;
     if (hipHostMalloc(&hp, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) { st = HOPU_ENOMEM; ctx->err = "hipHostMalloc failed"; goto fail_create; }
@@ -315,6 +322,7 @@ extern "C" hopu_status hopu_sizes(hopu_ctx ctx, int64_t* n_dof, int64_t* n_facet
 extern "C" hopu_status hopu_set_upwind(hopu_ctx ctx, int l_global, const int8_t* l_per_facet_dev) {
   if (!ctx) return HOPU_EINVAL;
   if (l_global < -1 || l_global > ctx->k) return fail(ctx, HOPU_EINVAL, "l must be in -1..k");
+  ctx->adapt_every = 0;  // an explicit choice replaces the adaptive order
   ctx->lglob = l_global;
   ctx->lfac = l_per_facet_dev;
   refresh_dm(ctx);
@@ -344,13 +352,13 @@ static hopu_status do_modal(hopu_ctx ctx, const double* u, hopu_precision prec, 
 }
 
 static hopu_status do_apply(hopu_ctx ctx, const double* u, double* r, int terms, hopu_precision prec,
-                            double* diss_part) {
+                            double* diss_part, double* eta_nd = nullptr) {
   hopu_status st = do_modal(ctx, u, prec);
   if (st) return st;
   prof_begin(ctx, PROF_ELEM);
   DISPATCH(ctx->dim, ctx->k, {
-    if (prec == HOPU_FP64) launch_elem<double, D, KK>(ctx->stream, ctx->m64, r, ctx->slot, ctx->dm, ctx->tb64, terms, diss_part);
-    else launch_elem<float, D, KK>(ctx->stream, ctx->m32, r, ctx->slot, ctx->dm, ctx->tb32, terms, diss_part);
+    if (prec == HOPU_FP64) launch_elem<double, D, KK>(ctx->stream, ctx->m64, r, ctx->slot, ctx->dm, ctx->tb64, terms, diss_part, eta_nd);
+    else launch_elem<float, D, KK>(ctx->stream, ctx->m32, r, ctx->slot, ctx->dm, ctx->tb32, terms, diss_part, eta_nd);
   });
   prof_end(ctx);
   DISPATCH(ctx->dim, ctx->k, { launch_assemble<D, KK>(ctx->stream, r, ctx->slot, ctx->dm, nullptr); });
@@ -504,6 +512,73 @@ extern "C" hopu_status hopu_diagnostics(hopu_ctx ctx, const double* u, double* e
   return HOPU_OK;
 }
 
+// ------------------------------------------------------------------ adaptive order
+// jump indicator of u with the facet orders in use (FP64 facet pass)
+static hopu_status eta_pass(hopu_ctx ctx, const double* u) {
+  refresh_dm(ctx);
+  return do_apply(ctx, u, ctx->rc, HOPU_TERM_ALL, HOPU_FP64, nullptr, ctx->eta_nd);
+}
+
+extern "C" hopu_status hopu_jump_indicator(hopu_ctx ctx, const double* u, double* eta_dev) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!u || !eta_dev) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  hopu_status st = eta_pass(ctx, u);
+  if (st) return st;
+  launch_adapt(ctx->stream, ctx->eta_nd, ctx->mesh.F, nullptr, ctx->k, nullptr, eta_dev);
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_set_adaptive(hopu_ctx ctx, int every, int n_thresholds, const double* thresholds,
+                                         int l_initial) {
+  if (!ctx) return HOPU_EINVAL;
+  if (every <= 0) {
+    ctx->adapt_every = 0;
+    ctx->lfac = nullptr;
+    refresh_dm(ctx);
+    return HOPU_OK;
+  }
+  if (n_thresholds != ctx->k + 1 || !thresholds) return fail(ctx, HOPU_EINVAL, "need k+1 thresholds eta_0..eta_k");
+  for (int i = 0; i <= ctx->k; ++i) {
+    const double lo = i ? thresholds[i - 1] : 0.0;
+    if (!(thresholds[i] > lo) || !(thresholds[i] < 1.0))
+      return fail(ctx, HOPU_EINVAL, "thresholds must satisfy 0 < eta_0 < ... < eta_k < 1");
+  }
+  if (l_initial < -1 || l_initial > ctx->k) return fail(ctx, HOPU_EINVAL, "l_initial must be in -1..k");
+  for (int i = 0; i <= ctx->k; ++i) ctx->thr[i] = thresholds[i];
+  ctx->adapt_every = every;
+  HCHECK(hipMemsetAsync(ctx->own_lfac, (int)(uint8_t)(int8_t)l_initial, ctx->mesh.F, ctx->stream));
+  ctx->lfac = ctx->own_lfac;
+  refresh_dm(ctx);
+  return HOPU_OK;
+}
+
+static hopu_status adapt_now(hopu_ctx ctx, const double* u) {
+  hopu_status st = eta_pass(ctx, u);
+  if (st) return st;
+  launch_adapt(ctx->stream, ctx->eta_nd, ctx->mesh.F, ctx->thr, ctx->k, ctx->own_lfac, nullptr);
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_get_facet_orders(hopu_ctx ctx, int8_t* l_dev) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!l_dev) return fail(ctx, HOPU_EINVAL, "NULL output");
+  if (ctx->adapt_every <= 0) return fail(ctx, HOPU_EINVAL, "adaptive order not enabled (hopu_set_adaptive)");
+  if (ctx->mesh.F > 0)
+    HCHECK(hipMemcpyAsync(l_dev, ctx->own_lfac, ctx->mesh.F, hipMemcpyDeviceToDevice, ctx->stream));
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_adapt_upwind(hopu_ctx ctx, const double* u) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!u) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  if (ctx->adapt_every <= 0) return fail(ctx, HOPU_EINVAL, "adaptive order not enabled (hopu_set_adaptive)");
+  hopu_status st = adapt_now(ctx, u);
+  if (st) return st;
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
+}
+
 extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_steps, hopu_precision prec,
                                      double* diag_dev) {
   if (!ctx) return HOPU_EINVAL;
@@ -531,6 +606,10 @@ extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_s
       if (st_i == 0) HCHECK(hipMemsetAsync(row + 3, 0, 2 * sizeof(double), s));
     }
     if (last) break;
+    if (ctx->adapt_every > 0 && st_i % ctx->adapt_every == 0) {
+      hopu_status sa = adapt_now(ctx, u);
+      if (sa) return sa;
+    }
     hopu_status st = do_apply(ctx, u, ctx->rc, HOPU_TERM_ALL, prec, nullptr);
     if (st) return st;
     double* w = wh[2];

@@ -107,10 +107,13 @@ template <typename T, int D, int KK>
 __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* __restrict__ r,
                                               double* __restrict__ rslot, DevMesh mesh,
                                               DevTables<T> tb, int terms,
-                                              double* __restrict__ diss_part) {
+                                              double* __restrict__ diss_part, double* __restrict__ eta_nd) {
   using C = Cfg<D, KK>;
   using M = MF<T>;
   using V = typename M::V;
+  // the jump indicator of the adaptive order is always evaluated in FP64;
+  // the FP32 kernel carries no code for it
+  constexpr bool ETA = sizeof(T) == sizeof(double);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int64_t nwave_blocks = (mesh.nb + 3) / 4;
   const int64_t blk = xcd_remap(blockIdx.x, nwave_blocks);
@@ -271,6 +274,7 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int jt = 0; jt < C::NFJT; ++jt) c2[a][jt] = vzero<V>();
+      double eta_num = 0.0, eta_den = 0.0;  // jump indicator of the adaptive order
 
 #pragma unroll 1
       for (int qt = 0; qt < C::NQFT; ++qt) {
@@ -323,6 +327,13 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
             jj2 += jp[a] * jp[a];
           }
           if (up && valid) diss += 0.5 * wq * nfn * hu * jj2;
+          if (ETA && eta_nd) {
+            double aa = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) aa += avg[a] * avg[a];
+            eta_num += wq * nfn * sqrt(jj2);
+            eta_den += wq * nfn * sqrt(aa);
+          }
           const double sh = wq * nfn * idet;
 #pragma unroll
           for (int a = 0; a < D; ++a) {
@@ -360,6 +371,19 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
 #pragma unroll
               for (int a = 0; a < D; ++a) c2[a][jt] = M::mma(ap, aw[a][i], c2[a][jt]);
             }
+        }
+      }
+      if (ETA && eta_nd) {
+        // sum over the four lane groups holding this element's points; the
+        // lower element id of the facet writes
+        eta_num += __shfl_xor(eta_num, 16, 64);
+        eta_num += __shfl_xor(eta_num, 32, 64);
+        eta_den += __shfl_xor(eta_den, 16, 64);
+        eta_den += __shfl_xor(eta_den, 32, 64);
+        if (valid && g == 0 && en > (int32_t)ee) {
+          const int64_t F = mesh.fid[ee * (D + 1) + f];
+          eta_nd[2 * F] = eta_num;
+          eta_nd[2 * F + 1] = eta_den;
         }
       }
       if (up) {
@@ -692,11 +716,11 @@ void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, con
 
 template <typename T, int D, int KK>
 void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMesh& mesh,
-                 const DevTables<T>& tb, int terms, double* diss_part) {
+                 const DevTables<T>& tb, int terms, double* diss_part, double* eta_nd) {
   using C = Cfg<D, KK>;
   const int64_t blocks = (mesh.nb + 3) / 4;
   HOPU_LAUNCH((k_elem<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, m, r, slot, mesh, tb,
-                     terms, diss_part);
+                     terms, diss_part, eta_nd);
   (void)sizeof(C);
 }
 
@@ -742,9 +766,9 @@ void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* 
   template void launch_modal<float, D, KK>(hipStream_t, const double*, float*, const DevMesh&,              \
                                            const float*);                                                   \
   template void launch_elem<double, D, KK>(hipStream_t, const double*, double*, double*, const DevMesh&,    \
-                                           const DevTables<double>&, int, double*);                         \
+                                           const DevTables<double>&, int, double*, double*);                \
   template void launch_elem<float, D, KK>(hipStream_t, const float*, double*, double*, const DevMesh&,      \
-                                          const DevTables<float>&, int, double*);                           \
+                                          const DevTables<float>&, int, double*, double*);                  \
   template void launch_mass<D, KK>(hipStream_t, int, const double*, double*, double*, const DevMesh&,       \
                                    const double*, const double*, const int*);                               \
   template void launch_assemble<D, KK>(hipStream_t, double*, const double*, const DevMesh&, const int*);      \

@@ -8,7 +8,7 @@ template <typename T, int D, int KK>
 void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, const T* frag);
 template <typename T, int D, int KK>
 void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMesh& mesh,
-                 const DevTables<T>& tb, int terms, double* diss_part);
+                 const DevTables<T>& tb, int terms, double* diss_part, double* eta_nd);
 template <int D, int KK>
 void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* slot, const DevMesh& mesh,
                  const double* fin, const double* fout, const int* flag);

@@ -64,6 +64,28 @@ class Hopu:
         self._lfac = l_per_facet
         check(L.lib().hopu_set_upwind(self.h, int(l), _ptr(l_per_facet)), self.h)
 
+    def jump_indicator(self, u):
+        eta = torch.empty(self.n_facets, dtype=torch.float64, device=self.device)
+        check(L.lib().hopu_jump_indicator(self.h, _ptr(_dev(u)), _ptr(eta)), self.h)
+        return eta
+
+    def set_adaptive(self, every, thresholds=None, l_initial=-1):
+        thr = None
+        if thresholds is not None:
+            thr = np.ascontiguousarray(thresholds, dtype=np.float64)
+        check(L.lib().hopu_set_adaptive(self.h, int(every), 0 if thr is None else thr.size,
+                                        None if thr is None else thr.ctypes.data_as(C.c_void_p),
+                                        int(l_initial)), self.h)
+
+    def adapt_upwind(self, u):
+        check(L.lib().hopu_adapt_upwind(self.h, _ptr(_dev(u))), self.h)
+
+    def facet_orders(self):
+        """The context's current per-facet orders (adaptive mode), int8."""
+        out = torch.empty(self.n_facets, dtype=torch.int8, device=self.device)
+        check(L.lib().hopu_get_facet_orders(self.h, _ptr(out)), self.h)
+        return out
+
     def set_solver(self, rtol=1e-13, max_it=500, check_every=4):
         check(L.lib().hopu_set_solver(self.h, float(rtol), int(max_it), int(check_every)), self.h)
 

@@ -76,12 +76,15 @@ def test_apply_two_elements(dim, k):
         assert np.abs(r - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-def test_apply_is_deterministic():
-    mesh, sp, x, c = case(2, (4, 3, 3), 3, noise=1e-3)
-    h = gpu_space(mesh, 3)
+@pytest.mark.parametrize("cfg,n,k,prec", [(2, (4, 3, 3), 3, 0), (3, (3, 3, 4), 5, 1), (3, (3, 3, 4), 5, 0)])
+def test_apply_is_deterministic(cfg, n, k, prec):
+    """Repeated applies are bitwise equal (no atomics, fixed facet order);
+    includes the register-heavy k = 5 kernels."""
+    mesh, sp, x, c = case(cfg, n, k, noise=1e-3)
+    h = gpu_space(mesh, k)
     u = dev(x)
-    a = host(h.apply(u))
-    b = host(h.apply(u))
+    a = host(h.apply(u, prec=prec))
+    b = host(h.apply(u, prec=prec))
     assert np.array_equal(a, b)
 
 

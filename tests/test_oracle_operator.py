@@ -261,3 +261,25 @@ def test_chain_adjoint_fd():
         dlt *= m_norm(sp, x0) / m_norm(sp, dlt)
         fd = (loss(x0 + h * dlt) - loss(x0 - h * dlt)) / (2 * h)
         assert abs(fd - lam0 @ dlt) <= 1e-7 * abs(fd)
+
+
+# ------------------------------------------------------ adaptive order (NEXT f1)
+def test_jump_indicator_properties(periodic2d):
+    """eta vanishes for fields without jumps, is scale invariant, and with
+    l = k the projected jump is zero."""
+    sp, f = periodic2d
+    c = sp.interpolate(fields.constant_field([0.4, -0.2]))
+    assert np.abs(O.jump_indicator(sp, c, -1)).max() < 1e-12
+    x = sp.interpolate(f, nq1d=10) + 1e-2 * np.random.default_rng(3).standard_normal(sp.n_dof)
+    e1 = O.jump_indicator(sp, x, -1)
+    assert np.allclose(O.jump_indicator(sp, 3.7 * x, -1), e1, rtol=1e-13)
+    assert np.abs(O.jump_indicator(sp, x, sp.k)).max() < 1e-12 * e1.max()
+
+
+def test_adapt_order_intervals():
+    """The threshold rule of section 3.2 with the k = 3 thresholds
+    {0.1, 0.2, 0.3, 0.4}: eta_i < eta <= eta_{i+1} -> i, below eta_0 -> -1."""
+    th = [0.1, 0.2, 0.3, 0.4]
+    eta = np.array([0.0, 0.05, 0.1, 0.1000001, 0.2, 0.25, 0.3, 0.35, 0.4, 0.7, 1.0, 1.5, np.inf])
+    want = np.array([-1, -1, -1, 0, 0, 1, 1, 2, 2, 3, 3, 3, 3])
+    assert np.array_equal(O.adapt_order(eta, th, 3), want)
