@@ -95,6 +95,52 @@ __global__ __launch_bounds__(256) void k_modal(const double* __restrict__ x, T* 
   }
 }
 
+// Residual accumulators of the element kernel.  FP64: the MFMA accumulators
+// themselves.  FP32: FP32 MFMA accumulation inside one tile (a quadrature
+// tile or one facet's test), added into FP64 across tiles.
+template <typename T, int D, int NAT> struct ElemAcc;
+template <int D, int NAT> struct ElemAcc<double, D, NAT> {
+  d4 v[D][NAT];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int at = 0; at < NAT; ++at) v[a][at] = vzero<d4>();
+  }
+  __device__ __forceinline__ void begin() {}
+  __device__ __forceinline__ d4& tile(int a, int at) { return v[a][at]; }
+  __device__ __forceinline__ void end() {}
+  __device__ __forceinline__ double get(int a, int at, int i) const { return v[a][at][i]; }
+};
+template <int D, int NAT> struct ElemAcc<float, D, NAT> {
+  double v[D][NAT][4];
+  f4 t[D][NAT];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int at = 0; at < NAT; ++at)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[a][at][i] = 0.0;
+  }
+  __device__ __forceinline__ void begin() {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int at = 0; at < NAT; ++at) t[a][at] = vzero<f4>();
+  }
+  __device__ __forceinline__ f4& tile(int a, int at) { return t[a][at]; }
+  __device__ __forceinline__ void end() {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int at = 0; at < NAT; ++at)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[a][at][i] += (double)t[a][at][i];
+  }
+  __device__ __forceinline__ double get(int a, int at, int i) const { return v[a][at][i]; }
+};
+
 // ------------------------------------------------------------------ element
 // Fused convection residual of a batch of 16 elements:
 //   volume  - int (u x u) : grad phi, in reference form
@@ -135,13 +181,8 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
 #pragma unroll
     for (int kk = 0; kk < C::NPK; ++kk) mB[a][kk] = m[ee * C::NM + kk * 4 * D + 4 * a + g];
 
-  double acc[D][C::NAT][4];
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int at = 0; at < C::NAT; ++at)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) acc[a][at][i] = 0.0;
+  ElemAcc<T, D, C::NAT> acc;
+  acc.init();
 
   // ---------------- volume term
   if (terms & 1) {
@@ -167,31 +208,23 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
 #pragma unroll
         for (int a = 0; a < D; ++a) u[a] = M::mma(av, mB[a][kk], u[a]);
       }
-      T F[D][D][4];
+      // flux F_ab = w sgn/det^2 (G u^)_a u^_b formed per MFMA operand
+      double uh[D][4], gu[D][4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int q = 16 * qt + M::row(i, g);
         const double wq = q < C::NQV ? tb.wv[q] : 0.0;
-        double uh[D], gu[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) uh[a] = (double)u[a][i];
+        for (int a = 0; a < D; ++a) uh[a][i] = (double)u[a][i];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
           double s = 0;
 #pragma unroll
-          for (int bb = 0; bb < D; ++bb) s += Gm[a][bb] * uh[bb];
-          gu[a] = s * wq * sc;
+          for (int bb = 0; bb < D; ++bb) s += Gm[a][bb] * (double)u[bb][i];
+          gu[a][i] = s * wq * sc;
         }
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-          for (int bb = 0; bb < D; ++bb) F[a][bb][i] = (T)(gu[a] * uh[bb]);
       }
-      V t[D][C::NAT];
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int at = 0; at < C::NAT; ++at) t[a][at] = vzero<V>();
+      acc.begin();
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -200,14 +233,9 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
           for (int at = 0; at < C::NAT; ++at) {
             const T av = tb.vol_dVT[(((qt * 4 + i) * D + bb) * C::NAT + at) * 64 + lane];
 #pragma unroll
-            for (int a = 0; a < D; ++a) t[a][at] = M::mma(av, F[a][bb][i], t[a][at]);
+            for (int a = 0; a < D; ++a) acc.tile(a, at) = M::mma(av, (T)(gu[a][i] * uh[bb][i]), acc.tile(a, at));
           }
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int at = 0; at < C::NAT; ++at)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) acc[a][at][i] += (double)t[a][at][i];
+      acc.end();
     }
   }
 
@@ -343,25 +371,16 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
             h[a][i] = (T)(s * sh);
           }
         }
-        V t[D][C::NAT];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-          for (int at = 0; at < C::NAT; ++at) t[a][at] = vzero<V>();
+        acc.begin();
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int at = 0; at < C::NAT; ++at) {
             const T av = tb.fac_TrT[(((f * C::NQFT + qt) * 4 + i) * C::NAT + at) * 64 + lane];
 #pragma unroll
-            for (int a = 0; a < D; ++a) t[a][at] = M::mma(av, h[a][i], t[a][at]);
+            for (int a = 0; a < D; ++a) acc.tile(a, at) = M::mma(av, h[a][i], acc.tile(a, at));
           }
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-          for (int at = 0; at < C::NAT; ++at)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[a][at][i] += (double)t[a][at][i];
+        acc.end();
         if (up) {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
@@ -403,25 +422,16 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
               cc[a][jt][i] = keep ? (T)(-s * nfn * idet) : (T)0;
             }
           }
-        V t[D][C::NAT];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-          for (int at = 0; at < C::NAT; ++at) t[a][at] = vzero<V>();
+        acc.begin();
 #pragma unroll
         for (int jk = 0; jk < C::NFK; ++jk)
 #pragma unroll
           for (int at = 0; at < C::NAT; ++at) {
             const T av = tb.fac_KT[((f * C::NAT + at) * C::NFK + jk) * 64 + lane];
 #pragma unroll
-            for (int a = 0; a < D; ++a) t[a][at] = M::mma(av, cc[a][jk / 4][jk % 4], t[a][at]);
+            for (int a = 0; a < D; ++a) acc.tile(a, at) = M::mma(av, cc[a][jk / 4][jk % 4], acc.tile(a, at));
           }
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-          for (int at = 0; at < C::NAT; ++at)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[a][at][i] += (double)t[a][at][i];
+        acc.end();
       }
     }
   }
@@ -437,7 +447,7 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
       for (int at = 0; at < C::NAT; ++at)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          o = M::mma(tb.dual[((((jt * D + a) * C::NAT + at) * 4) + i) * 64 + lane], (T)acc[a][at][i], o);
+          o = M::mma(tb.dual[((((jt * D + a) * C::NAT + at) * 4) + i) * 64 + lane], (T)acc.get(a, at, i), o);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int j = 16 * jt + M::row(i, g);
