@@ -217,12 +217,19 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(upload(ctx, &dnbr, ctx->mesh.nbr));
     TRY(upload(ctx, &dfe, ctx->mesh.facet_elem));
     TRY(upload(ctx, &dfl, ctx->mesh.facet_local));
+    const int8_t* dfs;
+    {
+      std::vector<int8_t> fside((size_t)n_elems * (ctx->dim + 1), 0);
+      for (int64_t F = 0; F < ctx->mesh.F; ++F)
+        fside[(size_t)ctx->mesh.facet_elem[2 * F + 1] * (ctx->dim + 1) + ctx->mesh.facet_local[2 * F + 1]] = 1;
+      TRY(upload(ctx, &dfs, fside));
+    }
     TRY(upload(ctx, &dbe, ctx->bat.elem));
     TRY(upload(ctx, &dbs, ctx->bat.sig));
     const double* dxyz;
     TRY(upload(ctx, &dxyz, ctx->mesh.xyz));
     ctx->xyz = (double*)dxyz;
-    ctx->dm = DevMesh{dgeo, dfid, dnbr, dfe, dfl, dbe, dbs, nullptr, n_elems, ctx->mesh.F, ctx->bat.nb, ctx->lglob};
+    ctx->dm = DevMesh{dgeo, dfid, dnbr, dfe, dfl, dfs, dbe, dbs, nullptr, n_elems, ctx->mesh.F, ctx->bat.nb, ctx->lglob};
     // tables
     const double *wv, *wf;
     const int* pdeg;
@@ -365,24 +372,25 @@ static hopu_status do_apply(hopu_ctx ctx, const double* u, double* r, int terms,
   return HOPU_OK;
 }
 
-// y = M x (mode 0) or the preconditioner (mode 1).  Without `dot_w` the facet
-// rows are assembled at once; with it, facet rows are assembled together with
-// the partial sums of dot_w . y (PCG inner products).
-static void do_mass(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag, bool in_loop = false,
-                    const double* dot_w = nullptr) {
+// y = M x (mode 0) or the preconditioner (mode 1), unassembled: interior rows
+// of y plus the facet-side contributions in ctx->slot (the facet rows of y
+// are left untouched).  With `dot`, the per-block partials of x . y go to
+// ctx->part; returns their number.
+static int mass_raw(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag, bool in_loop, bool dot) {
+  int np = 0;
   prof_begin(ctx, in_loop ? (mode == 0 ? PROF_MASS : PROF_PREC) : PROF_PLAIN);
   DISPATCH(ctx->dim, ctx->k, {
-    launch_mass<D, KK>(ctx->stream, mode, x, y, ctx->slot, ctx->dm, mode == 0 ? ctx->mass_in : ctx->prec_in,
-                       mode == 0 ? ctx->mass_out : ctx->prec_out, flag);
+    np = launch_mass<D, KK>(ctx->stream, mode, x, y, ctx->slot, ctx->dm, mode == 0 ? ctx->mass_in : ctx->prec_in,
+                            mode == 0 ? ctx->mass_out : ctx->prec_out, flag, dot ? ctx->part : nullptr);
   });
   prof_end(ctx);
-  if (dot_w) {
-    DISPATCH(ctx->dim, ctx->k, {
-      launch_asm_dot<D, KK>(ctx->stream, y, ctx->slot, dot_w, ctx->dm, ctx->n_dof, flag, ctx->part, NPART);
-    });
-  } else {
-    DISPATCH(ctx->dim, ctx->k, { launch_assemble<D, KK>(ctx->stream, y, ctx->slot, ctx->dm, flag); });
-  }
+  return np;
+}
+
+// y = M x (mode 0) or the preconditioner (mode 1), assembled
+static void do_mass(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag) {
+  mass_raw(ctx, mode, x, y, flag, false, false);
+  launch_fs_assemble(ctx->stream, y, ctx->slot, ctx->mesh.F * ctx->sz.nf, flag);
 }
 
 static hopu_status check_prec(hopu_ctx ctx, hopu_precision prec) {
@@ -415,34 +423,36 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
   const int64_t n = ctx->n_dof;
   hipStream_t s = ctx->stream;
   int* fl = ctx->flag;
+  const int64_t nfl = ctx->mesh.F * ctx->sz.nf;
   HCHECK(hipMemsetAsync(fl, 0, 4 * sizeof(int), s));
   // tolerance from b.Pb
-  do_mass(ctx, 1, b, ctx->z, nullptr);
-  vec_dot(s, b, ctx->z, n, ctx->part, nullptr);
-  vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_SET_TOL, rtol, nullptr);
-  // r = b - M x; z = P r; p = z
-  do_mass(ctx, 0, x, ctx->q, nullptr);
-  vec_sub(s, ctx->r, b, ctx->q, n);
-  do_mass(ctx, 1, ctx->r, ctx->z, nullptr);
-  vec_dot(s, ctx->r, ctx->z, n, ctx->part, nullptr);
-  vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_SET_RZ, 0.0, nullptr);
-  HCHECK(hipMemcpyAsync(ctx->p, ctx->z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  int np = mass_raw(ctx, 1, b, ctx->z, nullptr, false, true);
+  vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_SET_TOL, rtol, nullptr);
+  // r = b - M x; z = P r (assembled straight into p); p = z
+  mass_raw(ctx, 0, x, ctx->q, nullptr, false, false);
+  vec_sub_fs(s, ctx->r, b, ctx->q, ctx->slot, nfl, n);
+  np = mass_raw(ctx, 1, ctx->r, ctx->p, nullptr, false, true);
+  launch_fs_assemble(s, ctx->p, ctx->slot, nfl, nullptr);
+  vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_SET_RZ, 0.0, nullptr);
   int it = 0;
   bool conv = false;
   // the first chunk runs as many iterations as the previous solve needed
-  // (warm-started solves converge in similar counts), then check_every
+  // (warm-started solves converge in similar counts), then check_every.
+  // q = M p and z = P r stay unassembled: their facet rows are summed from
+  // the facet-side buffer by the update that reads them, and p . q, r . z
+  // come from the mass kernels' element-local partials.
   std::vector<size_t> prof_idx;  // profile pairs of each launched iteration
   while (it < max_it) {
     const int want = (it == 0 && ctx->last_its > 1) ? ctx->last_its - 1 : ctx->check_every;
     const int chunk = std::min(want, max_it - it);
     for (int c = 0; c < chunk; ++c) {
       prof_idx.push_back(ctx->ev_used);
-      do_mass(ctx, 0, ctx->p, ctx->q, fl, true, ctx->p);
-      vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
-      vec_axpy2(s, x, ctx->r, ctx->p, ctx->q, n, ctx->sc, fl);
-      do_mass(ctx, 1, ctx->r, ctx->z, fl, true, ctx->r);
-      vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_BETA, 0.0, nullptr);
-      vec_xpay(s, ctx->p, ctx->z, n, ctx->sc, fl);
+      np = mass_raw(ctx, 0, ctx->p, ctx->q, fl, true, true);
+      vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
+      vec_axpy2(s, x, ctx->r, ctx->p, ctx->q, ctx->slot, nfl, n, ctx->sc, fl);
+      np = mass_raw(ctx, 1, ctx->r, ctx->z, fl, true, true);
+      vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_BETA, 0.0, nullptr);
+      vec_xpay(s, ctx->p, ctx->z, ctx->slot, nfl, n, ctx->sc, fl);
     }
     it += chunk;
     HCHECK(hipMemcpyAsync(ctx->hflag, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));

@@ -467,7 +467,11 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
 // ------------------------------------------------------------------ mass
 // MODE 0: y = M_T x_T  = S Dinv^T (G (x) I) Dinv S x_T / |det J|
 // MODE 1: y = (M_T^-1)(1/2 facet rows)  = 1/2 S^-1 D (G^-1 (x) I) D^T S^-1 (1/2) x_T |det J|
-// Facet rows go to slots (summed by k_assemble), interior rows to out.
+// Interior rows go to out.  Facet rows go to the facet-side buffer fs, laid
+// out [side][F][NF]: each interior facet receives exactly one contribution
+// per side, and the assembled row is fs[0][F] + fs[1][F], added by whichever
+// kernel consumes it.  Since y = sum_T R_T y_T, the inner product x . y is
+// the sum over elements of x_T . y_T, which each lane accumulates locally.
 // Each wave walks batches of 16 elements with a grid stride and gathers the
 // next batch while the MFMAs of the current one run.
 template <int D, int KK, int MODE>
@@ -504,11 +508,12 @@ __device__ __forceinline__ void mass_gather(const double* __restrict__ x, const 
 }
 
 // one batch: xh gathered, outputs written
+// Returns this lane's share of x_T . y_T over the batch.
 template <int D, int KK, int MODE>
-__device__ __forceinline__ void mass_batch(const double (&xh)[Cfg<D, KK>::NK], double* __restrict__ out,
-                                           double* __restrict__ slot, const DevMesh& mesh,
-                                           const double* __restrict__ fi, const double* __restrict__ fo,
-                                           int64_t wave, int lane) {
+__device__ __forceinline__ double mass_batch(const double (&xh)[Cfg<D, KK>::NK], double* __restrict__ out,
+                                             double* __restrict__ fs, const DevMesh& mesh,
+                                             const double* __restrict__ fi, const double* __restrict__ fo,
+                                             int64_t wave, int lane) {
   using C = Cfg<D, KK>;
   using M = MF<double>;
   const int g = lane >> 4, c = lane & 15;
@@ -580,9 +585,15 @@ __device__ __forceinline__ void mass_batch(const double (&xh)[Cfg<D, KK>::NK], d
     for (int a = 0; a < D; ++a) y[(blk * D + a) / 4][(blk * D + a) % 4] = t[a];
   }
   double sfac[D + 1];
+  int64_t fbase[D + 1];
 #pragma unroll
-  for (int f = 0; f <= D; ++f) sfac[f] = MODE == 0 ? Gr[GEO_NFN + f] : 0.5 / Gr[GEO_NFN + f];
+  for (int f = 0; f <= D; ++f) {
+    sfac[f] = MODE == 0 ? Gr[GEO_NFN + f] : 0.5 / Gr[GEO_NFN + f];
+    const int32_t F = mesh.fid[ee * (D + 1) + f];
+    fbase[f] = F < 0 ? -1 : ((int64_t)mesh.fside[ee * (D + 1) + f] * mesh.F + F) * C::NF;
+  }
   const double sint = MODE == 0 ? Gr[GEO_SI] : 1.0 / Gr[GEO_SI];
+  double dot = 0.0;
 #pragma unroll
   for (int jt = 0; jt < C::NJT; ++jt) {
     d4 o = vzero<d4>();
@@ -591,28 +602,55 @@ __device__ __forceinline__ void mass_batch(const double (&xh)[Cfg<D, KK>::NK], d
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int j = 16 * jt + M::row(i, g);
+      // row j = 4 kk + g is also the row that xh[kk] holds; the facet and
+      // interior scalings cancel in the product (xh = x_j s_j, y_j = o s_j)
+      const int kk = 4 * jt + i;
+      if (kk < C::NK) dot += xh[kk] * o[i];
       if (valid && j < C::N) {
-        if (j < C::NFL) slot[ee * C::NFL + j] = o[i] * sfac[j / C::NF];
-        else out[off + ee * C::NINT + (j - C::NFL)] = o[i] * sint;
+        if (j < C::NFL) {
+          const int f = j / C::NF;
+          if (fbase[f] >= 0) fs[fbase[f] + (j - f * C::NF)] = o[i] * sfac[f];
+        } else {
+          out[off + ee * C::NINT + (j - C::NFL)] = o[i] * sint;
+        }
       }
     }
   }
+  return dot;
+}
+
+// block sum of one double per lane (256 lanes), fixed order; lane 0 of the
+// block gets the total
+__device__ __forceinline__ double block_sum256(double v) {
+  __shared__ double red[4];
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // one batch per wave
+// part (nullable): per-block partial of x . y
 template <int D, int KK, int MODE>
 __global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, double* __restrict__ out,
-                                              double* __restrict__ slot, DevMesh mesh,
+                                              double* __restrict__ fs, DevMesh mesh,
                                               const double* __restrict__ fin,
                                               const double* __restrict__ fout,
-                                              const int* __restrict__ flag) {
+                                              const int* __restrict__ flag, double* __restrict__ part) {
   if (flag && *flag) return;
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wave * 16 >= mesh.E) return;
-  double xh[Cfg<D, KK>::NK];
-  mass_gather<D, KK, MODE>(x, mesh, wave, lane >> 4, lane & 15, xh);
-  mass_batch<D, KK, MODE>(xh, out, slot, mesh, fin, fout, wave, lane);
+  double dot = 0.0;
+  if (wave * 16 < mesh.E) {
+    double xh[Cfg<D, KK>::NK];
+    mass_gather<D, KK, MODE>(x, mesh, wave, lane >> 4, lane & 15, xh);
+    dot = mass_batch<D, KK, MODE>(xh, out, fs, mesh, fin, fout, wave, lane);
+  }
+  if (part) {
+    dot = block_sum256(dot);
+    if (threadIdx.x == 0) part[blockIdx.x] = dot;
+  }
 }
 
 // Persistent variant for orders whose two tables fit in LDS: each block
@@ -628,10 +666,10 @@ constexpr int mass_lds_doubles() {
 
 template <int D, int KK, int MODE>
 __global__ __launch_bounds__(256) void k_mass_lds(const double* __restrict__ x, double* __restrict__ out,
-                                                  double* __restrict__ slot, DevMesh mesh,
+                                                  double* __restrict__ fs, DevMesh mesh,
                                                   const double* __restrict__ fin,
                                                   const double* __restrict__ fout,
-                                                  const int* __restrict__ flag) {
+                                                  const int* __restrict__ flag, double* __restrict__ part) {
   using C = Cfg<D, KK>;
   extern __shared__ double lds[];
   if (flag && *flag) return;  // uniform over the launch
@@ -643,8 +681,9 @@ __global__ __launch_bounds__(256) void k_mass_lds(const double* __restrict__ x, 
   const int64_t nw = (mesh.E + 15) / 16;
   const int64_t stride = (int64_t)gridDim.x * 4;
   int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wave >= nw) return;
+  double dot = 0.0;
   double xh[C::NK];
+  // (a wave past the last batch gathers zeros and skips the loop)
   mass_gather<D, KK, MODE>(x, mesh, wave, g, c, xh);
   for (; wave < nw; wave += stride) {
     double xn[C::NK];
@@ -654,11 +693,15 @@ __global__ __launch_bounds__(256) void k_mass_lds(const double* __restrict__ x, 
     // hoisting all of them into registers
     int base = 0;
     asm volatile("" : "+s"(base));
-    mass_batch<D, KK, MODE>(xh, out, slot, mesh, lds + base, lds + base + NIN, wave, lane);
+    dot += mass_batch<D, KK, MODE>(xh, out, fs, mesh, lds + base, lds + base + NIN, wave, lane);
     if (more) {
 #pragma unroll
       for (int kk = 0; kk < C::NK; ++kk) xh[kk] = xn[kk];
     }
+  }
+  if (part) {
+    dot = block_sum256(dot);
+    if (threadIdx.x == 0) part[blockIdx.x] = dot;
   }
 }
 
@@ -676,45 +719,19 @@ __global__ void k_assemble_flag(double* __restrict__ r, const double* __restrict
   r[t] = slot[(int64_t)e0 * NFL + i0 * NF + jj] + slot[(int64_t)e1 * NFL + i1 * NF + jj];
 }
 
-// Facet rows v_F = slot(T) + slot(T') plus the per-block partial of w . v over
-// all rows (interior rows of v were written by the element kernel).
-template <int NF, int NFL>
-__global__ __launch_bounds__(256) void k_asm_dot(double* __restrict__ v, const double* __restrict__ slot,
-                                                 const double* __restrict__ w, DevMesh mesh, int64_t n,
-                                                 const int* __restrict__ flag, double* __restrict__ part) {
-  if (*flag) return;
-  __shared__ double sh[256];
-  const int64_t nf = mesh.F * NF;
-  double s = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
-    double val;
-    if (t < nf) {
-      const int64_t F = t / NF;
-      const int jj = (int)(t - F * NF);
-      const int32_t e0 = mesh.facet_elem[2 * F], e1 = mesh.facet_elem[2 * F + 1];
-      const int i0 = mesh.facet_local[2 * F], i1 = mesh.facet_local[2 * F + 1];
-      val = slot[(int64_t)e0 * NFL + i0 * NF + jj] + slot[(int64_t)e1 * NFL + i1 * NF + jj];
-      v[t] = val;
-    } else {
-      val = v[t];
-    }
-    s += w[t] * val;
-  }
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+// facet rows from the facet-side buffer: v_F = fs[0][F] + fs[1][F]
+__global__ void k_fs_assemble(double* __restrict__ v, const double* __restrict__ fs, int64_t nfl,
+                              const int* __restrict__ flag) {
+  if (flag && *flag) return;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < nfl; t += (int64_t)gridDim.x * 256)
+    v[t] = fs[t] + fs[nfl + t];
 }
 
 // ------------------------------------------------------------------ launchers
-template <int D, int KK>
-void launch_asm_dot(hipStream_t s, double* v, const double* slot, const double* w, const DevMesh& mesh, int64_t n,
-                    const int* flag, double* part, int nblocks) {
-  using C = Cfg<D, KK>;
-  hipLaunchKernelGGL((k_asm_dot<C::NF, C::NFL>), dim3(nblocks), dim3(256), 0, s, v, slot, w, mesh, n, flag, part);
+void launch_fs_assemble(hipStream_t s, double* v, const double* fs, int64_t nfl, const int* flag) {
+  if (nfl <= 0) return;
+  const int64_t b = std::min<int64_t>((nfl + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_fs_assemble, dim3((unsigned)b), dim3(256), 0, s, v, fs, nfl, flag);
 }
 
 template <typename T, int D, int KK>
@@ -744,30 +761,32 @@ void launch_assemble(hipStream_t s, double* r, const double* slot, const DevMesh
 }
 
 template <int D, int KK>
-void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* slot, const DevMesh& mesh,
-                 const double* fin, const double* fout, const int* flag) {
+int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* fs, const DevMesh& mesh,
+                const double* fin, const double* fout, const int* flag, double* part) {
   using C = Cfg<D, KK>;
   const int64_t waves = (mesh.E + 15) / 16;
   constexpr size_t lds_bytes = (size_t)mass_lds_doubles<D, KK>() * sizeof(double);
+  if (waves == 0) return 0;
   if (lds_bytes <= 64 * 1024) {
     // two resident blocks per CU (the tables take up to 64 KB of LDS each)
     const int64_t blocks = std::min<int64_t>((waves + 3) / 4, MASS_BLOCKS);
     if (mode == 0)
-      HOPU_LAUNCH((k_mass_lds<D, KK, 0>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, slot, mesh,
-                         fin, fout, flag);
+      HOPU_LAUNCH((k_mass_lds<D, KK, 0>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, fs, mesh,
+                         fin, fout, flag, part);
     else
-      HOPU_LAUNCH((k_mass_lds<D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, slot, mesh,
-                         fin, fout, flag);
-  } else {
-    const int64_t blocks = (waves + 3) / 4;
-    if (mode == 0)
-      HOPU_LAUNCH((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
-                         fout, flag);
-    else
-      HOPU_LAUNCH((k_mass<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, slot, mesh, fin,
-                         fout, flag);
+      HOPU_LAUNCH((k_mass_lds<D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, fs, mesh,
+                         fin, fout, flag, part);
+    return (int)blocks;
   }
+  const int64_t blocks = (waves + 3) / 4;
+  if (mode == 0)
+    HOPU_LAUNCH((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, fs, mesh, fin, fout, flag,
+                part);
+  else
+    HOPU_LAUNCH((k_mass<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, fs, mesh, fin, fout, flag,
+                part);
   (void)sizeof(C);
+  return (int)blocks;
 }
 
 #define HOPU_INST(D, KK)                                                                                     \
@@ -779,11 +798,9 @@ void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* 
                                            const DevTables<double>&, int, double*, double*);                \
   template void launch_elem<float, D, KK>(hipStream_t, const float*, double*, double*, const DevMesh&,      \
                                           const DevTables<float>&, int, double*, double*);                  \
-  template void launch_mass<D, KK>(hipStream_t, int, const double*, double*, double*, const DevMesh&,       \
-                                   const double*, const double*, const int*);                               \
-  template void launch_assemble<D, KK>(hipStream_t, double*, const double*, const DevMesh&, const int*);      \
-  template void launch_asm_dot<D, KK>(hipStream_t, double*, const double*, const double*, const DevMesh&,     \
-                                      int64_t, const int*, double*, int);
+  template int launch_mass<D, KK>(hipStream_t, int, const double*, double*, double*, const DevMesh&,        \
+                                  const double*, const double*, const int*, double*);                       \
+  template void launch_assemble<D, KK>(hipStream_t, double*, const double*, const DevMesh&, const int*);
 
 HOPU_INST(2, 1)
 HOPU_INST(2, 2)

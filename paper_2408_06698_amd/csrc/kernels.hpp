@@ -61,6 +61,7 @@ struct DevMesh {
   const int32_t* nbr;
   const int32_t* facet_elem;
   const int8_t* facet_local;
+  const int8_t* fside;  // [E][d+1]: 0 if the element is facet_elem[2F] on that side, else 1
   const int32_t* belem;
   const int32_t* bsig;
   const int8_t* lfac;  // nullable

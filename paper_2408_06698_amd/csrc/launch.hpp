@@ -9,15 +9,18 @@ void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, con
 template <typename T, int D, int KK>
 void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMesh& mesh,
                  const DevTables<T>& tb, int terms, double* diss_part, double* eta_nd);
+// y = M x (mode 0) or the preconditioner applied to x (mode 1): interior rows
+// into out, facet rows as one contribution per side into fs ([2][F][NF]);
+// with part set, also the per-block partials of x . y.  Returns the number of
+// blocks launched (= partials written).
 template <int D, int KK>
-void launch_mass(hipStream_t s, int mode, const double* x, double* out, double* slot, const DevMesh& mesh,
-                 const double* fin, const double* fout, const int* flag);
+int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* fs, const DevMesh& mesh,
+                const double* fin, const double* fout, const int* flag, double* part);
+// facet rows v[0, nfl) = fs[0][.] + fs[1][.]
+void launch_fs_assemble(hipStream_t s, double* v, const double* fs, int64_t nfl, const int* flag);
 template <int D, int KK>
 void launch_assemble(hipStream_t s, double* r, const double* slot, const DevMesh& mesh, const int* flag);
 template <typename T, int D, int KK>
 void launch_vjp(hipStream_t s, const T* mu_u, const T* mu_mu, double* out, double* slot, const DevMesh& mesh,
                 const DevTables<T>& tb);
-template <int D, int KK>
-void launch_asm_dot(hipStream_t s, double* v, const double* slot, const double* w, const DevMesh& mesh, int64_t n,
-                    const int* flag, double* part, int nblocks);
 }  // namespace hopu

@@ -9,9 +9,14 @@ enum { OP_SET_TOL = 0, OP_SET_RZ = 1, OP_ALPHA = 2, OP_BETA = 3, OP_STORE = 4, O
 void vec_dot(hipStream_t s, const double* a, const double* b, int64_t n, double* part, const int* flag);
 void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag, int op, double arg,
                 double* dst);
-void vec_axpy2(hipStream_t s, double* x, double* r, const double* p, const double* q, int64_t n,
-               const double* sc, const int* flag);
-void vec_xpay(hipStream_t s, double* p, const double* z, int64_t n, const double* sc, const int* flag);
+// q, z, and q in vec_sub_fs are unassembled: facet rows [0, nfl) come from the
+// facet-side buffer fs ([2][nfl]), interior rows from the vector itself
+void vec_axpy2(hipStream_t s, double* x, double* r, const double* p, const double* q, const double* fs, int64_t nfl,
+               int64_t n, const double* sc, const int* flag);
+void vec_xpay(hipStream_t s, double* p, const double* z, const double* fs, int64_t nfl, int64_t n, const double* sc,
+              const int* flag);
+void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, const double* fs, int64_t nfl,
+                int64_t n);
 void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n);
 void vec_axpy(hipStream_t s, double* y, const double* x, double a, int64_t n);
 void vec_comb3(hipStream_t s, double* w, const double* h1, const double* h2, double a, double b, double c,

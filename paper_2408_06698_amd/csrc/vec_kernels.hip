@@ -67,22 +67,39 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part,
   }
 }
 
+// Vectors whose facet rows [0, nfl) are held unassembled as one contribution
+// per facet side (fs[0][.] and fs[1][.]) and whose interior rows sit in place.
+__device__ __forceinline__ double fs_row(const double* __restrict__ v, const double* __restrict__ fs, int64_t nfl,
+                                         int64_t i) {
+  return i < nfl ? fs[i] + fs[nfl + i] : v[i];
+}
+
+// x += alpha p; r -= alpha q (q unassembled)
 __global__ void k_axpy2(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-                        const double* __restrict__ q, int64_t n, const double* sc, const int* flag) {
+                        const double* __restrict__ q, const double* __restrict__ fs, int64_t nfl, int64_t n,
+                        const double* sc, const int* flag) {
   if (*flag) return;
   const double al = sc[SC_ALPHA];
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     x[i] += al * p[i];
-    r[i] -= al * q[i];
+    r[i] -= al * fs_row(q, fs, nfl, i);
   }
 }
 
-__global__ void k_xpay(double* __restrict__ p, const double* __restrict__ z, int64_t n, const double* sc,
-                       const int* flag) {
+// p = z + beta p (z unassembled)
+__global__ void k_xpay(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ fs,
+                       int64_t nfl, int64_t n, const double* sc, const int* flag) {
   if (*flag) return;
   const double be = sc[SC_BETA];
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    p[i] = z[i] + be * p[i];
+    p[i] = fs_row(z, fs, nfl, i) + be * p[i];
+}
+
+// r = b - q (q unassembled)
+__global__ void k_sub_fs(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ q,
+                         const double* __restrict__ fs, int64_t nfl, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    r[i] = b[i] - fs_row(q, fs, nfl, i);
 }
 
 __global__ void k_sub(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ q,
@@ -118,12 +135,17 @@ void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag
                 double* dst) {
   hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, s, part, np, sc, flag, op, arg, dst);
 }
-void vec_axpy2(hipStream_t s, double* x, double* r, const double* p, const double* q, int64_t n,
-               const double* sc, const int* flag) {
-  hipLaunchKernelGGL(k_axpy2, dim3(grid_for(n)), dim3(256), 0, s, x, r, p, q, n, sc, flag);
+void vec_axpy2(hipStream_t s, double* x, double* r, const double* p, const double* q, const double* fs, int64_t nfl,
+               int64_t n, const double* sc, const int* flag) {
+  hipLaunchKernelGGL(k_axpy2, dim3(grid_for(n)), dim3(256), 0, s, x, r, p, q, fs, nfl, n, sc, flag);
 }
-void vec_xpay(hipStream_t s, double* p, const double* z, int64_t n, const double* sc, const int* flag) {
-  hipLaunchKernelGGL(k_xpay, dim3(grid_for(n)), dim3(256), 0, s, p, z, n, sc, flag);
+void vec_xpay(hipStream_t s, double* p, const double* z, const double* fs, int64_t nfl, int64_t n, const double* sc,
+              const int* flag) {
+  hipLaunchKernelGGL(k_xpay, dim3(grid_for(n)), dim3(256), 0, s, p, z, fs, nfl, n, sc, flag);
+}
+void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, const double* fs, int64_t nfl,
+                int64_t n) {
+  hipLaunchKernelGGL(k_sub_fs, dim3(grid_for(n)), dim3(256), 0, s, r, b, q, fs, nfl, n);
 }
 void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n) {
   hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, s, r, b, q, n);
