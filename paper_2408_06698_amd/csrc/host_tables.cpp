@@ -409,25 +409,36 @@ void make_frag_tables(const RefTables& t, RowMap rm, FragTables& f) {
   };
   auto Dinv = [&](int a, int al, int j) { return t.Dinv[(a * nP + al) * n + j]; };
   auto D = [&](int j, int a, int al) { return t.D[j * n + a * nP + al]; };
-  // modal / mass_in / prec_in
+  // modal: dual rows j = 4 kk + g in order
   f.modal.assign(fd.NMT * fd.NK * 64, 0.0);
-  f.prec_in.assign(fd.NMT * fd.NK * 64, 0.0);
   for (int mt = 0; mt < fd.NMT; ++mt)
     for (int kk = 0; kk < fd.NK; ++kk)
       for (int l = 0; l < 64; ++l) {
         int a, al, rho = 16 * mt + (l & 15), j = 4 * kk + (l >> 4);
         if (!rho_inv(rho, a, al) || j >= n) continue;
         f.modal[(mt * fd.NK + kk) * 64 + l] = Dinv(a, al, j);
+      }
+  // mass / preconditioner: dual rows in mass_row order, K side (in) and M
+  // side (out: output row m of tile jt sits in register m/4 of group m%4,
+  // i.e. step 4 jt + m/4)
+  f.mass_in.assign(fd.NMT * fd.NK * 64, 0.0);
+  f.prec_in.assign(fd.NMT * fd.NK * 64, 0.0);
+  for (int mt = 0; mt < fd.NMT; ++mt)
+    for (int kk = 0; kk < fd.NK; ++kk)
+      for (int l = 0; l < 64; ++l) {
+        int a, al, rho = 16 * mt + (l & 15), j = mass_row(s, kk, l >> 4);
+        if (!rho_inv(rho, a, al) || j < 0) continue;
+        f.mass_in[(mt * fd.NK + kk) * 64 + l] = Dinv(a, al, j);
         f.prec_in[(mt * fd.NK + kk) * 64 + l] = D(j, a, al);
       }
-  f.mass_in = f.modal;
   f.mass_out.assign(fd.NJT * fd.NMQ * 64, 0.0);
   f.prec_out.assign(fd.NJT * fd.NMQ * 64, 0.0);
   for (int jt = 0; jt < fd.NJT; ++jt)
     for (int rq = 0; rq < fd.NMQ; ++rq)
       for (int l = 0; l < 64; ++l) {
-        int j = 16 * jt + (l & 15), rho = 16 * (rq / 4) + rowof(rq % 4, l >> 4), a, al;
-        if (j >= n || !rho_inv(rho, a, al)) continue;
+        const int m = l & 15;
+        int j = mass_row(s, 4 * jt + m / 4, m % 4), rho = 16 * (rq / 4) + rowof(rq % 4, l >> 4), a, al;
+        if (j < 0 || !rho_inv(rho, a, al)) continue;
         f.mass_out[(jt * fd.NMQ + rq) * 64 + l] = Dinv(a, al, j);
         f.prec_out[(jt * fd.NMQ + rq) * 64 + l] = D(j, a, al);
       }

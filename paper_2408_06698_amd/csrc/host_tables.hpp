@@ -76,6 +76,17 @@ struct RefTables {
 bool make_ref_tables(int dim, int k, RefTables& t, std::string& err);
 
 // Modal row layout: rho(a, alpha) = (alpha/4)*4*dim + 4*a + alpha%4.
+// Dual row held at step s by lane group g (g = 0..3) in the mass kernels, or
+// -1: for s < nf, groups g <= dim take row s of facet g; every other slot,
+// in (s, g) order, takes the next interior row.
+inline int mass_row(const Sizes& sz, int s, int g) {
+  const int nfg = sz.dim + 1;  // facet groups
+  if (s < sz.nf && g < nfg) return g * sz.nf + s;
+  const int before = s < sz.nf ? s * (4 - nfg) : sz.nf * (4 - nfg) + (s - sz.nf) * 4;
+  const int t = before + (s < sz.nf ? g - nfg : g);
+  return t < sz.nint ? sz.nfl + t : -1;
+}
+
 inline int modal_row(int dim, int a, int alpha) {
   return (alpha / 4) * 4 * dim + 4 * a + (alpha % 4);
 }
@@ -99,8 +110,10 @@ struct FragTables {
   // vjp extras
   std::vector<double> vol_dV;  // [NQVT][dim][NPK][64]  d_b p_alpha at (q, alpha)
   std::vector<double> vol_VT;  // [NQVT][4][NAT][64]
-  // mass / preconditioner sandwiches (modal rows in rho layout)
-  std::vector<double> mass_in;   // [NMT][NK][64]  = modal
+  // mass / preconditioner sandwiches (modal rows in rho layout).  Their dual
+  // rows follow mass_row(): lane group g holds facet g's rows, so a lane
+  // touches one facet only.
+  std::vector<double> mass_in;   // [NMT][NK][64]  Dinv rows rho, k = mass_row
   std::vector<double> mass_out;  // [NJT][NMQ][64] Dinv^T with k = rho quads
   std::vector<double> prec_in;   // [NMT][NK][64]  D^T rows rho, k = j
   std::vector<double> prec_out;  // [NJT][NMQ][64] D with k = rho quads

@@ -474,54 +474,98 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
 // the sum over elements of x_T . y_T, which each lane accumulates locally.
 // Each wave walks batches of 16 elements with a grid stride and gathers the
 // next batch while the MFMAs of the current one run.
-template <int D, int KK, int MODE>
-__device__ __forceinline__ void mass_gather(const double* __restrict__ x, const DevMesh& mesh, int64_t wave, int g,
-                                            int c, double (&xh)[Cfg<D, KK>::NK]) {
+// A lane's per-batch inputs come in two stages, each issued one batch ahead
+// of its use, so that no global load is waited on between the MFMAs of a
+// batch: the facet ids and sides of element c (needed to address the
+// gather), then the gathered rows and the element's geometry.  The hardware
+// retires vector-memory loads in order, so a load issued inside the compute
+// phase would also wait for every prefetch issued before it.
+// Row order of the mass kernels (the tables follow it): at step s, lane
+// group g holds row s of facet g while s < NF and g <= d; every other slot,
+// taken in (s, g) order, holds the next interior row.  A lane therefore
+// touches a single facet, whose id, side and scale it keeps in scalars.
+template <int D, int KK>
+__device__ __forceinline__ bool mass_is_facet(int s, int g) {
+  return s < Cfg<D, KK>::NF && g <= D;
+}
+template <int D, int KK>
+__device__ __forceinline__ int mass_int_row(int s, int g) {
+  using C = Cfg<D, KK>;
+  constexpr int nfg = D + 1;
+  return s < C::NF ? s * (4 - nfg) + (g - nfg) : C::NF * (4 - nfg) + (s - C::NF) * 4 + g;
+}
+
+// A lane's per-batch inputs come in two stages, each issued one batch ahead
+// of its use, so that no global load is waited on between the MFMAs of a
+// batch: the id and side of the lane's facet (needed to address the
+// gather), then the gathered rows and the element's geometry.  The hardware
+// retires vector-memory loads in order, so a load issued inside the compute
+// phase would also wait for every prefetch issued before it.
+struct MassIdx {
+  int32_t fid;   // global facet id of facet g, -1 for none (wall, padding, g > d)
+  int32_t side;  // 0/1: which contribution of that facet this element writes
+};
+template <int D, int KK>
+struct MassData {
+  double x[Cfg<D, KK>::NK];  // rows held at steps kk, unscaled
+  double J[D][D];
+  double det, si, nf;  // det J, interior scale, |N_F| of facet g
+};
+
+template <int D>
+__device__ __forceinline__ void mass_load_idx(const DevMesh& mesh, int64_t wave, int g, int c, MassIdx& ix) {
+  const int64_t e = wave * 16 + c;
+  const bool ok = e < mesh.E && g <= D;
+  ix.fid = ok ? mesh.fid[e * (D + 1) + g] : -1;
+  ix.side = ok ? (int32_t)mesh.fside[e * (D + 1) + g] : 0;
+}
+
+template <int D, int KK>
+__device__ __forceinline__ void mass_load_data(const double* __restrict__ x, const DevMesh& mesh, int64_t wave,
+                                               int g, int c, const MassIdx& ix, MassData<D, KK>& md) {
   using C = Cfg<D, KK>;
   const int64_t e = wave * 16 + c;
   const bool valid = e < mesh.E;
   const int64_t ee = valid ? e : 0;
-  const double* Gr = mesh.geo + ee * GEO_STRIDE;
   const int64_t off = mesh.F * C::NF;
-  int32_t fid[D + 1];
-  double sfac[D + 1];
-#pragma unroll
-  for (int f = 0; f <= D; ++f) {
-    fid[f] = mesh.fid[ee * (D + 1) + f];
-    sfac[f] = MODE == 0 ? Gr[GEO_NFN + f] : 0.5 / Gr[GEO_NFN + f];
-  }
-  const double sint = MODE == 0 ? Gr[GEO_SI] : 1.0 / Gr[GEO_SI];
 #pragma unroll
   for (int kk = 0; kk < C::NK; ++kk) {
-    const int j = 4 * kk + g;
     double v = 0.0;
-    if (valid && j < C::N) {
-      if (j < C::NFL) {
-        const int f = j / C::NF, jj = j - f * C::NF;
-        if (fid[f] >= 0) v = x[(int64_t)fid[f] * C::NF + jj] * sfac[f];
-      } else {
-        v = x[off + ee * C::NINT + (j - C::NFL)] * sint;
-      }
+    if (mass_is_facet<D, KK>(kk, g)) {
+      if (ix.fid >= 0) v = x[(int64_t)ix.fid * C::NF + kk];
+    } else {
+      const int t = mass_int_row<D, KK>(kk, g);
+      if (valid && t < C::NINT) v = x[off + ee * C::NINT + t];
     }
-    xh[kk] = v;
+    md.x[kk] = v;
   }
+  const double* Gr = mesh.geo + ee * GEO_STRIDE;
+  load_J<D>(Gr, md.J);
+  md.det = Gr[GEO_DET];
+  md.si = Gr[GEO_SI];
+  md.nf = g <= D ? Gr[GEO_NFN + (g <= D ? g : 0)] : 1.0;
 }
 
-// one batch: xh gathered, outputs written
-// Returns this lane's share of x_T . y_T over the batch.
+// One batch from registers and the fragment tables; writes the outputs and
+// returns this lane's share of x_T . y_T.
 template <int D, int KK, int MODE>
-__device__ __forceinline__ double mass_batch(const double (&xh)[Cfg<D, KK>::NK], double* __restrict__ out,
-                                             double* __restrict__ fs, const DevMesh& mesh,
-                                             const double* __restrict__ fi, const double* __restrict__ fo,
-                                             int64_t wave, int lane) {
+__device__ __forceinline__ double mass_compute(const MassData<D, KK>& md, const MassIdx& ix,
+                                               double* __restrict__ out, double* __restrict__ fs,
+                                               const DevMesh& mesh, const double* __restrict__ fi,
+                                               const double* __restrict__ fo, int64_t wave, int lane) {
   using C = Cfg<D, KK>;
   using M = MF<double>;
   const int g = lane >> 4, c = lane & 15;
   const int64_t off = mesh.F * C::NF;
   const int64_t e = wave * 16 + c;
   const bool valid = e < mesh.E;
-  const int64_t ee = valid ? e : 0;
-  const double* Gr = mesh.geo + ee * GEO_STRIDE;
+  // facet rows scaled by |N_F| (mode 1: 1/2 |N_F|^-1, the facet split
+  // included), interior rows by the interior scale (its inverse)
+  const double sfac = MODE == 0 ? md.nf : 0.5 / md.nf;
+  const double sint = MODE == 0 ? md.si : 1.0 / md.si;
+  double xh[C::NK];
+#pragma unroll
+  for (int kk = 0; kk < C::NK; ++kk) xh[kk] = md.x[kk] * (mass_is_facet<D, KK>(kk, g) ? sfac : sint);
   double y[C::NMT][4];
 #pragma unroll
   for (int mt = 0; mt < C::NMT; ++mt) {
@@ -532,9 +576,6 @@ __device__ __forceinline__ double mass_batch(const double (&xh)[Cfg<D, KK>::NK],
     for (int i = 0; i < 4; ++i) y[mt][i] = acc[i];
   }
   // component mixing: quads rq = blk*D + a hold components a of one alpha block
-  double J[D][D];
-  load_J<D>(Gr, J);
-  const double det = Gr[GEO_DET];
   double Gm[D][D];
 #pragma unroll
   for (int a = 0; a < D; ++a)
@@ -542,11 +583,11 @@ __device__ __forceinline__ double mass_batch(const double (&xh)[Cfg<D, KK>::NK],
     for (int bb = 0; bb < D; ++bb) {
       double s = 0;
 #pragma unroll
-      for (int r2 = 0; r2 < D; ++r2) s += J[r2][a] * J[r2][bb];
+      for (int r2 = 0; r2 < D; ++r2) s += md.J[r2][a] * md.J[r2][bb];
       Gm[a][bb] = s;
     }
   double Gs[D][D];
-  const double sd = 1.0 / fabs(det);
+  const double sd = 1.0 / fabs(md.det);
   if (MODE == 0) {
 #pragma unroll
     for (int a = 0; a < D; ++a)
@@ -584,15 +625,7 @@ __device__ __forceinline__ double mass_batch(const double (&xh)[Cfg<D, KK>::NK],
 #pragma unroll
     for (int a = 0; a < D; ++a) y[(blk * D + a) / 4][(blk * D + a) % 4] = t[a];
   }
-  double sfac[D + 1];
-  int64_t fbase[D + 1];
-#pragma unroll
-  for (int f = 0; f <= D; ++f) {
-    sfac[f] = MODE == 0 ? Gr[GEO_NFN + f] : 0.5 / Gr[GEO_NFN + f];
-    const int32_t F = mesh.fid[ee * (D + 1) + f];
-    fbase[f] = F < 0 ? -1 : ((int64_t)mesh.fside[ee * (D + 1) + f] * mesh.F + F) * C::NF;
-  }
-  const double sint = MODE == 0 ? Gr[GEO_SI] : 1.0 / Gr[GEO_SI];
+  double* const fsrow = ix.fid >= 0 ? fs + ((int64_t)ix.side * mesh.F + ix.fid) * C::NF : nullptr;
   double dot = 0.0;
 #pragma unroll
   for (int jt = 0; jt < C::NJT; ++jt) {
@@ -601,17 +634,16 @@ __device__ __forceinline__ double mass_batch(const double (&xh)[Cfg<D, KK>::NK],
     for (int rq = 0; rq < C::NMQ; ++rq) o = M::mma(fo[(jt * C::NMQ + rq) * 64 + lane], y[rq / 4][rq % 4], o);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int j = 16 * jt + M::row(i, g);
-      // row j = 4 kk + g is also the row that xh[kk] holds; the facet and
-      // interior scalings cancel in the product (xh = x_j s_j, y_j = o s_j)
-      const int kk = 4 * jt + i;
-      if (kk < C::NK) dot += xh[kk] * o[i];
-      if (valid && j < C::N) {
-        if (j < C::NFL) {
-          const int f = j / C::NF;
-          if (fbase[f] >= 0) fs[fbase[f] + (j - f * C::NF)] = o[i] * sfac[f];
+      // output register i of tile jt holds step s = 4 jt + i of this lane,
+      // the row that xh[s] holds; the scalings cancel in the product
+      const int s = 4 * jt + i;
+      if (s < C::NK) {
+        dot += xh[s] * o[i];
+        if (mass_is_facet<D, KK>(s, g)) {
+          if (fsrow) fsrow[s] = o[i] * sfac;
         } else {
-          out[off + ee * C::NINT + (j - C::NFL)] = o[i] * sint;
+          const int t = mass_int_row<D, KK>(s, g);
+          if (valid && t < C::NINT) out[off + e * C::NINT + t] = o[i] * sint;
         }
       }
     }
@@ -643,9 +675,11 @@ __global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, doub
   const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   double dot = 0.0;
   if (wave * 16 < mesh.E) {
-    double xh[Cfg<D, KK>::NK];
-    mass_gather<D, KK, MODE>(x, mesh, wave, lane >> 4, lane & 15, xh);
-    dot = mass_batch<D, KK, MODE>(xh, out, fs, mesh, fin, fout, wave, lane);
+    MassIdx ix;
+    MassData<D, KK> md;
+    mass_load_idx<D>(mesh, wave, lane >> 4, lane & 15, ix);
+    mass_load_data<D, KK>(x, mesh, wave, lane >> 4, lane & 15, ix, md);
+    dot = mass_compute<D, KK, MODE>(md, ix, out, fs, mesh, fin, fout, wave, lane);
   }
   if (part) {
     dot = block_sum256(dot);
@@ -665,7 +699,7 @@ constexpr int mass_lds_doubles() {
 }
 
 template <int D, int KK, int MODE>
-__global__ __launch_bounds__(256) void k_mass_lds(const double* __restrict__ x, double* __restrict__ out,
+__global__ __launch_bounds__(256, 2) void k_mass_lds(const double* __restrict__ x, double* __restrict__ out,
                                                   double* __restrict__ fs, DevMesh mesh,
                                                   const double* __restrict__ fin,
                                                   const double* __restrict__ fout,
@@ -682,21 +716,29 @@ __global__ __launch_bounds__(256) void k_mass_lds(const double* __restrict__ x, 
   const int64_t stride = (int64_t)gridDim.x * 4;
   int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   double dot = 0.0;
-  double xh[C::NK];
-  // (a wave past the last batch gathers zeros and skips the loop)
-  mass_gather<D, KK, MODE>(x, mesh, wave, g, c, xh);
+  // (a wave past the last batch loads nothing and skips the loop)
+  MassIdx ia, ib;
+  MassData<D, KK> da;
+  mass_load_idx<D>(mesh, wave, g, c, ia);
+  mass_load_data<D, KK>(x, mesh, wave, g, c, ia, da);
+  mass_load_idx<D>(mesh, wave + stride, g, c, ib);
   for (; wave < nw; wave += stride) {
-    double xn[C::NK];
+    MassData<D, KK> dn;
+    MassIdx ic;
     const bool more = wave + stride < nw;
-    if (more) mass_gather<D, KK, MODE>(x, mesh, wave + stride, g, c, xn);
+    if (more) {
+      mass_load_data<D, KK>(x, mesh, wave + stride, g, c, ib, dn);
+      mass_load_idx<D>(mesh, wave + 2 * stride, g, c, ic);
+    }
     // opaque base: keeps the fragment reads inside the loop instead of
     // hoisting all of them into registers
     int base = 0;
     asm volatile("" : "+s"(base));
-    dot += mass_batch<D, KK, MODE>(xh, out, fs, mesh, lds + base, lds + base + NIN, wave, lane);
+    dot += mass_compute<D, KK, MODE>(da, ia, out, fs, mesh, lds + base, lds + base + NIN, wave, lane);
     if (more) {
-#pragma unroll
-      for (int kk = 0; kk < C::NK; ++kk) xh[kk] = xn[kk];
+      da = dn;
+      ia = ib;
+      ib = ic;
     }
   }
   if (part) {
@@ -767,7 +809,7 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
   const int64_t waves = (mesh.E + 15) / 16;
   constexpr size_t lds_bytes = (size_t)mass_lds_doubles<D, KK>() * sizeof(double);
   if (waves == 0) return 0;
-  if (lds_bytes <= 64 * 1024) {
+  if constexpr (lds_bytes <= 64 * 1024) {
     // two resident blocks per CU (the tables take up to 64 KB of LDS each)
     const int64_t blocks = std::min<int64_t>((waves + 3) / 4, MASS_BLOCKS);
     if (mode == 0)
@@ -777,16 +819,17 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
       HOPU_LAUNCH((k_mass_lds<D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, fs, mesh,
                          fin, fout, flag, part);
     return (int)blocks;
+  } else {
+    const int64_t blocks = (waves + 3) / 4;
+    if (mode == 0)
+      HOPU_LAUNCH((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, fs, mesh, fin, fout, flag,
+                  part);
+    else
+      HOPU_LAUNCH((k_mass<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, fs, mesh, fin, fout, flag,
+                  part);
+    (void)sizeof(C);
+    return (int)blocks;
   }
-  const int64_t blocks = (waves + 3) / 4;
-  if (mode == 0)
-    HOPU_LAUNCH((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, fs, mesh, fin, fout, flag,
-                part);
-  else
-    HOPU_LAUNCH((k_mass<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, fs, mesh, fin, fout, flag,
-                part);
-  (void)sizeof(C);
-  return (int)blocks;
 }
 
 #define HOPU_INST(D, KK)                                                                                     \
