@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -42,6 +43,7 @@ struct hopu_ctx_s {
   double* part = nullptr;   // partial sums (max(NPART, nb, waves))
   int64_t npart = 0;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *rc = nullptr;
+  double* stage = nullptr;  // 16-byte aligned copy of a mass-kernel input that is not
   double* wh[3] = {nullptr, nullptr, nullptr};  // previous substep solutions (newest first)
   double* sc = nullptr;
   int* flag = nullptr;      // [0] converged, [1] iterations
@@ -273,6 +275,7 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(dev_alloc(ctx, &ctx->z, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->p, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->q, (size_t)n));
+    TRY(dev_alloc(ctx, &ctx->stage, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->w, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->rc, (size_t)n));
     for (int i = 0; i < 3; ++i) TRY(dev_alloc(ctx, &ctx->wh[i], (size_t)n));
@@ -378,6 +381,11 @@ static hopu_status do_apply(hopu_ctx ctx, const double* u, double* r, int terms,
 // ctx->part; returns their number.
 static int mass_raw(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag, bool in_loop, bool dot) {
   int np = 0;
+  // the 3D kernels read a facet's rows in 16-byte pairs
+  if (reinterpret_cast<uintptr_t>(x) % 16 != 0) {
+    vec_copy(ctx->stream, ctx->stage, x, ctx->n_dof);
+    x = ctx->stage;
+  }
   prof_begin(ctx, in_loop ? (mode == 0 ? PROF_MASS : PROF_PREC) : PROF_PLAIN);
   DISPATCH(ctx->dim, ctx->k, {
     np = launch_mass<D, KK>(ctx->stream, mode, x, y, ctx->slot, ctx->dm, mode == 0 ? ctx->mass_in : ctx->prec_in,

@@ -532,7 +532,18 @@ __device__ __forceinline__ void mass_load_data(const double* __restrict__ x, con
   for (int kk = 0; kk < C::NK; ++kk) {
     double v = 0.0;
     if (mass_is_facet<D, KK>(kk, g)) {
-      if (ix.fid >= 0) v = x[(int64_t)ix.fid * C::NF + kk];
+      if constexpr (C::NF % 2 == 0 && D == 3) {
+        // a lane's facet rows are contiguous: 16-byte loads of row pairs
+        if (kk % 2 == 0) {
+          double2 w = make_double2(0.0, 0.0);
+          if (ix.fid >= 0) w = *reinterpret_cast<const double2*>(x + (int64_t)ix.fid * C::NF + kk);
+          md.x[kk] = w.x;
+          md.x[kk + 1] = w.y;
+        }
+        continue;
+      } else {
+        if (ix.fid >= 0) v = x[(int64_t)ix.fid * C::NF + kk];
+      }
     } else {
       const int t = mass_int_row<D, KK>(kk, g);
       if (valid && t < C::NINT) v = x[off + ee * C::NINT + t];
@@ -640,7 +651,12 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md, const 
       if (s < C::NK) {
         dot += xh[s] * o[i];
         if (mass_is_facet<D, KK>(s, g)) {
-          if (fsrow) fsrow[s] = o[i] * sfac;
+          if constexpr (C::NF % 2 == 0 && D == 3) {
+            if (i % 2 == 0 && fsrow)
+              *reinterpret_cast<double2*>(fsrow + s) = make_double2(o[i] * sfac, o[i + 1] * sfac);
+          } else {
+            if (fsrow) fsrow[s] = o[i] * sfac;
+          }
         } else {
           const int t = mass_int_row<D, KK>(s, g);
           if (valid && t < C::NINT) out[off + e * C::NINT + t] = o[i] * sint;

@@ -18,6 +18,7 @@ void vec_xpay(hipStream_t s, double* p, const double* z, const double* fs, int64
 void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, const double* fs, int64_t nfl,
                 int64_t n);
 void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n);
+void vec_copy(hipStream_t s, double* y, const double* x, int64_t n);
 void vec_axpy(hipStream_t s, double* y, const double* x, double a, int64_t n);
 void vec_comb3(hipStream_t s, double* w, const double* h1, const double* h2, double a, double b, double c,
                int64_t n);

@@ -107,6 +107,10 @@ __global__ void k_sub(double* __restrict__ r, const double* __restrict__ b, cons
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) r[i] = b[i] - q[i];
 }
 
+__global__ void k_copy(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = x[i];
+}
+
 __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] += a * x[i];
 }
@@ -149,6 +153,9 @@ void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, cons
 }
 void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n) {
   hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, s, r, b, q, n);
+}
+void vec_copy(hipStream_t s, double* y, const double* x, int64_t n) {
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, s, y, x, n);
 }
 void vec_axpy(hipStream_t s, double* y, const double* x, double a, int64_t n) {
   hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, y, x, a, n);

@@ -109,6 +109,29 @@ def test_mass_apply(cfg, n, k):
     assert rel_dual(sp, y, ref) <= 1e-13
 
 
+def _odd_view(a):
+    """A device copy of `a` that is 8- but not 16-byte aligned."""
+    buf = torch.zeros(a.size + 1, dtype=torch.float64, device="cuda:0")
+    buf[1:] = dev(a)
+    v = buf[1:]
+    assert v.data_ptr() % 16 == 8
+    return v
+
+
+def test_mass_unaligned_vectors():
+    # the 3D mass kernels read facet rows in 16-byte pairs; inputs that are
+    # only 8-byte aligned go through an aligned copy and give identical bits
+    mesh, sp, x, c = case(2, (4, 3, 3), 3, noise=1e-3)
+    h = gpu_space(mesh, 3)
+    y0 = host(h.mass_apply(dev(x)))
+    y1 = host(h.mass_apply(_odd_view(x)))
+    assert np.array_equal(y0, y1)
+    r = O.residual(sp, x, 2)
+    w0, i0 = h.mass_solve(dev(r), rtol=1e-13)
+    w1, i1 = h.mass_solve(_odd_view(r), w=_odd_view(np.zeros_like(r)), rtol=1e-13)
+    assert i0 == i1 and np.array_equal(host(w0), host(w1))
+
+
 @pytest.mark.parametrize("cfg,n,k", [(1, (6, 5), 2), (2, (3, 3, 4), 3), (3, (3, 4, 3), 4)])
 def test_interpolate_and_eval(cfg, n, k):
     import synth
