@@ -268,7 +268,9 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(dev_alloc(ctx, &ctx->m32, (size_t)E * s.nm));
     TRY(dev_alloc(ctx, &ctx->mu64, (size_t)E * s.nm));
     TRY(dev_alloc(ctx, &ctx->mu32, (size_t)E * s.nm));
-    TRY(dev_alloc(ctx, &ctx->slot, (size_t)E * s.nfl));
+    // element slots (E * nfl) or the mass kernels' facet-side rows (2 F nf
+    // <= E nfl) followed by their trash slots
+    TRY(dev_alloc(ctx, &ctx->slot, (size_t)E * s.nfl + 128));
     ctx->npart = std::max<int64_t>(std::max<int64_t>(NPART, ctx->bat.nb), (E + 15) / 16);
     TRY(dev_alloc(ctx, &ctx->part, (size_t)ctx->npart));
     TRY(dev_alloc(ctx, &ctx->r, (size_t)n));

@@ -510,14 +510,19 @@ struct MassData {
   double x[Cfg<D, KK>::NK];  // rows held at steps kk, unscaled
   double J[D][D];
   double det, si, nf;  // det J, interior scale, |N_F| of facet g
+  MassIdx ix;          // the facet these rows came from (for the output)
 };
 
+// All loads below are unconditional (indices clamped into range; what is
+// invalid is masked where the values are used): a load under a branch
+// makes the compiler merge its result right away, which waits for it.
 template <int D>
 __device__ __forceinline__ void mass_load_idx(const DevMesh& mesh, int64_t wave, int g, int c, MassIdx& ix) {
   const int64_t e = wave * 16 + c;
-  const bool ok = e < mesh.E && g <= D;
-  ix.fid = ok ? mesh.fid[e * (D + 1) + g] : -1;
-  ix.side = ok ? (int32_t)mesh.fside[e * (D + 1) + g] : 0;
+  const int64_t ee = e < mesh.E ? e : 0;
+  const int gg = g <= D ? g : D;
+  ix.fid = mesh.fid[ee * (D + 1) + gg];
+  ix.side = (int32_t)mesh.fside[ee * (D + 1) + gg];
 }
 
 template <int D, int KK>
@@ -525,66 +530,127 @@ __device__ __forceinline__ void mass_load_data(const double* __restrict__ x, con
                                                int g, int c, const MassIdx& ix, MassData<D, KK>& md) {
   using C = Cfg<D, KK>;
   const int64_t e = wave * 16 + c;
-  const bool valid = e < mesh.E;
-  const int64_t ee = valid ? e : 0;
+  const int64_t ee = e < mesh.E ? e : 0;
   const int64_t off = mesh.F * C::NF;
+  const double* xf = x + (int64_t)(ix.fid >= 0 ? ix.fid : 0) * C::NF;
+  const double* xi = x + off + ee * C::NINT;
 #pragma unroll
   for (int kk = 0; kk < C::NK; ++kk) {
-    double v = 0.0;
-    if (mass_is_facet<D, KK>(kk, g)) {
-      if constexpr (C::NF % 2 == 0 && D == 3) {
-        // a lane's facet rows are contiguous: 16-byte loads of row pairs
+    if constexpr (C::NF % 2 == 0 && D == 3) {
+      // a lane's facet rows are contiguous: 16-byte loads of row pairs
+      if (kk < C::NF) {
         if (kk % 2 == 0) {
-          double2 w = make_double2(0.0, 0.0);
-          if (ix.fid >= 0) w = *reinterpret_cast<const double2*>(x + (int64_t)ix.fid * C::NF + kk);
+          const double2 w = *reinterpret_cast<const double2*>(xf + kk);
           md.x[kk] = w.x;
           md.x[kk + 1] = w.y;
         }
         continue;
-      } else {
-        if (ix.fid >= 0) v = x[(int64_t)ix.fid * C::NF + kk];
       }
-    } else {
-      const int t = mass_int_row<D, KK>(kk, g);
-      if (valid && t < C::NINT) v = x[off + ee * C::NINT + t];
     }
-    md.x[kk] = v;
+    const int t = mass_int_row<D, KK>(kk, g);
+    if constexpr (C::NINT > 0) {
+      const double* a = mass_is_facet<D, KK>(kk, g) ? xf + kk : xi + (t < C::NINT ? t : C::NINT - 1);
+      md.x[kk] = *a;
+    } else {
+      md.x[kk] = xf[kk < C::NF ? kk : 0];
+    }
   }
   const double* Gr = mesh.geo + ee * GEO_STRIDE;
   load_J<D>(Gr, md.J);
   md.det = Gr[GEO_DET];
   md.si = Gr[GEO_SI];
-  md.nf = g <= D ? Gr[GEO_NFN + (g <= D ? g : 0)] : 1.0;
+  md.nf = Gr[GEO_NFN + (g <= D ? g : 0)];
+  md.ix = ix;
 }
+
+// The store of step s: one store instruction per step and lane (a 16-byte
+// row pair at even facet steps in 3D with an even facet size, nothing at the
+// odd ones); a lane with nothing to write stores to `trash`.  With a fixed
+// store count per batch the compiler can wait for the prefetched loads
+// without also waiting for these stores.
+template <int D, int KK>
+constexpr bool mass_pairs() {
+  return D == 3 && Cfg<D, KK>::NF % 2 == 0;
+}
+template <int D, int KK>
+__device__ __forceinline__ void mass_store(int s, int g, double v0, double v1, double sfac, double sint, bool fok,
+                                           double* fsrow, bool valid, double* irow, double* trash) {
+  using C = Cfg<D, KK>;
+  if constexpr (mass_pairs<D, KK>()) {
+    if (s < C::NF) {
+      if (s % 2 == 0)
+        *reinterpret_cast<double2*>(fok ? fsrow + s : trash) = make_double2(v0 * sfac, v1 * sfac);
+    } else {
+      const int t = mass_int_row<D, KK>(s, g);
+      *(valid && t < C::NINT ? irow + t : trash) = v0 * sint;
+    }
+  } else {
+    const bool isf = mass_is_facet<D, KK>(s, g);
+    const int t = mass_int_row<D, KK>(s, g);
+    const bool ok = isf ? fok : valid && t < C::NINT;
+    *(ok ? (isf ? fsrow + s : irow + t) : trash) = v0 * (isf ? sfac : sint);
+  }
+}
+// at least as many store instructions as one batch issues (NK), to distinct
+// trash slots (so that none is dropped as overwritten)
+template <int NK>
+__device__ __forceinline__ void mass_dummy_stores(double* trash) {
+#pragma unroll
+  for (int s = 0; s < NK; ++s) trash[2 + 2 * s] = 0.0;
+}
+constexpr int64_t MASS_TRASH_DOUBLES = 128;  // >= 2 + 2 NK for every order
 
 // One batch from registers and the fragment tables; writes the outputs and
 // returns this lane's share of x_T . y_T.
 template <int D, int KK, int MODE>
-__device__ __forceinline__ double mass_compute(const MassData<D, KK>& md, const MassIdx& ix,
+__device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
                                                double* __restrict__ out, double* __restrict__ fs,
-                                               const DevMesh& mesh, const double* __restrict__ fi,
-                                               const double* __restrict__ fo, int64_t wave, int lane) {
+                                               double* __restrict__ trash, const DevMesh& mesh,
+                                               const double* __restrict__ fi, const double* __restrict__ fo,
+                                               int64_t wave, int lane, bool live = true) {
   using C = Cfg<D, KK>;
   using M = MF<double>;
   const int g = lane >> 4, c = lane & 15;
   const int64_t off = mesh.F * C::NF;
   const int64_t e = wave * 16 + c;
-  const bool valid = e < mesh.E;
+  const bool valid = live && e < mesh.E;  // (a batch that is not live writes nothing)
   // facet rows scaled by |N_F| (mode 1: 1/2 |N_F|^-1, the facet split
   // included), interior rows by the interior scale (its inverse)
   const double sfac = MODE == 0 ? md.nf : 0.5 / md.nf;
   const double sint = MODE == 0 ? md.si : 1.0 / md.si;
+  // the lane's facet exists (an interior facet of a real element)
+  const bool fok = valid && g <= D && md.ix.fid >= 0;
   double xh[C::NK];
 #pragma unroll
-  for (int kk = 0; kk < C::NK; ++kk) xh[kk] = md.x[kk] * (mass_is_facet<D, KK>(kk, g) ? sfac : sint);
+  for (int kk = 0; kk < C::NK; ++kk) {
+    const bool ok = mass_is_facet<D, KK>(kk, g) ? fok : valid && mass_int_row<D, KK>(kk, g) < C::NINT;
+    xh[kk] = ok ? md.x[kk] * (mass_is_facet<D, KK>(kk, g) ? sfac : sint) : 0.0;
+  }
+  // Both contractions run their output tiles side by side (independent
+  // accumulators) and read the table fragments of the next step while the
+  // MFMAs of the current one run.
   double y[C::NMT][4];
+  {
+    d4 acc[C::NMT];
+    double a[2][C::NMT];
 #pragma unroll
-  for (int mt = 0; mt < C::NMT; ++mt) {
-    d4 acc = vzero<d4>();
+    for (int mt = 0; mt < C::NMT; ++mt) {
+      acc[mt] = vzero<d4>();
+      a[0][mt] = fi[(mt * C::NK) * 64 + lane];
+    }
 #pragma unroll
-    for (int kk = 0; kk < C::NK; ++kk) acc = M::mma(fi[(mt * C::NK + kk) * 64 + lane], xh[kk], acc);
+    for (int kk = 0; kk < C::NK; ++kk) {
+      if (kk + 1 < C::NK) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) y[mt][i] = acc[i];
+        for (int mt = 0; mt < C::NMT; ++mt) a[(kk + 1) % 2][mt] = fi[(mt * C::NK + kk + 1) * 64 + lane];
+      }
+#pragma unroll
+      for (int mt = 0; mt < C::NMT; ++mt) acc[mt] = M::mma(a[kk % 2][mt], xh[kk], acc[mt]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < C::NMT; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) y[mt][i] = acc[mt][i];
   }
   // component mixing: quads rq = blk*D + a hold components a of one alpha block
   double Gm[D][D];
@@ -619,7 +685,11 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md, const 
         }
     }
   }
-  // in place: quads blk*D .. blk*D + D-1 only mix among themselves
+  // in place: quads blk*D .. blk*D + D-1 only mix among themselves.  With
+  // m the modal rows before and t after the mix, x_T . y_T = m . t (the two
+  // outer factors of the sandwich are transposes of each other), which is
+  // this lane's share of the inner product.
+  double dot = 0.0;
 #pragma unroll
   for (int blk = 0; blk < C::NPK; ++blk) {
     double t[D];
@@ -634,33 +704,40 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md, const 
       t[a] = s;
     }
 #pragma unroll
-    for (int a = 0; a < D; ++a) y[(blk * D + a) / 4][(blk * D + a) % 4] = t[a];
+    for (int a = 0; a < D; ++a) {
+      dot += y[(blk * D + a) / 4][(blk * D + a) % 4] * t[a];
+      y[(blk * D + a) / 4][(blk * D + a) % 4] = t[a];
+    }
   }
-  double* const fsrow = ix.fid >= 0 ? fs + ((int64_t)ix.side * mesh.F + ix.fid) * C::NF : nullptr;
-  double dot = 0.0;
+  double* const fsrow = fs + ((int64_t)md.ix.side * mesh.F + (md.ix.fid >= 0 ? md.ix.fid : 0)) * C::NF;
+  double* const irow = out + off + (valid ? e : 0) * C::NINT;
+  d4 o[C::NJT];
+  {
+    double b[2][C::NJT];
+#pragma unroll
+    for (int jt = 0; jt < C::NJT; ++jt) {
+      o[jt] = vzero<d4>();
+      b[0][jt] = fo[(jt * C::NMQ) * 64 + lane];
+    }
+#pragma unroll
+    for (int rq = 0; rq < C::NMQ; ++rq) {
+      if (rq + 1 < C::NMQ) {
+#pragma unroll
+        for (int jt = 0; jt < C::NJT; ++jt) b[(rq + 1) % 2][jt] = fo[(jt * C::NMQ + rq + 1) * 64 + lane];
+      }
+#pragma unroll
+      for (int jt = 0; jt < C::NJT; ++jt) o[jt] = M::mma(b[rq % 2][jt], y[rq / 4][rq % 4], o[jt]);
+    }
+  }
 #pragma unroll
   for (int jt = 0; jt < C::NJT; ++jt) {
-    d4 o = vzero<d4>();
-#pragma unroll
-    for (int rq = 0; rq < C::NMQ; ++rq) o = M::mma(fo[(jt * C::NMQ + rq) * 64 + lane], y[rq / 4][rq % 4], o);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      // output register i of tile jt holds step s = 4 jt + i of this lane,
-      // the row that xh[s] holds; the scalings cancel in the product
+      // output register i of tile jt holds step s = 4 jt + i of this lane
       const int s = 4 * jt + i;
       if (s < C::NK) {
-        dot += xh[s] * o[i];
-        if (mass_is_facet<D, KK>(s, g)) {
-          if constexpr (C::NF % 2 == 0 && D == 3) {
-            if (i % 2 == 0 && fsrow)
-              *reinterpret_cast<double2*>(fsrow + s) = make_double2(o[i] * sfac, o[i + 1] * sfac);
-          } else {
-            if (fsrow) fsrow[s] = o[i] * sfac;
-          }
-        } else {
-          const int t = mass_int_row<D, KK>(s, g);
-          if (valid && t < C::NINT) out[off + e * C::NINT + t] = o[i] * sint;
-        }
+        mass_store<D, KK>(s, g, o[jt][i], i % 2 == 0 && i < 3 ? o[jt][i + 1] : 0.0, sfac, sint, fok, fsrow, valid,
+                          irow, trash);
       }
     }
   }
@@ -695,7 +772,7 @@ __global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, doub
     MassData<D, KK> md;
     mass_load_idx<D>(mesh, wave, lane >> 4, lane & 15, ix);
     mass_load_data<D, KK>(x, mesh, wave, lane >> 4, lane & 15, ix, md);
-    dot = mass_compute<D, KK, MODE>(md, ix, out, fs, mesh, fin, fout, wave, lane);
+    dot = mass_compute<D, KK, MODE>(md, out, fs, fs + 2 * mesh.F * Cfg<D, KK>::NF, mesh, fin, fout, wave, lane);
   }
   if (part) {
     dot = block_sum256(dot);
@@ -728,33 +805,49 @@ __global__ __launch_bounds__(256, 2) void k_mass_lds(const double* __restrict__ 
   for (int i = threadIdx.x; i < NTOT; i += 256) lds[i] = i < NIN ? fin[i] : fout[i - NIN];
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-  const int64_t nw = (mesh.E + 15) / 16;
-  const int64_t stride = (int64_t)gridDim.x * 4;
-  int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  // Each XCD (blocks are dealt round-robin over the 8) walks a contiguous
+  // range of batches, so that elements sharing a facet, mostly close in
+  // numbering, read its rows through the same L2.
+  const int nx = gridDim.x % 8 == 0 ? 8 : 1;
+  const int64_t xcd = blockIdx.x % nx;
+  const int64_t nw_all = (mesh.E + 15) / 16;
+  const int64_t nw = nw_all * (xcd + 1) / nx;  // end of this XCD's range
+  const int64_t stride = (int64_t)(gridDim.x / nx) * 4;
+  int64_t wave = nw_all * xcd / nx + (int64_t)(blockIdx.x / nx) * 4 + (threadIdx.x >> 6);
   double dot = 0.0;
-  // (a wave past the last batch loads nothing and skips the loop)
-  MassIdx ia, ib;
-  MassData<D, KK> da;
-  mass_load_idx<D>(mesh, wave, g, c, ia);
-  mass_load_data<D, KK>(x, mesh, wave, g, c, ia, da);
-  mass_load_idx<D>(mesh, wave + stride, g, c, ib);
-  for (; wave < nw; wave += stride) {
-    MassData<D, KK> dn;
-    MassIdx ic;
-    const bool more = wave + stride < nw;
-    if (more) {
-      mass_load_data<D, KK>(x, mesh, wave + stride, g, c, ib, dn);
-      mass_load_idx<D>(mesh, wave + 2 * stride, g, c, ic);
-    }
-    // opaque base: keeps the fragment reads inside the loop instead of
-    // hoisting all of them into registers
-    int base = 0;
-    asm volatile("" : "+s"(base));
-    dot += mass_compute<D, KK, MODE>(da, ia, out, fs, mesh, lds + base, lds + base + NIN, wave, lane);
-    if (more) {
-      da = dn;
-      ia = ib;
-      ib = ic;
+  // Two register sets alternate (no copy between them).  Every load and
+  // store is issued unconditionally (prefetches past the last batch read
+  // clamped, in-range addresses; a batch past the end computes zeros and
+  // stores them to the trash slot), and the prologue issues the stores of
+  // one batch to the trash slot, so the loop is entered with the same
+  // vector-memory history as it repeats with: the wait at the top (for the
+  // facet ids that address the next gather) then lets the previous batch's
+  // stores stay in flight.  There is no exit between a prefetch and its use,
+  // which would let the compiler sink the prefetch to the use.
+  double* const trash = fs + 2 * mesh.F * C::NF;
+  MassIdx ib;
+  MassData<D, KK> da, db;
+  if (wave < nw) {
+    mass_load_idx<D>(mesh, wave, g, c, ib);
+    mass_load_data<D, KK>(x, mesh, wave, g, c, ib, da);
+    mass_load_idx<D>(mesh, wave + stride, g, c, ib);
+    asm volatile("" ::: "memory");  // the dummy stores follow the loads
+    mass_dummy_stores<C::NK>(trash);
+    while (true) {
+      mass_load_data<D, KK>(x, mesh, wave + stride, g, c, ib, db);
+      mass_load_idx<D>(mesh, wave + 2 * stride, g, c, ib);
+      // opaque base: keeps the fragment reads inside the loop instead of
+      // hoisting all of them into registers
+      int base = 0;
+      asm volatile("" : "+s"(base));
+      dot += mass_compute<D, KK, MODE>(da, out, fs, trash, mesh, lds + base, lds + base + NIN, wave, lane);
+      mass_load_data<D, KK>(x, mesh, wave + 2 * stride, g, c, ib, da);
+      mass_load_idx<D>(mesh, wave + 3 * stride, g, c, ib);
+      asm volatile("" : "+s"(base));
+      dot += mass_compute<D, KK, MODE>(db, out, fs, trash, mesh, lds + base, lds + base + NIN, wave + stride,
+                                       lane, wave + stride < nw);
+      wave += 2 * stride;
+      if (wave >= nw) break;
     }
   }
   if (part) {
