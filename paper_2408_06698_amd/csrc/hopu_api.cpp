@@ -459,18 +459,21 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
       prof_idx.push_back(ctx->ev_used);
       np = mass_raw(ctx, 0, ctx->p, ctx->q, fl, true, true);
       vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
-      vec_axpy2(s, x, ctx->r, ctx->p, ctx->q, ctx->slot, nfl, n, ctx->sc, fl);
+      vec_rupdate(s, ctx->r, ctx->q, ctx->slot, nfl, n, ctx->sc, fl);
       np = mass_raw(ctx, 1, ctx->r, ctx->z, fl, true, true);
       vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_BETA, 0.0, nullptr);
-      vec_xpay(s, ctx->p, ctx->z, ctx->slot, nfl, n, ctx->sc, fl);
+      vec_xpay(s, x, ctx->p, ctx->z, ctx->slot, nfl, n, ctx->sc, fl);
     }
     it += chunk;
     HCHECK(hipMemcpyAsync(ctx->hflag, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HCHECK(hipStreamSynchronize(s));
     if (ctx->hflag[0]) { conv = true; break; }
   }
-  HCHECK(hipGetLastError());
   const int done = ctx->hflag[1];
+  // the iteration that converged skipped its k_xpay, and with it its x
+  // update (none to make up when the initial residual already met rtol)
+  if (conv && done > 0) vec_xfinal(s, x, ctx->p, n, ctx->sc);
+  HCHECK(hipGetLastError());
   // launches queued after convergence returned at once: keep them out of the
   // per-kernel timing
   if (ctx->prof)

@@ -10,11 +10,14 @@ void vec_dot(hipStream_t s, const double* a, const double* b, int64_t n, double*
 void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag, int op, double arg,
                 double* dst);
 // q, z, and q in vec_sub_fs are unassembled: facet rows [0, nfl) come from the
-// facet-side buffer fs ([2][nfl]), interior rows from the vector itself
-void vec_axpy2(hipStream_t s, double* x, double* r, const double* p, const double* q, const double* fs, int64_t nfl,
-               int64_t n, const double* sc, const int* flag);
-void vec_xpay(hipStream_t s, double* p, const double* z, const double* fs, int64_t nfl, int64_t n, const double* sc,
-              const int* flag);
+// facet-side buffer fs ([2][nfl]), interior rows from the vector itself.
+// PCG updates: r -= alpha q; then x += alpha p, p = z + beta p; and, after
+// convergence, the last x += alpha p.
+void vec_rupdate(hipStream_t s, double* r, const double* q, const double* fs, int64_t nfl, int64_t n,
+                 const double* sc, const int* flag);
+void vec_xpay(hipStream_t s, double* x, double* p, const double* z, const double* fs, int64_t nfl, int64_t n,
+              const double* sc, const int* flag);
+void vec_xfinal(hipStream_t s, double* x, const double* p, int64_t n, const double* sc);
 void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, const double* fs, int64_t nfl,
                 int64_t n);
 void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n);

@@ -74,25 +74,33 @@ __device__ __forceinline__ double fs_row(const double* __restrict__ v, const dou
   return i < nfl ? fs[i] + fs[nfl + i] : v[i];
 }
 
-// x += alpha p; r -= alpha q (q unassembled)
-__global__ void k_axpy2(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-                        const double* __restrict__ q, const double* __restrict__ fs, int64_t nfl, int64_t n,
-                        const double* sc, const int* flag) {
+// r -= alpha q (q unassembled)
+__global__ void k_rupdate(double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ fs,
+                          int64_t nfl, int64_t n, const double* sc, const int* flag) {
   if (*flag) return;
   const double al = sc[SC_ALPHA];
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    x[i] += al * p[i];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     r[i] -= al * fs_row(q, fs, nfl, i);
+}
+
+// x += alpha p, then p = z + beta p (z unassembled): the solution update of
+// an iteration rides on the direction update that reads p anyway
+__global__ void k_xpay(double* __restrict__ x, double* __restrict__ p, const double* __restrict__ z,
+                       const double* __restrict__ fs, int64_t nfl, int64_t n, const double* sc, const int* flag) {
+  if (*flag) return;
+  const double al = sc[SC_ALPHA], be = sc[SC_BETA];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double pi = p[i];
+    x[i] += al * pi;
+    p[i] = fs_row(z, fs, nfl, i) + be * pi;
   }
 }
 
-// p = z + beta p (z unassembled)
-__global__ void k_xpay(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ fs,
-                       int64_t nfl, int64_t n, const double* sc, const int* flag) {
-  if (*flag) return;
-  const double be = sc[SC_BETA];
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    p[i] = fs_row(z, fs, nfl, i) + be * p[i];
+// x += alpha p (the update of the iteration that converged, whose k_xpay was
+// skipped)
+__global__ void k_xfinal(double* __restrict__ x, const double* __restrict__ p, int64_t n, const double* sc) {
+  const double al = sc[SC_ALPHA];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) x[i] += al * p[i];
 }
 
 // r = b - q (q unassembled)
@@ -139,13 +147,16 @@ void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag
                 double* dst) {
   hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, s, part, np, sc, flag, op, arg, dst);
 }
-void vec_axpy2(hipStream_t s, double* x, double* r, const double* p, const double* q, const double* fs, int64_t nfl,
-               int64_t n, const double* sc, const int* flag) {
-  hipLaunchKernelGGL(k_axpy2, dim3(grid_for(n)), dim3(256), 0, s, x, r, p, q, fs, nfl, n, sc, flag);
+void vec_rupdate(hipStream_t s, double* r, const double* q, const double* fs, int64_t nfl, int64_t n,
+                 const double* sc, const int* flag) {
+  hipLaunchKernelGGL(k_rupdate, dim3(grid_for(n)), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag);
 }
-void vec_xpay(hipStream_t s, double* p, const double* z, const double* fs, int64_t nfl, int64_t n, const double* sc,
-              const int* flag) {
-  hipLaunchKernelGGL(k_xpay, dim3(grid_for(n)), dim3(256), 0, s, p, z, fs, nfl, n, sc, flag);
+void vec_xpay(hipStream_t s, double* x, double* p, const double* z, const double* fs, int64_t nfl, int64_t n,
+              const double* sc, const int* flag) {
+  hipLaunchKernelGGL(k_xpay, dim3(grid_for(n)), dim3(256), 0, s, x, p, z, fs, nfl, n, sc, flag);
+}
+void vec_xfinal(hipStream_t s, double* x, const double* p, int64_t n, const double* sc) {
+  hipLaunchKernelGGL(k_xfinal, dim3(grid_for(n)), dim3(256), 0, s, x, p, n, sc);
 }
 void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, const double* fs, int64_t nfl,
                 int64_t n) {

@@ -23,6 +23,15 @@ def test_mass_solve(cfg, n, k):
     assert e <= 1e-12
 
 
+def test_mass_solve_zero_rhs():
+    # the initial residual already meets rtol: no iteration, no update
+    mesh, sp, x, c = case(2, (4, 3, 3), 3, noise=1e-3)
+    h = gpu_space(mesh, 3)
+    h.mass_solve(dev(O.residual(sp, x, 2)), rtol=1e-13)  # leaves solver scalars behind
+    w, its = h.mass_solve(dev(np.zeros(sp.n_dof)), rtol=1e-13)
+    assert its == 0 and not host(w).any()
+
+
 def test_mass_solve_warm_start_and_noconv():
     mesh, sp, x, c = case(2, (4, 3, 3), 3, noise=1e-3)
     h = gpu_space(mesh, 3)
