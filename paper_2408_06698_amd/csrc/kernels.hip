@@ -480,6 +480,14 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
 // gather), then the gathered rows and the element's geometry.  The hardware
 // retires vector-memory loads in order, so a load issued inside the compute
 // phase would also wait for every prefetch issued before it.
+// Table fragments are read MASS_PF steps ahead of the MFMAs that use them;
+// the fences keep the scheduler from moving the reads back down to their
+// uses (which would expose the LDS latency at every step).
+#ifndef MASS_PF
+#define MASS_PF 2
+#endif
+#define MASS_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
+
 // Row order of the mass kernels (the tables follow it): at step s, lane
 // group g holds row s of facet g while s < NF and g <= d; every other slot,
 // taken in (s, g) order, holds the next interior row.  A lane therefore
@@ -632,20 +640,24 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
   double y[C::NMT][4];
   {
     d4 acc[C::NMT];
-    double a[2][C::NMT];
+    double a[MASS_PF + 1][C::NMT];
 #pragma unroll
-    for (int mt = 0; mt < C::NMT; ++mt) {
-      acc[mt] = vzero<d4>();
-      a[0][mt] = fi[(mt * C::NK) * 64 + lane];
-    }
+    for (int mt = 0; mt < C::NMT; ++mt) acc[mt] = vzero<d4>();
+#pragma unroll
+    for (int kk = 0; kk < MASS_PF && kk < C::NK; ++kk)
+#pragma unroll
+      for (int mt = 0; mt < C::NMT; ++mt) a[kk][mt] = fi[(mt * C::NK + kk) * 64 + lane];
 #pragma unroll
     for (int kk = 0; kk < C::NK; ++kk) {
-      if (kk + 1 < C::NK) {
+      if (kk + MASS_PF < C::NK) {
 #pragma unroll
-        for (int mt = 0; mt < C::NMT; ++mt) a[(kk + 1) % 2][mt] = fi[(mt * C::NK + kk + 1) * 64 + lane];
+        for (int mt = 0; mt < C::NMT; ++mt)
+          a[(kk + MASS_PF) % (MASS_PF + 1)][mt] = fi[(mt * C::NK + kk + MASS_PF) * 64 + lane];
       }
+      MASS_SCHED_FENCE();
 #pragma unroll
-      for (int mt = 0; mt < C::NMT; ++mt) acc[mt] = M::mma(a[kk % 2][mt], xh[kk], acc[mt]);
+      for (int mt = 0; mt < C::NMT; ++mt) acc[mt] = M::mma(a[kk % (MASS_PF + 1)][mt], xh[kk], acc[mt]);
+      MASS_SCHED_FENCE();
     }
 #pragma unroll
     for (int mt = 0; mt < C::NMT; ++mt)
@@ -713,20 +725,24 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
   double* const irow = out + off + (valid ? e : 0) * C::NINT;
   d4 o[C::NJT];
   {
-    double b[2][C::NJT];
+    double b[MASS_PF + 1][C::NJT];
 #pragma unroll
-    for (int jt = 0; jt < C::NJT; ++jt) {
-      o[jt] = vzero<d4>();
-      b[0][jt] = fo[(jt * C::NMQ) * 64 + lane];
-    }
+    for (int jt = 0; jt < C::NJT; ++jt) o[jt] = vzero<d4>();
+#pragma unroll
+    for (int rq = 0; rq < MASS_PF && rq < C::NMQ; ++rq)
+#pragma unroll
+      for (int jt = 0; jt < C::NJT; ++jt) b[rq][jt] = fo[(jt * C::NMQ + rq) * 64 + lane];
 #pragma unroll
     for (int rq = 0; rq < C::NMQ; ++rq) {
-      if (rq + 1 < C::NMQ) {
+      if (rq + MASS_PF < C::NMQ) {
 #pragma unroll
-        for (int jt = 0; jt < C::NJT; ++jt) b[(rq + 1) % 2][jt] = fo[(jt * C::NMQ + rq + 1) * 64 + lane];
+        for (int jt = 0; jt < C::NJT; ++jt)
+          b[(rq + MASS_PF) % (MASS_PF + 1)][jt] = fo[(jt * C::NMQ + rq + MASS_PF) * 64 + lane];
       }
+      MASS_SCHED_FENCE();
 #pragma unroll
-      for (int jt = 0; jt < C::NJT; ++jt) o[jt] = M::mma(b[rq % 2][jt], y[rq / 4][rq % 4], o[jt]);
+      for (int jt = 0; jt < C::NJT; ++jt) o[jt] = M::mma(b[rq % (MASS_PF + 1)][jt], y[rq / 4][rq % 4], o[jt]);
+      MASS_SCHED_FENCE();
     }
   }
 #pragma unroll

@@ -1,10 +1,29 @@
-"""Summarise a rocprofv3 kernel-trace database (rocpd SQLite) into a short
-text table: per kernel name, launches, average/total duration."""
+"""Summaries of rocprofv3 results (rocpd SQLite databases) as short text.
+
+    python -m paper_2408_06698_amd.rocpd_summary trace <db> [top]
+        per kernel name: launches, average / busy-average / max / total duration
+    python -m paper_2408_06698_amd.rocpd_summary traffic <fetch_db> <write_db> <kernels.hip>
+        HBM bytes per launch from a FETCH_SIZE and a WRITE_SIZE run, scaled by
+        what the counters read for the largest plain device copy in the runs
+"""
+import hashlib
 import sqlite3
+import statistics
 import sys
 
+# kernel keys of the traffic summary: substring of the demangled name
+TRAFFIC_KERNELS = [
+    ("mass", "k_mass_lds<3, 3, 0>"),
+    ("prec", "k_mass_lds<3, 3, 1>"),
+    ("elem", "k_elem<double, 3, 3>"),
+    ("elem_fp32", "k_elem<float, 3, 3>"),
+    ("modal", "k_modal<double, 3, 3>"),
+    ("rupdate", "k_rupdate("),
+    ("xpay", "k_xpay("),
+]
 
-def main(db, top=20):
+
+def trace(db, top=20):
     c = sqlite3.connect(db)
     rows = c.execute("select name, count(*), avg(duration), sum(duration), min(duration), max(duration) "
                      "from kernels group by name order by sum(duration) desc").fetchall()
@@ -19,5 +38,57 @@ def main(db, top=20):
               f"{100*r[3]/tot:6.2f}  {r[0][:110]}")
 
 
+def _counter(db, name):
+    """({kernel name: [per-dispatch values]}, value of the last dispatch) of
+    one counter (KiB)."""
+    c = sqlite3.connect(db)
+    out = {}
+    last = None
+    for k, v in c.execute("select kernel_name, value from counters_collection where counter_name = ? "
+                          "order by dispatch_id", (name,)):
+        out.setdefault(k, []).append(float(v))
+        last = (k, float(v))
+    return out, last
+
+
+def kernels_sha(src):
+    text = open(src).read()
+    body = text[text.index("namespace hopu {"):text.index("// " + "-" * 66 + " launchers")]
+    return hashlib.sha256(body.encode()).hexdigest()[:16]
+
+
+def traffic(fetch_db, write_db, src):
+    (fetch, flast), (write, wlast) = _counter(fetch_db, "FETCH_SIZE"), _counter(write_db, "WRITE_SIZE")
+    # calibration: the last dispatch of each run, the 1 GiB device-to-device
+    # copy that bench.py --copy-calib makes after everything else
+    copy_bytes = 1 << 30
+    assert "copy" in flast[0].lower() and "copy" in wlast[0].lower(), (flast[0], wlast[0])
+    fmax, wmax = flast[1], wlast[1]
+    fs, ws = copy_bytes / (fmax * 1024), copy_bytes / (wmax * 1024)
+    print(f"# calibration: 1 GiB device copy ({flast[0]}) reads back FETCH_SIZE {fmax:.1f} KiB, "
+          f"WRITE_SIZE {wmax:.1f} KiB")
+    print(f"#   -> fetch scale {fs:.4f}, write scale {ws:.4f} (bytes = KiB * 1024 * scale)")
+    print("# kernels_sha: SHA-256 (16 hex) of kernels.hip from 'namespace hopu {' to the launchers marker")
+    print("# per-launch medians over launches that did work (> 5% of the kernel's largest)")
+    print(f"kernels_sha = {kernels_sha(src)}")
+    print(f"fetch_scale = {fs:.6f}")
+    print(f"write_scale = {ws:.6f}")
+    for key, pat in TRAFFIC_KERNELS:
+        fk = [k for k in fetch if pat in k]
+        wk = [k for k in write if pat in k]
+        if not fk or not wk:
+            continue
+        fv = [x for x in fetch[fk[0]] if x > 0.05 * max(fetch[fk[0]])]
+        wv = [x for x in write[wk[0]] if x > 0.05 * max(write[wk[0]])]
+        f, w = statistics.median(fv), statistics.median(wv)
+        print(f"# {key}: FETCH_SIZE {f:.0f} KiB (n={len(fv)}), WRITE_SIZE {w:.0f} KiB (n={len(wv)})")
+        print(f"{key}_bytes_per_launch = {f * 1024 * fs + w * 1024 * ws:.0f}")
+
+
 if __name__ == "__main__":
-    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 20)
+    if sys.argv[1] == "trace":
+        trace(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 20)
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4])
+    else:
+        trace(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 20)
