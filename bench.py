@@ -32,6 +32,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-projection", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after the run, copy a 1 GiB device buffer (reference for HBM counters)")
     return ap.parse_args()
@@ -213,6 +214,23 @@ def main():
         "kernel_ms_total": {kk: v[1] for kk, v in prof64.items()},
         "kernel_launches": {kk: v[0] for kk, v in prof64.items()},
     }
+    if not args.no_projection:
+        # projection step (paper section 2.3, eq. (MCS_step2)) of the state
+        # after the timed substeps, whose divergence the convection broke
+        un = h.zeros()
+        h.project(u64, un, rtol=1e-13)            # set-up (A^-1) and warm-up
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        _, its = h.project(u64, un, rtol=1e-13)
+        b.record(stream)
+        torch.cuda.synchronize()
+        _, div0, _ = h.diagnostics(u64)
+        _, div1, _ = h.diagnostics(un)
+        out_proj = {"ms": a.elapsed_time(b), "cg_iters": its, "rtol": 1e-13,
+                    "div_l2_before": div0, "div_l2_after": div1,
+                    "note": "condensed facet-multiplier system, unpreconditioned CG"}
     if not args.no_mixed:
         u32, ms32, prof32 = run(FP32_MFMA, args.steps, 1)
         d = u32 - u64
@@ -220,6 +238,8 @@ def main():
         out["mixed"] = {"value": ndof * args.steps / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
                         "rel_err_vs_fp64_M_norm": err, "dtype": "fp32-mfma contractions, f64 state/PCG",
                         "speedup_substep": ms64 / ms32, "speedup_apply": apply64 / apply32}
+    if not args.no_projection:
+        out["projection"] = out_proj
     if args.copy_calib:
         src = torch.ones(1 << 27, dtype=torch.float64, device=u0.device)
         dst = torch.empty_like(src)

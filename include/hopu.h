@@ -132,6 +132,23 @@ hopu_status hopu_mass_apply(hopu_ctx ctx, const double* u, double* y);
 hopu_status hopu_mass_solve(hopu_ctx ctx, const double* r, double* w,
                             double rtol, int max_it, int* iters);
 
+/* Projection step of the operator splitting (paper section 2.3, eq.
+ * (MCS_step2), update eq. (UpdateStep) read as u_new = u* - u~): the
+ * hybrid-mixed problem for (u~, p, p^) in the broken velocity space x
+ * P^{k-1} per element x P^k per facet (walls included) is condensed onto the
+ * facet multipliers p^ and solved by CG (FP64) to
+ * ||r|| <= rtol (||g||^2 + ||u*_F||^2)^1/2 (g the condensed right-hand side,
+ * u*_F the facet block of u*, in the same units), then
+ * u~ is recovered element by element.  u_new is divergence-free and lies in
+ * V_h.  ustar, unew: dev [n_dof], distinct (else HOPU_EINVAL).  rtol > 0,
+ * max_it >= 1; *iters (host, nullable) receives the CG iteration count.
+ * The first call allocates the step's workspace (E dim P^{k-1}^2 + 5 (F + W)
+ * n_f doubles) and computes the element matrices A^-1; later calls allocate
+ * nothing.  Syncs.  HOPU_ENOCONV if max_it is reached (unew is still
+ * written from the last iterate). */
+hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* unew,
+                         double rtol, int max_it, int* iters);
+
 /* n_steps explicit substeps u <- u - dt M^-1 r(u), in place on u (dev).
  * diag_dev (dev double [n_steps+1][5], nullable): per state energy
  * 1/2 u.Mu, ||div u||_L2, upwind dissipation, PCG iterations of the solve

@@ -14,6 +14,7 @@
 #include "aux.hpp"
 #include "host_tables.hpp"
 #include "kernels.hpp"
+#include "proj.hpp"
 #include "launch.hpp"
 #include "launch_events.hpp"
 #include "vec.hpp"
@@ -43,6 +44,11 @@ struct hopu_ctx_s {
   double* part = nullptr;   // partial sums (max(NPART, nb, waves))
   int64_t npart = 0;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *rc = nullptr;
+  // projection step (tables at create; workspace on the first hopu_project)
+  const double *proj_b = nullptr, *proj_bt = nullptr, *proj_kab = nullptr;
+  const int32_t* mfid = nullptr;
+  double *ainv = nullptr, *ph = nullptr, *pr = nullptr, *pp = nullptr, *pfs = nullptr;
+  bool proj_ready = false;
   double* stage = nullptr;  // 16-byte aligned copy of a mass-kernel input that is not
   double* wh[3] = {nullptr, nullptr, nullptr};  // previous substep solutions (newest first)
   double* sc = nullptr;
@@ -261,6 +267,18 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(up64(&ctx->mass_out, f64.mass_out));
     TRY(up64(&ctx->prec_in, f64.prec_in));
     TRY(up64(&ctx->prec_out, f64.prec_out));
+    TRY(up64(&ctx->proj_b, f64.proj_b));
+    TRY(up64(&ctx->proj_bt, f64.proj_bt));
+    TRY(up64(&ctx->proj_kab, f64.proj_kab));
+    {
+      // multiplier block of every element facet: interior facets keep their
+      // id, wall facets follow in element order
+      std::vector<int32_t> mf(ctx->mesh.fid);
+      int64_t w = 0;
+      for (auto& v : mf)
+        if (v < 0) v = (int32_t)(ctx->mesh.F + w++);
+      TRY(upload(ctx, &ctx->mfid, mf));
+    }
     ctx->vol_dV64 = a.vol_dV;
     // workspaces
     const int64_t E = n_elems, n = ctx->n_dof;
@@ -271,7 +289,7 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     // element slots (E * nfl) or the mass kernels' facet-side rows (2 F nf
     // <= E nfl) followed by their trash slots
     TRY(dev_alloc(ctx, &ctx->slot, (size_t)E * s.nfl + 128));
-    ctx->npart = std::max<int64_t>(std::max<int64_t>(NPART, ctx->bat.nb), (E + 15) / 16);
+    ctx->npart = std::max<int64_t>(std::max<int64_t>(2 * NPART, ctx->bat.nb), (E + 15) / 16);
     TRY(dev_alloc(ctx, &ctx->part, (size_t)ctx->npart));
     TRY(dev_alloc(ctx, &ctx->r, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->z, (size_t)n));
@@ -483,6 +501,79 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
   if (iters) *iters = done;
   if (!conv) {
     ctx->err = "PCG did not reach rtol within max_it iterations";
+    return HOPU_ENOCONV;
+  }
+  return HOPU_OK;
+}
+
+// Projection step (paper section 2.3, eq. (MCS_step2); u_new = u* - u~):
+// CG on the condensed multiplier system S_p p^ = g (unpreconditioned), then
+// the element-wise recovery of u~.
+extern "C" hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* unew, double rtol, int max_it,
+                                    int* iters) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!ustar || !unew) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  if (ustar == unew) return fail(ctx, HOPU_EINVAL, "u* and u_new must be different vectors");
+  if (!(rtol > 0.0) || max_it < 1) return fail(ctx, HOPU_EINVAL, "rtol must be > 0 and max_it >= 1");
+  hipStream_t s = ctx->stream;
+  const int nQ = ctx->sz.dim == 2 ? ctx->k * (ctx->k + 1) / 2 : ctx->k * (ctx->k + 1) * (ctx->k + 2) / 6;
+  const int64_t FW = ctx->mesh.F + ctx->mesh.W;
+  const int64_t nh = FW * ctx->sz.nf;
+  ProjDev pj{ctx->mfid, FW, ctx->mass_in, ctx->prec_in, ctx->prec_out, ctx->proj_b, ctx->proj_bt, nullptr};
+  if (!ctx->proj_ready) {
+    hopu_status st;
+    if ((st = dev_alloc(ctx, &ctx->ainv, (size_t)ctx->mesh.E * nQ * nQ)) ||
+        (st = dev_alloc(ctx, &ctx->ph, (size_t)nh)) || (st = dev_alloc(ctx, &ctx->pr, (size_t)nh)) ||
+        (st = dev_alloc(ctx, &ctx->pp, (size_t)nh)) || (st = dev_alloc(ctx, &ctx->pfs, (size_t)2 * nh)))
+      return st;
+    // wall facets have one side: their second contribution stays zero
+    HCHECK(hipMemsetAsync(ctx->pfs, 0, (size_t)2 * nh * sizeof(double), s));
+    DISPATCH(ctx->dim, ctx->k, { launch_proj_ainv<D, KK>(s, ctx->dm, ctx->proj_kab, ctx->ainv); });
+    HCHECK(hipGetLastError());
+    ctx->proj_ready = true;
+  }
+  pj.ainv = ctx->ainv;
+  int* fl = ctx->flag;
+  HCHECK(hipMemsetAsync(fl, 0, 4 * sizeof(int), s));
+  HCHECK(hipMemsetAsync(ctx->ph, 0, (size_t)nh * sizeof(double), s));
+  // r = g, p = r
+  DISPATCH(ctx->dim, ctx->k, { launch_proj<D, KK>(s, 1, nullptr, ustar, ctx->pfs, ctx->dm, pj, nullptr); });
+  launch_fs_assemble(s, ctx->pr, ctx->pfs, nh, nullptr);
+  vec_copy(s, ctx->pp, ctx->pr, nh);
+  // ||r|| <= rtol (||g||^2 + ||u*_F||^2)^1/2: the facet block of u* (same
+  // units as g) keeps the criterion meaningful when u* is (nearly)
+  // divergence-free and g is rounding noise
+  vec_dot(s, ctx->pr, ctx->pr, nh, ctx->part, nullptr);
+  vec_dot(s, ustar, ustar, ctx->mesh.F * ctx->sz.nf, ctx->part + NPART, nullptr);
+  vec_scalar(s, ctx->part, 2 * NPART, ctx->sc, fl, OP_SET_TOL, rtol, nullptr);
+  vec_dot(s, ctx->pr, ctx->pr, nh, ctx->part, nullptr);
+  vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_SET_RZ, 0.0, nullptr);
+  int it = 0;
+  bool conv = false;
+  while (it < max_it) {
+    const int chunk = std::min(16, max_it - it);
+    for (int c = 0; c < chunk; ++c) {
+      int np = 0;
+      DISPATCH(ctx->dim, ctx->k, { np = launch_proj<D, KK>(s, 0, ctx->pp, nullptr, ctx->pfs, ctx->dm, pj, ctx->part); });
+      vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
+      vec_rupdate(s, ctx->pr, ctx->pr, ctx->pfs, nh, nh, ctx->sc, fl);  // r -= alpha S_p p
+      vec_dot(s, ctx->pr, ctx->pr, nh, ctx->part, fl);
+      vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_BETA, 0.0, nullptr);
+      vec_xpay(s, ctx->ph, ctx->pp, ctx->pr, ctx->pfs, 0, nh, ctx->sc, fl);  // x += alpha p; p = r + beta p
+    }
+    it += chunk;
+    HCHECK(hipMemcpyAsync(ctx->hflag, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    if (ctx->hflag[0]) { conv = true; break; }
+  }
+  const int done = ctx->hflag[1];
+  if (conv && done > 0) vec_xfinal(s, ctx->ph, ctx->pp, nh, ctx->sc);
+  // u_new = u* - u~
+  DISPATCH(ctx->dim, ctx->k, { launch_proj<D, KK>(s, 2, ctx->ph, ustar, unew, ctx->dm, pj, nullptr); });
+  HCHECK(hipGetLastError());
+  if (iters) *iters = done;
+  if (!conv) {
+    ctx->err = "projection CG did not reach rtol within max_it iterations";
     return HOPU_ENOCONV;
   }
   return HOPU_OK;

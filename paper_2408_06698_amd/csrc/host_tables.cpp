@@ -377,6 +377,24 @@ bool make_ref_tables(int dim, int k, RefTables& t, std::string& err) {
   }
   t.D.assign(db.D.begin(), db.D.end());
   t.Dinv.assign(db.Dinv.begin(), db.Dinv.end());
+  // projection: divergence moments of the modal basis against P^{k-1}
+  // (the volume rule integrates degree 2k-2 exactly)
+  {
+    const int nQ = dim_P(dim, k - 1);
+    t.nQ = nQ;
+    t.Bm.assign((size_t)nQ * s.nm, 0.0);
+    std::vector<ld> qv(nQ), qg(nQ * dim);
+    std::vector<ld> acc((size_t)nQ * s.nm, 0.0L);
+    for (int q = 0; q < s.nqv; ++q) {
+      dubiner(dim, k, &vp[q * dim], val.data(), grad.data());
+      dubiner(dim, k - 1, &vp[q * dim], qv.data(), qg.data());
+      for (int be = 0; be < nQ; ++be)
+        for (int a = 0; a < dim; ++a)
+          for (int al = 0; al < nP; ++al)
+            acc[(size_t)be * s.nm + modal_row(dim, a, al)] += vw[q] * grad[al * dim + a] * qv[be];
+    }
+    for (size_t i = 0; i < acc.size(); ++i) t.Bm[i] = (double)acc[i];
+  }
   return true;
 }
 
@@ -442,6 +460,37 @@ void make_frag_tables(const RefTables& t, RowMap rm, FragTables& f) {
         f.mass_out[(jt * fd.NMQ + rq) * 64 + l] = Dinv(a, al, j);
         f.prec_out[(jt * fd.NMQ + rq) * 64 + l] = D(j, a, al);
       }
+  // projection: Bm (rows beta, K = modal rows in the output-tile order of the
+  // first contraction) and Bm^T (rows rho, K = beta in the output order of
+  // the Bm contraction), f64 register layout
+  {
+    const int nQ = t.nQ, NBT = proj_nbt(nQ), NQK = proj_nqk(nQ);
+    auto Bm = [&](int be, int rho) { return t.Bm[(size_t)be * s.nm + rho]; };
+    f.proj_b.assign((size_t)NBT * fd.NMQ * 64, 0.0);
+    for (int bt = 0; bt < NBT; ++bt)
+      for (int rq = 0; rq < fd.NMQ; ++rq)
+        for (int l = 0; l < 64; ++l) {
+          const int be = 16 * bt + (l & 15), rho = 16 * (rq / 4) + rowof(rq % 4, l >> 4);
+          if (be < nQ && rho < s.nm) f.proj_b[((size_t)bt * fd.NMQ + rq) * 64 + l] = Bm(be, rho);
+        }
+    f.proj_bt.assign((size_t)fd.NMT * NQK * 64, 0.0);
+    for (int mt = 0; mt < fd.NMT; ++mt)
+      for (int kk = 0; kk < NQK; ++kk)
+        for (int l = 0; l < 64; ++l) {
+          const int rho = 16 * mt + (l & 15), be = 16 * (kk / 4) + rowof(kk % 4, l >> 4);
+          if (be < nQ && rho < s.nm) f.proj_bt[((size_t)mt * NQK + kk) * 64 + l] = Bm(be, rho);
+        }
+    f.proj_kab.assign((size_t)dim * dim * nQ * nQ, 0.0);
+    for (int a = 0; a < dim; ++a)
+      for (int b = 0; b < dim; ++b)
+        for (int be = 0; be < nQ; ++be)
+          for (int ga = 0; ga < nQ; ++ga) {
+            long double acc = 0.0L;
+            for (int al = 0; al < nP; ++al)
+              acc += (long double)Bm(be, modal_row(dim, a, al)) * Bm(ga, modal_row(dim, b, al));
+            f.proj_kab[(((size_t)a * dim + b) * nQ + be) * nQ + ga] = (double)acc;
+          }
+  }
   // volume
   f.vol_V.assign(fd.NQVT * fd.NPK * 64, 0.0);
   f.vol_dV.assign(fd.NQVT * dim * fd.NPK * 64, 0.0);

@@ -72,6 +72,9 @@ struct RefTables {
   std::vector<double> D, Dinv;   // [n][n] (dual x modal (a,alpha)) and inverse
   std::vector<double> xv;        // [nqv][dim] volume points
   std::vector<double> sf;        // [nqf][dim-1] facet points
+  // projection step: Q_h = P^{k-1}, Bm[beta][rho(a, alpha)] = int_T^ d_a p_alpha q_beta
+  int nQ = 0;
+  std::vector<double> Bm;        // [nQ][nm]
 };
 bool make_ref_tables(int dim, int k, RefTables& t, std::string& err);
 
@@ -117,7 +120,14 @@ struct FragTables {
   std::vector<double> mass_out;  // [NJT][NMQ][64] Dinv^T with k = rho quads
   std::vector<double> prec_in;   // [NMT][NK][64]  D^T rows rho, k = j
   std::vector<double> prec_out;  // [NJT][NMQ][64] D with k = rho quads
+  // projection step (f64 layouts only)
+  std::vector<double> proj_b;    // [NBT][NMQ][64]  Bm: rows beta, k = rho quads
+  std::vector<double> proj_bt;   // [NMT][NQK][64]  Bm^T: rows rho, k = beta
+  std::vector<double> proj_kab;  // [dim][dim][nQ][nQ]  sum_alpha Bm[.][rho(a,alpha)] Bm[.][rho(b,alpha)]
 };
+// tiles of the projection tables
+inline int proj_nbt(int nQ) { return (nQ + 15) / 16; }
+inline int proj_nqk(int nQ) { return (nQ + 3) / 4; }
 struct FragDims {
   int NMT, NK, NQVT, NPK, NAT, NQFT, NFJT, NFK, NJT, NMQ;
 };

@@ -32,6 +32,8 @@ struct Cfg {
   static constexpr int NFK = 4 * NFJT;
   static constexpr int NJT = (N + 15) / 16;
   static constexpr int NMQ = 4 * NMT;
+  // projection step: dim P^{k-1}
+  static constexpr int NQ = D == 2 ? KK * (KK + 1) / 2 : KK * (KK + 1) * (KK + 2) / 6;
 };
 
 

@@ -106,6 +106,14 @@ class Hopu:
                                       C.byref(its)), self.h)
         return w, its.value
 
+    def project(self, ustar, out=None, rtol=1e-13, max_it=20000):
+        """u_new = u* - u~ (projection step); returns (u_new, CG iterations)."""
+        out = self.zeros() if out is None else out
+        its = C.c_int()
+        check(L.lib().hopu_project(self.h, _ptr(_dev(ustar)), _ptr(_dev(out)), float(rtol), int(max_it),
+                                   C.byref(its)), self.h)
+        return out, its.value
+
     def substeps(self, u, dt, n_steps, prec=FP64, diag=False):
         d = torch.zeros((n_steps + 1, 5), dtype=torch.float64, device=self.device) if diag else None
         check(L.lib().hopu_substeps(self.h, _ptr(_dev(u)), float(dt), int(n_steps), prec, _ptr(d)), self.h)
