@@ -70,3 +70,32 @@ def test_fullsize_channel_k5_apply():
     ref = O.residual(sp, x, c["l"], elems=patch)
     _check(host(h.apply(u)), ref, rows_f, rows_i, 1e-12, "apply fp64 k5")
     _check(host(h.apply(u, prec=1)), ref, rows_f, rows_i, 1e-5, "apply fp32 k5")
+
+
+def test_fullsize_projection_properties():
+    # 3D periodic Taylor-Green at the bench size (32^3 x 6 tets, k = 3): the
+    # oracle's direct solve does not fit, so check what the projection must
+    # satisfy at any size: u_new is divergence-free, u~ = u* - u_new is
+    # M-orthogonal to u_new, and projecting again changes nothing
+    from synth.configs import coefficient_noise
+    mesh, field, c = synth.make_config(2)
+    k = c["k"]
+    h = gpu_space(mesh, k)
+    u = h.interpolate(field, n1d=k + 2)
+    u += torch.tensor(coefficient_noise(2, h.n_dof, c["noise"]), device=u.device)
+    h.set_upwind(c["l"])
+    h.substeps(u, 0.05, 1)                         # breaks div u = 0
+    unew, its = h.project(u, rtol=1e-13)
+    _, div0, _ = h.diagnostics(u)
+    _, div1, _ = h.diagnostics(unew)
+    ut = u - unew
+    mu, mt = torch.sqrt(torch.dot(unew, h.mass_apply(unew))), torch.sqrt(torch.dot(ut, h.mass_apply(ut)))
+    orth = float(torch.dot(unew, h.mass_apply(ut)) / (mu * mt))
+    again, its2 = h.project(unew, rtol=1e-13)
+    d = again - unew
+    rel2 = float(torch.sqrt(torch.dot(d, h.mass_apply(d))) / mu)
+    print(f"projection C2: {its} CG its, div {div0:.3e} -> {div1:.3e}, (u_new, u~)_M {orth:.1e}, "
+          f"reprojection {rel2:.1e} ({its2} its)")
+    assert div1 <= 1e-12 * div0
+    assert abs(orth) <= 1e-10
+    assert rel2 <= 1e-11
