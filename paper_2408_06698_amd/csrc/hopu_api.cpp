@@ -33,6 +33,7 @@ struct hopu_ctx_s {
   DevTables<double> tb64;
   DevTables<float> tb32;
   const double *mass_in = nullptr, *mass_out = nullptr, *prec_in = nullptr, *prec_out = nullptr;
+  const float *prec_in32 = nullptr, *prec_out32 = nullptr;  // FP32 preconditioner tables
   const double* vol_dV64 = nullptr;
   double* xyz = nullptr;
   // workspaces
@@ -267,6 +268,8 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(up64(&ctx->mass_out, f64.mass_out));
     TRY(up64(&ctx->prec_in, f64.prec_in));
     TRY(up64(&ctx->prec_out, f64.prec_out));
+    TRY(up32(&ctx->prec_in32, f32.prec_in));
+    TRY(up32(&ctx->prec_out32, f32.prec_out));
     TRY(up64(&ctx->proj_b, f64.proj_b));
     TRY(up64(&ctx->proj_bt, f64.proj_bt));
     TRY(up64(&ctx->proj_kab, f64.proj_kab));
@@ -399,7 +402,8 @@ static hopu_status do_apply(hopu_ctx ctx, const double* u, double* r, int terms,
 // of y plus the facet-side contributions in ctx->slot (the facet rows of y
 // are left untouched).  With `dot`, the per-block partials of x . y go to
 // ctx->part; returns their number.
-static int mass_raw(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag, bool in_loop, bool dot) {
+static int mass_raw(hopu_ctx ctx, int mode, const double* x, double* y, const int* flag, bool in_loop, bool dot,
+                    bool prec32 = false) {
   int np = 0;
   // the 3D kernels read a facet's rows in 16-byte pairs
   if (reinterpret_cast<uintptr_t>(x) % 16 != 0) {
@@ -409,7 +413,8 @@ static int mass_raw(hopu_ctx ctx, int mode, const double* x, double* y, const in
   prof_begin(ctx, in_loop ? (mode == 0 ? PROF_MASS : PROF_PREC) : PROF_PLAIN);
   DISPATCH(ctx->dim, ctx->k, {
     np = launch_mass<D, KK>(ctx->stream, mode, x, y, ctx->slot, ctx->dm, mode == 0 ? ctx->mass_in : ctx->prec_in,
-                            mode == 0 ? ctx->mass_out : ctx->prec_out, flag, dot ? ctx->part : nullptr);
+                            mode == 0 ? ctx->mass_out : ctx->prec_out, flag, dot ? ctx->part : nullptr,
+                            prec32 ? ctx->prec_in32 : nullptr, prec32 ? ctx->prec_out32 : nullptr);
   });
   prof_end(ctx);
   return np;
@@ -447,19 +452,23 @@ extern "C" hopu_status hopu_mass_apply(hopu_ctx ctx, const double* u, double* y)
 }
 
 // PCG on M with R blockdiag(M_T)^-1 R^t; x holds the initial guess.
-static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, int max_it, int* iters) {
+// prec32: the preconditioner's contractions in FP32 MFMA (the mixed-precision
+// substeps); M, the vectors and the inner products stay FP64, so the solution
+// meets the same tolerance
+static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, int max_it, int* iters,
+                       bool prec32 = false) {
   const int64_t n = ctx->n_dof;
   hipStream_t s = ctx->stream;
   int* fl = ctx->flag;
   const int64_t nfl = ctx->mesh.F * ctx->sz.nf;
   HCHECK(hipMemsetAsync(fl, 0, 4 * sizeof(int), s));
   // tolerance from b.Pb
-  int np = mass_raw(ctx, 1, b, ctx->z, nullptr, false, true);
+  int np = mass_raw(ctx, 1, b, ctx->z, nullptr, false, true, prec32);
   vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_SET_TOL, rtol, nullptr);
   // r = b - M x; z = P r (assembled straight into p); p = z
   mass_raw(ctx, 0, x, ctx->q, nullptr, false, false);
   vec_sub_fs(s, ctx->r, b, ctx->q, ctx->slot, nfl, n);
-  np = mass_raw(ctx, 1, ctx->r, ctx->p, nullptr, false, true);
+  np = mass_raw(ctx, 1, ctx->r, ctx->p, nullptr, false, true, prec32);
   launch_fs_assemble(s, ctx->p, ctx->slot, nfl, nullptr);
   vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_SET_RZ, 0.0, nullptr);
   int it = 0;
@@ -478,7 +487,7 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
       np = mass_raw(ctx, 0, ctx->p, ctx->q, fl, true, true);
       vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
       vec_rupdate(s, ctx->r, ctx->q, ctx->slot, nfl, n, ctx->sc, fl);
-      np = mass_raw(ctx, 1, ctx->r, ctx->z, fl, true, true);
+      np = mass_raw(ctx, 1, ctx->r, ctx->z, fl, true, true, prec32);
       vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_BETA, 0.0, nullptr);
       vec_xpay(s, x, ctx->p, ctx->z, ctx->slot, nfl, n, ctx->sc, fl);
     }
@@ -732,7 +741,7 @@ extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_s
     else if (nh == 2) vec_comb3(s, w, wh[0], wh[1], 2.0, -1.0, 0.0, ctx->n_dof);
     else vec_comb3(s, w, wh[0], wh[1], 3.0, -3.0, 1.0, ctx->n_dof);
     int its = 0;
-    st = pcg(ctx, ctx->rc, w, ctx->rtol, ctx->max_it, &its);
+    st = pcg(ctx, ctx->rc, w, ctx->rtol, ctx->max_it, &its, prec == HOPU_FP32_MFMA);
     if (st) return st;
     if (diag_dev) vec_copy_diag(s, diag_dev + (int64_t)(st_i + 1) * 5 + 3, ctx->sc, ctx->flag);
     vec_axpy(s, u, w, -dt, ctx->n_dof);
@@ -939,7 +948,7 @@ extern "C" int64_t hopu_substeps_vjp_workspace(hopu_ctx ctx, int n_steps, int ck
 static hopu_status substep(hopu_ctx ctx, double* u, double* w, double dt, hopu_precision prec) {
   hopu_status st = do_apply(ctx, u, ctx->rc, HOPU_TERM_ALL, prec, nullptr);
   if (st) return st;
-  st = pcg(ctx, ctx->rc, w, ctx->rtol, ctx->max_it, nullptr);
+  st = pcg(ctx, ctx->rc, w, ctx->rtol, ctx->max_it, nullptr, prec == HOPU_FP32_MFMA);
   if (st) return st;
   vec_axpy(ctx->stream, u, w, -dt, ctx->n_dof);
   return HOPU_OK;

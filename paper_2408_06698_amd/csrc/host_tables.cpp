@@ -436,15 +436,20 @@ void make_frag_tables(const RefTables& t, RowMap rm, FragTables& f) {
         if (!rho_inv(rho, a, al) || j >= n) continue;
         f.modal[(mt * fd.NK + kk) * 64 + l] = Dinv(a, al, j);
       }
-  // mass / preconditioner: dual rows in mass_row order, K side (in) and M
-  // side (out: output row m of tile jt sits in register m/4 of group m%4,
-  // i.e. step 4 jt + m/4)
+  // mass / preconditioner: dual rows in mass_row order.  The kernels see the
+  // same layout in both precisions: register i of lane group g holds modal
+  // row 16 mt + 4 i + g after the first contraction and dual step 4 jt + i
+  // after the second.  Output row m of an MFMA tile sits in register m/4 of
+  // group m%4 (f64) or in register m%4 of group m/4 (f32), so the tables'
+  // M rows are permuted accordingly; the K side is the same for both.
+  const bool f32 = rm == ROWMAP_F32;
   f.mass_in.assign(fd.NMT * fd.NK * 64, 0.0);
   f.prec_in.assign(fd.NMT * fd.NK * 64, 0.0);
   for (int mt = 0; mt < fd.NMT; ++mt)
     for (int kk = 0; kk < fd.NK; ++kk)
       for (int l = 0; l < 64; ++l) {
-        int a, al, rho = 16 * mt + (l & 15), j = mass_row(s, kk, l >> 4);
+        const int m = l & 15;
+        int a, al, rho = 16 * mt + (f32 ? 4 * (m % 4) + m / 4 : m), j = mass_row(s, kk, l >> 4);
         if (!rho_inv(rho, a, al) || j < 0) continue;
         f.mass_in[(mt * fd.NK + kk) * 64 + l] = Dinv(a, al, j);
         f.prec_in[(mt * fd.NK + kk) * 64 + l] = D(j, a, al);
@@ -455,7 +460,8 @@ void make_frag_tables(const RefTables& t, RowMap rm, FragTables& f) {
     for (int rq = 0; rq < fd.NMQ; ++rq)
       for (int l = 0; l < 64; ++l) {
         const int m = l & 15;
-        int j = mass_row(s, 4 * jt + m / 4, m % 4), rho = 16 * (rq / 4) + rowof(rq % 4, l >> 4), a, al;
+        const int step = 4 * jt + (f32 ? m % 4 : m / 4), grp = f32 ? m / 4 : m % 4;
+        int j = mass_row(s, step, grp), rho = 16 * (rq / 4) + 4 * (rq % 4) + (l >> 4), a, al;
         if (j < 0 || !rho_inv(rho, a, al)) continue;
         f.mass_out[(jt * fd.NMQ + rq) * 64 + l] = Dinv(a, al, j);
         f.prec_out[(jt * fd.NMQ + rq) * 64 + l] = D(j, a, al);

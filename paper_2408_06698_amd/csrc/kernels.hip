@@ -610,14 +610,18 @@ constexpr int64_t MASS_TRASH_DOUBLES = 128;  // >= 2 + 2 NK for every order
 
 // One batch from registers and the fragment tables; writes the outputs and
 // returns this lane's share of x_T . y_T.
-template <int D, int KK, int MODE>
+// T: the MFMA precision of the two contractions (the FP32 form is used for
+// the preconditioner of the mixed-precision substeps; everything around the
+// contractions stays FP64).
+template <typename T, int D, int KK, int MODE>
 __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
                                                double* __restrict__ out, double* __restrict__ fs,
                                                double* __restrict__ trash, const DevMesh& mesh,
-                                               const double* __restrict__ fi, const double* __restrict__ fo,
+                                               const T* __restrict__ fi, const T* __restrict__ fo,
                                                int64_t wave, int lane, bool live = true) {
   using C = Cfg<D, KK>;
-  using M = MF<double>;
+  using M = MF<T>;
+  using V = typename M::V;
   const int g = lane >> 4, c = lane & 15;
   const int64_t off = mesh.F * C::NF;
   const int64_t e = wave * 16 + c;
@@ -628,21 +632,21 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
   const double sint = MODE == 0 ? md.si : 1.0 / md.si;
   // the lane's facet exists (an interior facet of a real element)
   const bool fok = valid && g <= D && md.ix.fid >= 0;
-  double xh[C::NK];
+  T xh[C::NK];
 #pragma unroll
   for (int kk = 0; kk < C::NK; ++kk) {
     const bool ok = mass_is_facet<D, KK>(kk, g) ? fok : valid && mass_int_row<D, KK>(kk, g) < C::NINT;
-    xh[kk] = ok ? md.x[kk] * (mass_is_facet<D, KK>(kk, g) ? sfac : sint) : 0.0;
+    xh[kk] = (T)(ok ? md.x[kk] * (mass_is_facet<D, KK>(kk, g) ? sfac : sint) : 0.0);
   }
   // Both contractions run their output tiles side by side (independent
   // accumulators) and read the table fragments of the next step while the
   // MFMAs of the current one run.
   double y[C::NMT][4];
   {
-    d4 acc[C::NMT];
-    double a[MASS_PF + 1][C::NMT];
+    V acc[C::NMT];
+    T a[MASS_PF + 1][C::NMT];
 #pragma unroll
-    for (int mt = 0; mt < C::NMT; ++mt) acc[mt] = vzero<d4>();
+    for (int mt = 0; mt < C::NMT; ++mt) acc[mt] = vzero<V>();
 #pragma unroll
     for (int kk = 0; kk < MASS_PF && kk < C::NK; ++kk)
 #pragma unroll
@@ -662,7 +666,7 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
 #pragma unroll
     for (int mt = 0; mt < C::NMT; ++mt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) y[mt][i] = acc[mt][i];
+      for (int i = 0; i < 4; ++i) y[mt][i] = (double)acc[mt][i];
   }
   // component mixing: quads rq = blk*D + a hold components a of one alpha block
   double Gm[D][D];
@@ -723,11 +727,11 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
   }
   double* const fsrow = fs + ((int64_t)md.ix.side * mesh.F + (md.ix.fid >= 0 ? md.ix.fid : 0)) * C::NF;
   double* const irow = out + off + (valid ? e : 0) * C::NINT;
-  d4 o[C::NJT];
+  V o[C::NJT];
   {
-    double b[MASS_PF + 1][C::NJT];
+    T b[MASS_PF + 1][C::NJT];
 #pragma unroll
-    for (int jt = 0; jt < C::NJT; ++jt) o[jt] = vzero<d4>();
+    for (int jt = 0; jt < C::NJT; ++jt) o[jt] = vzero<V>();
 #pragma unroll
     for (int rq = 0; rq < MASS_PF && rq < C::NMQ; ++rq)
 #pragma unroll
@@ -741,7 +745,7 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
       }
       MASS_SCHED_FENCE();
 #pragma unroll
-      for (int jt = 0; jt < C::NJT; ++jt) o[jt] = M::mma(b[rq % (MASS_PF + 1)][jt], y[rq / 4][rq % 4], o[jt]);
+      for (int jt = 0; jt < C::NJT; ++jt) o[jt] = M::mma(b[rq % (MASS_PF + 1)][jt], (T)y[rq / 4][rq % 4], o[jt]);
       MASS_SCHED_FENCE();
     }
   }
@@ -752,8 +756,8 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
       // output register i of tile jt holds step s = 4 jt + i of this lane
       const int s = 4 * jt + i;
       if (s < C::NK) {
-        mass_store<D, KK>(s, g, o[jt][i], i % 2 == 0 && i < 3 ? o[jt][i + 1] : 0.0, sfac, sint, fok, fsrow, valid,
-                          irow, trash);
+        mass_store<D, KK>(s, g, (double)o[jt][i], i % 2 == 0 && i < 3 ? (double)o[jt][i + 1] : 0.0, sfac, sint, fok,
+                          fsrow, valid, irow, trash);
       }
     }
   }
@@ -788,7 +792,8 @@ __global__ __launch_bounds__(256) void k_mass(const double* __restrict__ x, doub
     MassData<D, KK> md;
     mass_load_idx<D>(mesh, wave, lane >> 4, lane & 15, ix);
     mass_load_data<D, KK>(x, mesh, wave, lane >> 4, lane & 15, ix, md);
-    dot = mass_compute<D, KK, MODE>(md, out, fs, fs + 2 * mesh.F * Cfg<D, KK>::NF, mesh, fin, fout, wave, lane);
+    dot = mass_compute<double, D, KK, MODE>(md, out, fs, fs + 2 * mesh.F * Cfg<D, KK>::NF, mesh, fin, fout, wave,
+                                            lane);
   }
   if (part) {
     dot = block_sum256(dot);
@@ -807,17 +812,18 @@ constexpr int mass_lds_doubles() {
   return (C::NMT * C::NK + C::NJT * C::NMQ) * 64;
 }
 
-template <int D, int KK, int MODE>
+template <typename T, int D, int KK, int MODE>
 __global__ __launch_bounds__(256, 2) void k_mass_lds(const double* __restrict__ x, double* __restrict__ out,
                                                   double* __restrict__ fs, DevMesh mesh,
-                                                  const double* __restrict__ fin,
-                                                  const double* __restrict__ fout,
+                                                  const T* __restrict__ fin,
+                                                  const T* __restrict__ fout,
                                                   const int* __restrict__ flag, double* __restrict__ part) {
   using C = Cfg<D, KK>;
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];
+  T* const lds = reinterpret_cast<T*>(lds_raw);
   if (flag && *flag) return;  // uniform over the launch
   constexpr int NIN = C::NMT * C::NK * 64;
-  constexpr int NTOT = mass_lds_doubles<D, KK>();
+  constexpr int NTOT = mass_lds_doubles<D, KK>();  // table entries (of type T)
   for (int i = threadIdx.x; i < NTOT; i += 256) lds[i] = i < NIN ? fin[i] : fout[i - NIN];
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
@@ -856,12 +862,12 @@ __global__ __launch_bounds__(256, 2) void k_mass_lds(const double* __restrict__ 
       // hoisting all of them into registers
       int base = 0;
       asm volatile("" : "+s"(base));
-      dot += mass_compute<D, KK, MODE>(da, out, fs, trash, mesh, lds + base, lds + base + NIN, wave, lane);
+      dot += mass_compute<T, D, KK, MODE>(da, out, fs, trash, mesh, lds + base, lds + base + NIN, wave, lane);
       mass_load_data<D, KK>(x, mesh, wave + 2 * stride, g, c, ib, da);
       mass_load_idx<D>(mesh, wave + 3 * stride, g, c, ib);
       asm volatile("" : "+s"(base));
-      dot += mass_compute<D, KK, MODE>(db, out, fs, trash, mesh, lds + base, lds + base + NIN, wave + stride,
-                                       lane, wave + stride < nw);
+      dot += mass_compute<T, D, KK, MODE>(db, out, fs, trash, mesh, lds + base, lds + base + NIN, wave + stride,
+                                          lane, wave + stride < nw);
       wave += 2 * stride;
       if (wave >= nw) break;
     }
@@ -929,7 +935,8 @@ void launch_assemble(hipStream_t s, double* r, const double* slot, const DevMesh
 
 template <int D, int KK>
 int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* fs, const DevMesh& mesh,
-                const double* fin, const double* fout, const int* flag, double* part) {
+                const double* fin, const double* fout, const int* flag, double* part, const float* fin32,
+                const float* fout32) {
   using C = Cfg<D, KK>;
   const int64_t waves = (mesh.E + 15) / 16;
   constexpr size_t lds_bytes = (size_t)mass_lds_doubles<D, KK>() * sizeof(double);
@@ -938,13 +945,17 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
     // two resident blocks per CU (the tables take up to 64 KB of LDS each)
     const int64_t blocks = std::min<int64_t>((waves + 3) / 4, MASS_BLOCKS);
     if (mode == 0)
-      HOPU_LAUNCH((k_mass_lds<D, KK, 0>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, fs, mesh,
-                         fin, fout, flag, part);
+      HOPU_LAUNCH((k_mass_lds<double, D, KK, 0>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, fs,
+                  mesh, fin, fout, flag, part);
+    else if (fin32 && fout32)
+      HOPU_LAUNCH((k_mass_lds<float, D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes / 2, s, x, out, fs,
+                  mesh, fin32, fout32, flag, part);
     else
-      HOPU_LAUNCH((k_mass_lds<D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, fs, mesh,
-                         fin, fout, flag, part);
+      HOPU_LAUNCH((k_mass_lds<double, D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, fs,
+                  mesh, fin, fout, flag, part);
     return (int)blocks;
   } else {
+    // (no FP32 form: its tables would not fit in LDS either)
     const int64_t blocks = (waves + 3) / 4;
     if (mode == 0)
       HOPU_LAUNCH((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, fs, mesh, fin, fout, flag,
@@ -953,6 +964,8 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
       HOPU_LAUNCH((k_mass<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, fs, mesh, fin, fout, flag,
                   part);
     (void)sizeof(C);
+    (void)fin32;
+    (void)fout32;
     return (int)blocks;
   }
 }
@@ -967,7 +980,8 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
   template void launch_elem<float, D, KK>(hipStream_t, const float*, double*, double*, const DevMesh&,      \
                                           const DevTables<float>&, int, double*, double*);                  \
   template int launch_mass<D, KK>(hipStream_t, int, const double*, double*, double*, const DevMesh&,        \
-                                  const double*, const double*, const int*, double*);                       \
+                                  const double*, const double*, const int*, double*, const float*,          \
+                                  const float*);                                                            \
   template void launch_assemble<D, KK>(hipStream_t, double*, const double*, const DevMesh&, const int*);
 
 HOPU_INST(2, 1)

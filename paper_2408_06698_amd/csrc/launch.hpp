@@ -11,11 +11,13 @@ void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMe
                  const DevTables<T>& tb, int terms, double* diss_part, double* eta_nd);
 // y = M x (mode 0) or the preconditioner applied to x (mode 1): interior rows
 // into out, facet rows as one contribution per side into fs ([2][F][NF]);
-// with part set, also the per-block partials of x . y.  Returns the number of
-// blocks launched (= partials written).
+// with part set, also the per-block partials of x . y.  With fin32/fout32
+// set, mode 1 runs its contractions in FP32 MFMA (orders whose tables fit in
+// LDS).  Returns the number of blocks launched (= partials written).
 template <int D, int KK>
 int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* fs, const DevMesh& mesh,
-                const double* fin, const double* fout, const int* flag, double* part);
+                const double* fin, const double* fout, const int* flag, double* part, const float* fin32 = nullptr,
+                const float* fout32 = nullptr);
 // facet rows v[0, nfl) = fs[0][.] + fs[1][.]
 void launch_fs_assemble(hipStream_t s, double* v, const double* fs, int64_t nfl, const int* flag);
 template <int D, int KK>

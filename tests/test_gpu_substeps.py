@@ -87,3 +87,25 @@ def test_diagnostics_and_energy_identity():
     # divergence-free input: u.r(u) = D
     r = host(h.apply(dev(x)))
     assert abs(x @ r - D) <= 1e-11 * D
+
+
+@pytest.mark.parametrize("cfg,n,k", [(1, (16, 16), 2), (2, (4, 3, 3), 3)])
+def test_substeps_mixed_precision(cfg, n, k):
+    """Mixed-precision substeps (FP32-MFMA residual and preconditioner
+    contractions, FP64 state, mass operator and PCG): the PCG still meets the
+    FP64 tolerance at every substep, and the chain stays within the FP32
+    contraction error of the oracle's FP64 chain."""
+    mesh, sp, x, c = case(cfg, n, k)
+    l = k - 1
+    h = gpu_space(mesh, k)
+    h.set_upwind(l)
+    h.set_solver(rtol=1e-13, max_it=2000)
+    u = dev(x)
+    steps, dt = 5, 1e-3
+    diag = host(h.substeps(u, dt, steps, prec=1, diag=True))
+    xs = O.substeps(sp, x, dt, steps, l, keep=True)
+    e = rel_primal(sp, host(u), xs[-1])
+    print(f"mixed substeps cfg={cfg} k={k} rel={e:.2e} its={diag[1:, 3]}")
+    assert e <= 1e-6
+    assert np.all(diag[1:, 3] >= 1)
+    assert np.all(diag[1:, 4] <= 1e-13)
