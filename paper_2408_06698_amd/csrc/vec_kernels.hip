@@ -1,5 +1,7 @@
 // Vector kernels: deterministic two-stage dot products, PCG scalar updates,
 // axpy-type updates, energy and divergence diagnostics.
+#include <cstdint>
+
 #include "vec.hpp"
 
 namespace hopu {
@@ -96,6 +98,45 @@ __global__ void k_xpay(double* __restrict__ x, double* __restrict__ p, const dou
   }
 }
 
+// The same two updates two rows per thread in 16-byte accesses (nfl and n
+// even, every pointer 16-byte aligned; the launchers check).
+__device__ __forceinline__ double2 fs_row2(const double* __restrict__ v, const double* __restrict__ fs, int64_t nfl,
+                                           int64_t i) {
+  if (i < nfl) {
+    const double2 a = *reinterpret_cast<const double2*>(fs + i), b = *reinterpret_cast<const double2*>(fs + nfl + i);
+    return make_double2(a.x + b.x, a.y + b.y);
+  }
+  return *reinterpret_cast<const double2*>(v + i);
+}
+
+__global__ void k_rupdate2(double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ fs,
+                           int64_t nfl, int64_t n, const double* sc, const int* flag) {
+  if (*flag) return;
+  const double al = sc[SC_ALPHA];
+  for (int64_t i = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x); i < n; i += (int64_t)gridDim.x * 512) {
+    const double2 qv = fs_row2(q, fs, nfl, i);
+    double2 rv = *reinterpret_cast<const double2*>(r + i);
+    rv.x -= al * qv.x;
+    rv.y -= al * qv.y;
+    *reinterpret_cast<double2*>(r + i) = rv;
+  }
+}
+
+__global__ void k_xpay2(double* __restrict__ x, double* __restrict__ p, const double* __restrict__ z,
+                        const double* __restrict__ fs, int64_t nfl, int64_t n, const double* sc, const int* flag) {
+  if (*flag) return;
+  const double al = sc[SC_ALPHA], be = sc[SC_BETA];
+  for (int64_t i = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x); i < n; i += (int64_t)gridDim.x * 512) {
+    const double2 pv = *reinterpret_cast<const double2*>(p + i);
+    const double2 zv = fs_row2(z, fs, nfl, i);
+    double2 xv = *reinterpret_cast<const double2*>(x + i);
+    xv.x += al * pv.x;
+    xv.y += al * pv.y;
+    *reinterpret_cast<double2*>(x + i) = xv;
+    *reinterpret_cast<double2*>(p + i) = make_double2(zv.x + be * pv.x, zv.y + be * pv.y);
+  }
+}
+
 // x += alpha p (the update of the iteration that converged, whose k_xpay was
 // skipped)
 __global__ void k_xfinal(double* __restrict__ x, const double* __restrict__ p, int64_t n, const double* sc) {
@@ -147,13 +188,25 @@ void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag
                 double* dst) {
   hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, s, part, np, sc, flag, op, arg, dst);
 }
+static bool al16(const void* a) { return (reinterpret_cast<uintptr_t>(a) & 15) == 0; }
+static int grid_pairs(int64_t n) {
+  const int64_t b = (n / 2 + 255) / 256;
+  return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
 void vec_rupdate(hipStream_t s, double* r, const double* q, const double* fs, int64_t nfl, int64_t n,
                  const double* sc, const int* flag) {
-  hipLaunchKernelGGL(k_rupdate, dim3(grid_for(n)), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag);
+  if (nfl % 2 == 0 && n % 2 == 0 && al16(r) && al16(q) && al16(fs))
+    hipLaunchKernelGGL(k_rupdate2, dim3(grid_pairs(n)), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag);
+  else
+    hipLaunchKernelGGL(k_rupdate, dim3(grid_for(n)), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag);
 }
 void vec_xpay(hipStream_t s, double* x, double* p, const double* z, const double* fs, int64_t nfl, int64_t n,
               const double* sc, const int* flag) {
-  hipLaunchKernelGGL(k_xpay, dim3(grid_for(n)), dim3(256), 0, s, x, p, z, fs, nfl, n, sc, flag);
+  if (nfl % 2 == 0 && n % 2 == 0 && al16(x) && al16(p) && al16(z) && al16(fs))
+    hipLaunchKernelGGL(k_xpay2, dim3(grid_pairs(n)), dim3(256), 0, s, x, p, z, fs, nfl, n, sc, flag);
+  else
+    hipLaunchKernelGGL(k_xpay, dim3(grid_for(n)), dim3(256), 0, s, x, p, z, fs, nfl, n, sc, flag);
 }
 void vec_xfinal(hipStream_t s, double* x, const double* p, int64_t n, const double* sc) {
   hipLaunchKernelGGL(k_xfinal, dim3(grid_for(n)), dim3(256), 0, s, x, p, n, sc);
