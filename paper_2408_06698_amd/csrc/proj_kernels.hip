@@ -106,8 +106,9 @@ __device__ __forceinline__ void zmix(Tiles<D, KK>& y, const double (&Gs)[D][D]) 
   }
 }
 
-// out (modal tiles) = table (NMT tiles x NK steps) . xin (one value per step)
-template <int D, int KK>
+// out (modal tiles) = table (NMT tiles x NK steps) . xin (one value per
+// step); only the first NKU steps are nonzero
+template <int D, int KK, int NKU>
 __device__ __forceinline__ void contract_in(const double* __restrict__ tab, const Steps<D, KK>& xin,
                                             Tiles<D, KK>& y, int lane) {
   using C = Cfg<D, KK>;
@@ -115,7 +116,7 @@ __device__ __forceinline__ void contract_in(const double* __restrict__ tab, cons
   for (int mt = 0; mt < C::NMT; ++mt) {
     d4 acc = d4zero();
 #pragma unroll
-    for (int kk = 0; kk < C::NK; ++kk) acc = mfma(tab[(mt * C::NK + kk) * 64 + lane], xin[kk], acc);
+    for (int kk = 0; kk < NKU; ++kk) acc = mfma(tab[(mt * C::NK + kk) * 64 + lane], xin[kk], acc);
 #pragma unroll
     for (int i = 0; i < 4; ++i) y[mt][i] = acc[i];
   }
@@ -208,7 +209,8 @@ __global__ __launch_bounds__(256) void k_proj(const double* __restrict__ ph, con
 #pragma unroll
     for (int kk = 0; kk < C::NK; ++kk)
       f[kk] = (is_facet<D, KK>(kk, g) && mf >= 0) ? sig * ph[(int64_t)mf * C::NF + kk] / nf : 0.0;
-    contract_in<D, KK>(pj.prec_in, f, w1, lane);
+    // (f vanishes on the interior steps s >= n_f)
+    contract_in<D, KK, C::NF>(pj.prec_in, f, w1, lane);
 #pragma unroll
     for (int mt = 0; mt < C::NMT; ++mt)
 #pragma unroll
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(256) void k_proj(const double* __restrict__ ph, con
 #pragma unroll
     for (int kk = 0; kk < C::NK; ++kk) xh[kk] = xs[kk] * (is_facet<D, KK>(kk, g) ? nf : si);
     double ms[C::NMT][4];
-    contract_in<D, KK>(pj.mass_in, xh, ms, lane);
+    contract_in<D, KK, C::NK>(pj.mass_in, xh, ms, lane);
 #pragma unroll
     for (int mt = 0; mt < C::NMT; ++mt)
 #pragma unroll
@@ -262,9 +264,11 @@ __global__ __launch_bounds__(256) void k_proj(const double* __restrict__ ph, con
 #pragma unroll
       for (int i = 0; i < 4; ++i) dot += w1[mt][i] * tau[mt][i];
   }
-  // u~ rows = S^-1 D tau (output tile jt, register i = step 4 jt + i)
+  // u~ rows = S^-1 D tau (output tile jt, register i = step 4 jt + i); modes
+  // 0 and 1 need the facet steps s < n_f only
+  constexpr int NJO = MODE == 2 ? C::NJT : (C::NF + 3) / 4;
 #pragma unroll
-  for (int jt = 0; jt < C::NJT; ++jt) {
+  for (int jt = 0; jt < NJO; ++jt) {
     d4 o = d4zero();
 #pragma unroll
     for (int rq = 0; rq < C::NMQ; ++rq) o = mfma(pj.prec_out[(jt * C::NMQ + rq) * 64 + lane], tau[rq / 4][rq % 4], o);
