@@ -13,13 +13,14 @@ import sys
 
 # kernel keys of the traffic summary: substring of the demangled name
 TRAFFIC_KERNELS = [
-    ("mass", "k_mass_lds<3, 3, 0>"),
-    ("prec", "k_mass_lds<3, 3, 1>"),
+    ("mass", "k_mass_lds<double, 3, 3, 0>"),
+    ("prec", "k_mass_lds<double, 3, 3, 1>"),
     ("elem", "k_elem<double, 3, 3>"),
     ("elem_fp32", "k_elem<float, 3, 3>"),
     ("modal", "k_modal<double, 3, 3>"),
-    ("rupdate", "k_rupdate("),
-    ("xpay", "k_xpay("),
+    ("rupdate", "k_rupdate2("),
+    ("xpay", "k_xpay2("),
+    ("proj", "k_proj<3, 3, 0>"),
 ]
 
 
@@ -69,7 +70,7 @@ def traffic(fetch_db, write_db, src):
           f"WRITE_SIZE {wmax:.1f} KiB")
     print(f"#   -> fetch scale {fs:.4f}, write scale {ws:.4f} (bytes = KiB * 1024 * scale)")
     print("# kernels_sha: SHA-256 (16 hex) of kernels.hip from 'namespace hopu {' to the launchers marker")
-    print("# per-launch medians over launches that did work (> 5% of the kernel's largest)")
+    print("# per-launch medians over the launches at full size (> 80% of the kernel's largest)")
     print(f"kernels_sha = {kernels_sha(src)}")
     print(f"fetch_scale = {fs:.6f}")
     print(f"write_scale = {ws:.6f}")
@@ -78,8 +79,8 @@ def traffic(fetch_db, write_db, src):
         wk = [k for k in write if pat in k]
         if not fk or not wk:
             continue
-        fv = [x for x in fetch[fk[0]] if x > 0.05 * max(fetch[fk[0]])]
-        wv = [x for x in write[wk[0]] if x > 0.05 * max(write[wk[0]])]
+        fv = [x for x in fetch[fk[0]] if x > 0.8 * max(fetch[fk[0]])]
+        wv = [x for x in write[wk[0]] if x > 0.8 * max(write[wk[0]])]
         f, w = statistics.median(fv), statistics.median(wv)
         print(f"# {key}: FETCH_SIZE {f:.0f} KiB (n={len(fv)}), WRITE_SIZE {w:.0f} KiB (n={len(wv)})")
         print(f"{key}_bytes_per_launch = {f * 1024 * fs + w * 1024 * ws:.0f}")
