@@ -194,6 +194,10 @@ def main():
         roof = {"kernel": f"k_mass ({'mass apply' if dom == 'mass' else 'preconditioner'} sandwich)",
                 "bound": "mfma", "achieved": algo / avg / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
+    # what this GPU sustains for register-only FP64 MFMA chains, by waves per
+    # SIMD (the FP64 kernels run one or two)
+    from paper_2408_06698_amd.hopu import mfma_f64_rate
+    sustained = {str(w): mfma_f64_rate(w) for w in (1, 2, 8)}
     roof["avg_launch_us"] = avg * 1e6
     roof["launches"] = launches
     tr = traffic_from_profiles(dom)
@@ -207,6 +211,7 @@ def main():
                                "7,864,320 DoFs, TG + N(0,1e-3^2) noise, l=2, dt=5e-4, one substep per step",
                    "n_dof": ndof, "elements": E, "facets": F},
         "roofline": roof,
+        "mfma_f64_sustained_tflops_by_waves_per_simd": sustained,
         "apply_ms_fp64": apply64, "apply_ms_fp32_mfma": apply32,
         "apply_rate_fp64": ndof / (apply64 * 1e-3), "apply_rate_fp32_mfma": ndof / (apply32 * 1e-3),
         "apply_frac_fp64_flops": F_apply / (apply64 * 1e-3) / PEAK_FP64,

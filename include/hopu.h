@@ -149,6 +149,14 @@ hopu_status hopu_mass_solve(hopu_ctx ctx, const double* r, double* w,
 hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* unew,
                          double rtol, int max_it, int* iters);
 
+/* Measurement helper (no context): the FP64 MFMA rate the current device
+ * sustains with independent 16x16x4 accumulation chains held in registers
+ * (no memory traffic), blocks_per_cu (1..8) blocks of four waves per compute
+ * unit, i.e. that many waves per SIMD.  The practical ceiling against which
+ * the FP64 kernels' MFMA rates can be read.  *tflops (host) receives the
+ * rate.  Allocates a small buffer; syncs the default stream. */
+hopu_status hopu_mfma_f64_rate(int blocks_per_cu, double* tflops);
+
 /* n_steps explicit substeps u <- u - dt M^-1 r(u), in place on u (dev).
  * diag_dev (dev double [n_steps+1][5], nullable): per state energy
  * 1/2 u.Mu, ||div u||_L2, upwind dissipation, PCG iterations of the solve

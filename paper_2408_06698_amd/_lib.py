@@ -32,6 +32,7 @@ SIGNATURES = {
     "hopu_mass_apply": (_i, [_p, _p, _p]),
     "hopu_mass_solve": (_i, [_p, _p, _p, _d, _i, _p]),
     "hopu_project": (_i, [_p, _p, _p, _d, _i, _p]),
+    "hopu_mfma_f64_rate": (_i, [_i, _p]),
     "hopu_substeps": (_i, [_p, _p, _d, _i, _i, _p]),
     "hopu_convection_vjp": (_i, [_p, _p, _p, _p, _i]),
     "hopu_substeps_vjp_workspace": (_i64, [_p, _i, _i]),

@@ -281,3 +281,30 @@ HOPU_AUX_INST(3, 4)
 HOPU_AUX_INST(3, 5)
 
 }  // namespace hopu
+
+namespace hopu {
+
+// Measurement only: sustained FP64 MFMA rate of independent 16x16x4
+// accumulation chains held in registers (no memory, no LDS), one block of
+// four waves per CU times `blocks_per_cu`.
+__global__ __launch_bounds__(256) void k_mfma_f64_rate(double* __restrict__ out, int iters, double a0, double b0) {
+  typedef double d4v __attribute__((ext_vector_type(4)));
+  d4v acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = d4v{0, 0, 0, 0};
+  const double a = a0 + threadIdx.x * 1e-9, b = b0 + blockIdx.x * 1e-9;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+  }
+  double s = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+void launch_mfma_f64_rate(hipStream_t s, double* out, int blocks, int iters) {
+  hipLaunchKernelGGL(k_mfma_f64_rate, dim3((unsigned)blocks), dim3(256), 0, s, out, iters, 1.0, 1e-3);
+}
+
+}  // namespace hopu

@@ -588,6 +588,33 @@ extern "C" hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* u
   return HOPU_OK;
 }
 
+// Measurement: the FP64 MFMA rate this GPU sustains with blocks_per_cu
+// blocks of four waves per CU (waves per SIMD = blocks_per_cu).
+extern "C" hopu_status hopu_mfma_f64_rate(int blocks_per_cu, double* tflops) {
+  if (blocks_per_cu < 1 || blocks_per_cu > 8 || !tflops) return HOPU_EINVAL;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return HOPU_EHIP;
+  const int blocks = cus * blocks_per_cu, iters = 4000;
+  double* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hopu_status st = HOPU_OK;
+  float ms = 0.f;
+  if (hipMalloc(&out, (size_t)blocks * 256 * sizeof(double)) != hipSuccess) return HOPU_ENOMEM;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) { st = HOPU_EHIP; goto done; }
+  launch_mfma_f64_rate(nullptr, out, blocks, iters);  // warm-up (clocks)
+  if (hipEventRecord(e0, nullptr) != hipSuccess) { st = HOPU_EHIP; goto done; }
+  launch_mfma_f64_rate(nullptr, out, blocks, iters);
+  if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+      hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = HOPU_EHIP; goto done; }
+  *tflops = (double)blocks * 4 * iters * 8 * 2048.0 / (ms * 1e-3) / 1e12;
+done:
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  return st;
+}
+
 extern "C" hopu_status hopu_mass_solve(hopu_ctx ctx, const double* r, double* w, double rtol, int max_it, int* iters) {
   if (!ctx) return HOPU_EINVAL;
   if (!r || !w) return fail(ctx, HOPU_EINVAL, "NULL vector");

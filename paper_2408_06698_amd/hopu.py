@@ -20,6 +20,14 @@ def _dev(t):
     return t
 
 
+def mfma_f64_rate(blocks_per_cu):
+    """Sustained FP64 MFMA rate (TFLOP/s) of register-only 16x16x4 chains
+    with blocks_per_cu blocks of four waves per CU (measurement helper)."""
+    t = C.c_double()
+    check(L.lib().hopu_mfma_f64_rate(int(blocks_per_cu), C.byref(t)), None)
+    return t.value
+
+
 class Hopu:
     """One velocity space on one mesh (see include/hopu.h)."""
 
