@@ -563,7 +563,7 @@ extern "C" hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* u
     const int chunk = std::min(16, max_it - it);
     for (int c = 0; c < chunk; ++c) {
       int np = 0;
-      DISPATCH(ctx->dim, ctx->k, { np = launch_proj<D, KK>(s, 0, ctx->pp, nullptr, ctx->pfs, ctx->dm, pj, ctx->part); });
+      DISPATCH(ctx->dim, ctx->k, { np = launch_proj<D, KK>(s, 0, ctx->pp, nullptr, ctx->pfs, ctx->dm, pj, ctx->part, fl); });
       vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
       vec_rupdate(s, ctx->pr, ctx->pr, ctx->pfs, nh, nh, ctx->sc, fl);  // r -= alpha S_p p
       vec_dot(s, ctx->pr, ctx->pr, nh, ctx->part, fl);

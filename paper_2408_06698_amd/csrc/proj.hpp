@@ -23,10 +23,11 @@ struct ProjDev {
 // mode 0: facet-side contributions ([2][FW][nf]) of S_p ph, per-block
 // partials of ph . S_p ph into part; mode 1: facet-side contributions of the
 // right-hand side g from us; mode 2: out = us - u~ (V_h layout) from ph, us.
-// Returns the number of blocks (partials) launched.
+// Returns the number of blocks (partials) launched.  flag (nullable): the
+// launch does nothing once *flag is set.
 template <int D, int KK>
 int launch_proj(hipStream_t s, int mode, const double* ph, const double* us, double* out, const DevMesh& mesh,
-                const ProjDev& pj, double* part);
+                const ProjDev& pj, double* part, const int* flag = nullptr);
 template <int D, int KK>
 void launch_proj_ainv(hipStream_t s, const DevMesh& mesh, const double* kab, double* ainv);
 

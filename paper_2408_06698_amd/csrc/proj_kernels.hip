@@ -181,8 +181,9 @@ __device__ __forceinline__ void schur_correct(const Tiles<D, KK>& v, Tiles<D, KK
 template <int D, int KK, int MODE>
 __global__ __launch_bounds__(256) void k_proj(const double* __restrict__ ph, const double* __restrict__ us,
                                               double* __restrict__ out, DevMesh mesh, ProjDev pj,
-                                              double* __restrict__ part) {
+                                              double* __restrict__ part, const int* __restrict__ flag) {
   using C = Cfg<D, KK>;
+  if (flag && *flag) return;  // CG converged: iterations queued after it do nothing
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t e = wave * 16 + c;
@@ -335,16 +336,16 @@ __global__ void k_proj_ainv(DevMesh mesh, const double* __restrict__ kab, double
 
 template <int D, int KK>
 int launch_proj(hipStream_t s, int mode, const double* ph, const double* us, double* out, const DevMesh& mesh,
-                const ProjDev& pj, double* part) {
+                const ProjDev& pj, double* part, const int* flag) {
   const int64_t waves = (mesh.E + 15) / 16;
   const int64_t blocks = (waves + 3) / 4;
   if (blocks == 0) return 0;
   if (mode == 0)
-    HOPU_LAUNCH((k_proj<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, ph, us, out, mesh, pj, part);
+    HOPU_LAUNCH((k_proj<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, ph, us, out, mesh, pj, part, flag);
   else if (mode == 1)
-    HOPU_LAUNCH((k_proj<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, ph, us, out, mesh, pj, part);
+    HOPU_LAUNCH((k_proj<D, KK, 1>), dim3((unsigned)blocks), dim3(256), 0, s, ph, us, out, mesh, pj, part, flag);
   else
-    HOPU_LAUNCH((k_proj<D, KK, 2>), dim3((unsigned)blocks), dim3(256), 0, s, ph, us, out, mesh, pj, part);
+    HOPU_LAUNCH((k_proj<D, KK, 2>), dim3((unsigned)blocks), dim3(256), 0, s, ph, us, out, mesh, pj, part, flag);
   return (int)blocks;
 }
 
@@ -357,7 +358,7 @@ void launch_proj_ainv(hipStream_t s, const DevMesh& mesh, const double* kab, dou
 
 #define HOPU_PROJ_INST(D, KK)                                                                              \
   template int launch_proj<D, KK>(hipStream_t, int, const double*, const double*, double*, const DevMesh&, \
-                                  const ProjDev&, double*);                                                \
+                                  const ProjDev&, double*, const int*);                                    \
   template void launch_proj_ainv<D, KK>(hipStream_t, const DevMesh&, const double*, double*);
 
 HOPU_PROJ_INST(2, 1)
