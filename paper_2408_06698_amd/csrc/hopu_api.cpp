@@ -43,6 +43,7 @@ struct hopu_ctx_s {
   float* mu32 = nullptr;
   double* slot = nullptr;
   double* part = nullptr;   // partial sums (max(NPART, nb, waves))
+  double* part2 = nullptr;  // partial sums of the vector updates (2 NPART)
   int64_t npart = 0;
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *rc = nullptr;
   // projection step (tables at create; workspace on the first hopu_project)
@@ -294,6 +295,7 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(dev_alloc(ctx, &ctx->slot, (size_t)E * s.nfl + 128));
     ctx->npart = std::max<int64_t>(std::max<int64_t>(2 * NPART, ctx->bat.nb), (E + 15) / 16);
     TRY(dev_alloc(ctx, &ctx->part, (size_t)ctx->npart));
+    TRY(dev_alloc(ctx, &ctx->part2, (size_t)(2 * NPART)));
     TRY(dev_alloc(ctx, &ctx->r, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->z, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->p, (size_t)n));
@@ -485,11 +487,9 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
     for (int c = 0; c < chunk; ++c) {
       prof_idx.push_back(ctx->ev_used);
       np = mass_raw(ctx, 0, ctx->p, ctx->q, fl, true, true);
-      vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
-      vec_rupdate(s, ctx->r, ctx->q, ctx->slot, nfl, n, ctx->sc, fl);
+      vec_rupdate(s, ctx->r, ctx->q, ctx->slot, nfl, n, ctx->sc, fl, ctx->part, np, nullptr);  // alpha; r -= alpha q
       np = mass_raw(ctx, 1, ctx->r, ctx->z, fl, true, true, prec32);
-      vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_BETA, 0.0, nullptr);
-      vec_xpay(s, x, ctx->p, ctx->z, ctx->slot, nfl, n, ctx->sc, fl);
+      vec_xpay(s, x, ctx->p, ctx->z, ctx->slot, nfl, n, ctx->sc, fl, ctx->part, np);  // beta, test; x, p updates
     }
     it += chunk;
     HCHECK(hipMemcpyAsync(ctx->hflag, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -564,11 +564,10 @@ extern "C" hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* u
     for (int c = 0; c < chunk; ++c) {
       int np = 0;
       DISPATCH(ctx->dim, ctx->k, { np = launch_proj<D, KK>(s, 0, ctx->pp, nullptr, ctx->pfs, ctx->dm, pj, ctx->part, fl); });
-      vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_ALPHA, 0.0, nullptr);
-      vec_rupdate(s, ctx->pr, ctx->pr, ctx->pfs, nh, nh, ctx->sc, fl);  // r -= alpha S_p p
-      vec_dot(s, ctx->pr, ctx->pr, nh, ctx->part, fl);
-      vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_BETA, 0.0, nullptr);
-      vec_xpay(s, ctx->ph, ctx->pp, ctx->pr, ctx->pfs, 0, nh, ctx->sc, fl);  // x += alpha p; p = r + beta p
+      // alpha; r -= alpha S_p p; partials of r.r into part2
+      const int nr = vec_rupdate(s, ctx->pr, ctx->pr, ctx->pfs, nh, nh, ctx->sc, fl, ctx->part, np, ctx->part2);
+      // beta, test; x += alpha p; p = r + beta p
+      vec_xpay(s, ctx->ph, ctx->pp, ctx->pr, ctx->pfs, 0, nh, ctx->sc, fl, ctx->part2, nr);
     }
     it += chunk;
     HCHECK(hipMemcpyAsync(ctx->hflag, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));

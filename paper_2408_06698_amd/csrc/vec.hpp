@@ -4,19 +4,25 @@
 
 namespace hopu {
 enum { NPART = 1024 };
-enum { SC_RZ = 0, SC_ALPHA = 1, SC_BETA = 2, SC_TOL2 = 3, SC_BPB = 4, SC_RES = 5, SC_N = 8 };
-enum { OP_SET_TOL = 0, OP_SET_RZ = 1, OP_ALPHA = 2, OP_BETA = 3, OP_STORE = 4, OP_STORE_HALF = 5 };
+enum { SC_RZ = 0, SC_ALPHA = 1, SC_BETA = 2, SC_TOL2 = 3, SC_BPB = 4, SC_RES = 5, SC_RZ_OLD = 6, SC_N = 8 };
+enum { OP_SET_TOL = 0, OP_SET_RZ = 1, OP_STORE = 4, OP_STORE_HALF = 5 };
 void vec_dot(hipStream_t s, const double* a, const double* b, int64_t n, double* part, const int* flag);
 void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag, int op, double arg,
                 double* dst);
 // q, z, and q in vec_sub_fs are unassembled: facet rows [0, nfl) come from the
 // facet-side buffer fs ([2][nfl]), interior rows from the vector itself.
 // PCG updates: r -= alpha q; then x += alpha p, p = z + beta p; and, after
-// convergence, the last x += alpha p.
-void vec_rupdate(hipStream_t s, double* r, const double* q, const double* fs, int64_t nfl, int64_t n,
-                 const double* sc, const int* flag);
+// convergence, the last x += alpha p.  The scalar steps ride on the updates:
+// vec_rupdate takes alpha = rz / (p.q) from the np partials of p.q (part,
+// from the operator launch before it) and, if rr is given, leaves one
+// partial of r.r per block there (returns the block count); vec_xpay takes
+// beta and the convergence test from the np partials of the new rz, counts
+// the iteration in flag[1] and raises flag[0] on convergence.  part ==
+// nullptr: alpha / beta are read from sc as they are.
+int vec_rupdate(hipStream_t s, double* r, const double* q, const double* fs, int64_t nfl, int64_t n, double* sc,
+                const int* flag, const double* part, int np, double* rr);
 void vec_xpay(hipStream_t s, double* x, double* p, const double* z, const double* fs, int64_t nfl, int64_t n,
-              const double* sc, const int* flag);
+              double* sc, int* flag, const double* part, int np);
 void vec_xfinal(hipStream_t s, double* x, const double* p, int64_t n, const double* sc);
 void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, const double* fs, int64_t nfl,
                 int64_t n);

@@ -21,11 +21,10 @@ __global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// Reduce partials in a fixed order and apply a PCG scalar operation.
-__global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part, int np, double* sc, int* flag,
-                                                int op, double arg, double* dst) {
-  if (op != OP_SET_TOL && op != OP_STORE && op != OP_STORE_HALF && flag && *flag) return;
-  __shared__ double sh[256];
+// Sum of np partials by one block of 256 threads in a fixed order (thread t
+// adds part[t], part[t + 256], ..., then a fixed tree): every block that
+// calls it gets the same bits.  All threads of the block must call it.
+__device__ double block_sum_fixed(const double* __restrict__ part, int np, double* sh) {
   double s = 0.0;
   for (int i = threadIdx.x; i < np; i += 256) s += part[i];
   sh[threadIdx.x] = s;
@@ -34,8 +33,29 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part,
     if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
+  return sh[0];
+}
+
+// Sum over the block of one value per thread, the same fixed tree.
+__device__ double block_sum_tree(double v, double* sh) {
+  __syncthreads();
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Reduce partials in a fixed order and apply a PCG scalar operation.
+__global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part, int np, double* sc, int* flag,
+                                                int op, double arg, double* dst) {
+  if (op != OP_SET_TOL && op != OP_STORE && op != OP_STORE_HALF && flag && *flag) return;
+  __shared__ double sh[256];
+  const double v0 = block_sum_fixed(part, np, sh);
   if (threadIdx.x != 0) return;
-  const double v = sh[0];
+  const double v = v0;
   switch (op) {
     case OP_SET_TOL:  // v = b.Pb
       sc[SC_TOL2] = arg * arg * v;
@@ -47,16 +67,6 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part,
       sc[SC_RZ] = v;
       if (!(v > sc[SC_TOL2])) flag[0] = 1;
       sc[SC_RES] = sc[SC_BPB] > 0 ? sqrt(fmax(v, 0.0) / sc[SC_BPB]) : 0.0;
-      break;
-    case OP_ALPHA:
-      sc[SC_ALPHA] = sc[SC_RZ] / v;
-      break;
-    case OP_BETA:
-      sc[SC_BETA] = v / sc[SC_RZ];
-      sc[SC_RZ] = v;
-      flag[1] += 1;
-      sc[SC_RES] = sc[SC_BPB] > 0 ? sqrt(fmax(v, 0.0) / sc[SC_BPB]) : 0.0;
-      if (!(v > sc[SC_TOL2])) flag[0] = 1;
       break;
     case OP_STORE:
       *dst = v;
@@ -76,64 +86,128 @@ __device__ __forceinline__ double fs_row(const double* __restrict__ v, const dou
   return i < nfl ? fs[i] + fs[nfl + i] : v[i];
 }
 
-// r -= alpha q (q unassembled)
-__global__ void k_rupdate(double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ fs,
-                          int64_t nfl, int64_t n, const double* sc, const int* flag) {
-  if (*flag) return;
-  const double al = sc[SC_ALPHA];
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    r[i] -= al * fs_row(q, fs, nfl, i);
+// Rows i and i + 1 (W = 2, 16-byte accesses) or row i (W = 1) of a vector
+// whose facet rows [0, nfl) are unassembled.
+template <int W> struct Rows;
+template <> struct Rows<1> {
+  double v[1];
+  __device__ __forceinline__ void load(const double* __restrict__ a, int64_t i) { v[0] = a[i]; }
+  __device__ __forceinline__ void load_fs(const double* __restrict__ a, const double* __restrict__ fs, int64_t nfl,
+                                          int64_t i) {
+    v[0] = fs_row(a, fs, nfl, i);
+  }
+  __device__ __forceinline__ void store(double* __restrict__ a, int64_t i) const { a[i] = v[0]; }
+};
+template <> struct Rows<2> {
+  double v[2];
+  __device__ __forceinline__ void load(const double* __restrict__ a, int64_t i) {
+    const double2 t = *reinterpret_cast<const double2*>(a + i);
+    v[0] = t.x;
+    v[1] = t.y;
+  }
+  __device__ __forceinline__ void load_fs(const double* __restrict__ a, const double* __restrict__ fs, int64_t nfl,
+                                          int64_t i) {
+    if (i < nfl) {
+      const double2 x = *reinterpret_cast<const double2*>(fs + i), y = *reinterpret_cast<const double2*>(fs + nfl + i);
+      v[0] = x.x + y.x;
+      v[1] = x.y + y.y;
+    } else {
+      load(a, i);
+    }
+  }
+  __device__ __forceinline__ void store(double* __restrict__ a, int64_t i) const {
+    *reinterpret_cast<double2*>(a + i) = make_double2(v[0], v[1]);
+  }
+};
+
+// r -= alpha q (q unassembled).  With part: alpha = rz / (p.q), p.q the sum
+// of the np partials of the operator launch before, reduced by every block
+// in the same order (so every block holds the same alpha); block 0 records
+// alpha and the rz it divided.  With rr: each block's partial of r.r after
+// the update (the inner product of an unpreconditioned CG).
+template <int W>
+__global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const double* __restrict__ q,
+                                                 const double* __restrict__ fs, int64_t nfl, int64_t n, double* sc,
+                                                 const int* flag, const double* __restrict__ part, int np,
+                                                 double* __restrict__ rr) {
+  if (*flag) return;  // no launch of this kernel's iteration writes the flag
+  __shared__ double sh[256];
+  double al;
+  if (part) {
+    al = sc[SC_RZ] / block_sum_fixed(part, np, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[SC_ALPHA] = al;
+      sc[SC_RZ_OLD] = sc[SC_RZ];
+    }
+  } else {
+    al = sc[SC_ALPHA];
+  }
+  double acc = 0.0;
+  for (int64_t i = W * ((int64_t)blockIdx.x * 256 + threadIdx.x); i < n; i += (int64_t)gridDim.x * 256 * W) {
+    Rows<W> qv, rv;
+    qv.load_fs(q, fs, nfl, i);
+    rv.load(r, i);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      rv.v[w] -= al * qv.v[w];
+      acc += rv.v[w] * rv.v[w];
+    }
+    rv.store(r, i);
+  }
+  if (rr) {
+    const double t = block_sum_tree(acc, sh);
+    if (threadIdx.x == 0) rr[blockIdx.x] = t;
+  }
 }
 
 // x += alpha p, then p = z + beta p (z unassembled): the solution update of
-// an iteration rides on the direction update that reads p anyway
-__global__ void k_xpay(double* __restrict__ x, double* __restrict__ p, const double* __restrict__ z,
-                       const double* __restrict__ fs, int64_t nfl, int64_t n, const double* sc, const int* flag) {
-  if (*flag) return;
-  const double al = sc[SC_ALPHA], be = sc[SC_BETA];
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const double pi = p[i];
-    x[i] += al * pi;
-    p[i] = fs_row(z, fs, nfl, i) + be * pi;
-  }
-}
-
-// The same two updates two rows per thread in 16-byte accesses (nfl and n
-// even, every pointer 16-byte aligned; the launchers check).
-__device__ __forceinline__ double2 fs_row2(const double* __restrict__ v, const double* __restrict__ fs, int64_t nfl,
-                                           int64_t i) {
-  if (i < nfl) {
-    const double2 a = *reinterpret_cast<const double2*>(fs + i), b = *reinterpret_cast<const double2*>(fs + nfl + i);
-    return make_double2(a.x + b.x, a.y + b.y);
-  }
-  return *reinterpret_cast<const double2*>(v + i);
-}
-
-__global__ void k_rupdate2(double* __restrict__ r, const double* __restrict__ q, const double* __restrict__ fs,
-                           int64_t nfl, int64_t n, const double* sc, const int* flag) {
-  if (*flag) return;
+// an iteration rides on the direction update that reads p anyway.  With
+// part: beta = rz_new / rz_old and the convergence test from the np partials
+// of rz_new, reduced by every block in the same order; block 0 records them,
+// counts the iteration and raises the flag, and every block of the
+// iteration that converged returns without an update (the caller adds its
+// x update afterwards).
+template <int W>
+__global__ __launch_bounds__(256) void k_xpay(double* __restrict__ x, double* __restrict__ p,
+                                              const double* __restrict__ z, const double* __restrict__ fs,
+                                              int64_t nfl, int64_t n, double* sc, int* flag,
+                                              const double* __restrict__ part, int np) {
+  __shared__ double sh[256];
+  __shared__ int stop;
+  // block 0 may raise the flag while other blocks start: each block reads it
+  // once, so that the whole block takes one branch
+  if (threadIdx.x == 0) stop = *flag;
+  __syncthreads();
+  if (stop) return;
   const double al = sc[SC_ALPHA];
-  for (int64_t i = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x); i < n; i += (int64_t)gridDim.x * 512) {
-    const double2 qv = fs_row2(q, fs, nfl, i);
-    double2 rv = *reinterpret_cast<const double2*>(r + i);
-    rv.x -= al * qv.x;
-    rv.y -= al * qv.y;
-    *reinterpret_cast<double2*>(r + i) = rv;
+  double be;
+  if (part) {
+    const double rz = block_sum_fixed(part, np, sh);
+    be = rz / sc[SC_RZ_OLD];
+    const bool conv = !(rz > sc[SC_TOL2]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[SC_BETA] = be;
+      sc[SC_RZ] = rz;
+      sc[SC_RES] = sc[SC_BPB] > 0 ? sqrt(fmax(rz, 0.0) / sc[SC_BPB]) : 0.0;
+      flag[1] += 1;
+      if (conv) flag[0] = 1;
+    }
+    if (conv) return;
+  } else {
+    be = sc[SC_BETA];
   }
-}
-
-__global__ void k_xpay2(double* __restrict__ x, double* __restrict__ p, const double* __restrict__ z,
-                        const double* __restrict__ fs, int64_t nfl, int64_t n, const double* sc, const int* flag) {
-  if (*flag) return;
-  const double al = sc[SC_ALPHA], be = sc[SC_BETA];
-  for (int64_t i = 2 * ((int64_t)blockIdx.x * 256 + threadIdx.x); i < n; i += (int64_t)gridDim.x * 512) {
-    const double2 pv = *reinterpret_cast<const double2*>(p + i);
-    const double2 zv = fs_row2(z, fs, nfl, i);
-    double2 xv = *reinterpret_cast<const double2*>(x + i);
-    xv.x += al * pv.x;
-    xv.y += al * pv.y;
-    *reinterpret_cast<double2*>(x + i) = xv;
-    *reinterpret_cast<double2*>(p + i) = make_double2(zv.x + be * pv.x, zv.y + be * pv.y);
+  for (int64_t i = W * ((int64_t)blockIdx.x * 256 + threadIdx.x); i < n; i += (int64_t)gridDim.x * 256 * W) {
+    Rows<W> pv, zv, xv;
+    pv.load(p, i);
+    zv.load_fs(z, fs, nfl, i);
+    xv.load(x, i);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      xv.v[w] += al * pv.v[w];
+      zv.v[w] += be * pv.v[w];
+    }
+    xv.store(x, i);
+    zv.store(p, i);
   }
 }
 
@@ -194,19 +268,23 @@ static int grid_pairs(int64_t n) {
   return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
 }
 
-void vec_rupdate(hipStream_t s, double* r, const double* q, const double* fs, int64_t nfl, int64_t n,
-                 const double* sc, const int* flag) {
-  if (nfl % 2 == 0 && n % 2 == 0 && al16(r) && al16(q) && al16(fs))
-    hipLaunchKernelGGL(k_rupdate2, dim3(grid_pairs(n)), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag);
-  else
-    hipLaunchKernelGGL(k_rupdate, dim3(grid_for(n)), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag);
+int vec_rupdate(hipStream_t s, double* r, const double* q, const double* fs, int64_t nfl, int64_t n, double* sc,
+                const int* flag, const double* part, int np, double* rr) {
+  if (nfl % 2 == 0 && n % 2 == 0 && al16(r) && al16(q) && al16(fs)) {
+    const int g = grid_pairs(n);
+    hipLaunchKernelGGL((k_rupdate<2>), dim3(g), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag, part, np, rr);
+    return g;
+  }
+  const int g = grid_for(n);
+  hipLaunchKernelGGL((k_rupdate<1>), dim3(g), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag, part, np, rr);
+  return g;
 }
 void vec_xpay(hipStream_t s, double* x, double* p, const double* z, const double* fs, int64_t nfl, int64_t n,
-              const double* sc, const int* flag) {
+              double* sc, int* flag, const double* part, int np) {
   if (nfl % 2 == 0 && n % 2 == 0 && al16(x) && al16(p) && al16(z) && al16(fs))
-    hipLaunchKernelGGL(k_xpay2, dim3(grid_pairs(n)), dim3(256), 0, s, x, p, z, fs, nfl, n, sc, flag);
+    hipLaunchKernelGGL((k_xpay<2>), dim3(grid_pairs(n)), dim3(256), 0, s, x, p, z, fs, nfl, n, sc, flag, part, np);
   else
-    hipLaunchKernelGGL(k_xpay, dim3(grid_for(n)), dim3(256), 0, s, x, p, z, fs, nfl, n, sc, flag);
+    hipLaunchKernelGGL((k_xpay<1>), dim3(grid_for(n)), dim3(256), 0, s, x, p, z, fs, nfl, n, sc, flag, part, np);
 }
 void vec_xfinal(hipStream_t s, double* x, const double* p, int64_t n, const double* sc) {
   hipLaunchKernelGGL(k_xfinal, dim3(grid_for(n)), dim3(256), 0, s, x, p, n, sc);

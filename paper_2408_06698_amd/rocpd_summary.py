@@ -18,8 +18,8 @@ TRAFFIC_KERNELS = [
     ("elem", "k_elem<double, 3, 3>"),
     ("elem_fp32", "k_elem<float, 3, 3>"),
     ("modal", "k_modal<double, 3, 3>"),
-    ("rupdate", "k_rupdate2("),
-    ("xpay", "k_xpay2("),
+    ("rupdate", "k_rupdate<2>("),
+    ("xpay", "k_xpay<2>("),
     ("proj", "k_proj<3, 3, 0>"),
 ]
 
