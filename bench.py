@@ -124,7 +124,7 @@ def main():
     import synth
     from synth.configs import coefficient_noise
     from paper_2408_06698_amd.hopu import Hopu
-    from paper_2408_06698_amd import FP64, FP32_MFMA
+    from paper_2408_06698_amd import FP64, FP32_MFMA, BF16X2, BF16X3
 
     mesh, field, cfg = synth.make_config(2)
     k, l, dt = cfg["k"], cfg["l"], cfg["dt"]
@@ -173,6 +173,16 @@ def main():
         return a.elapsed_time(b) / reps
     apply64 = apply_ms(FP64)
     apply32 = apply_ms(FP32_MFMA)
+    apply_bf = {p: apply_ms(p) for p in (BF16X2, BF16X3)}
+
+    # residual error of each reduced-precision form against the FP64 apply,
+    # in the M^-1 norm (the dual norm of a residual)
+    def apply_err(prec):
+        r64, rp = h.apply(u0, prec=FP64), h.apply(u0, prec=prec)
+        d = rp - r64
+        wd, _ = h.mass_solve(d, rtol=1e-12)
+        w64, _ = h.mass_solve(r64, rtol=1e-12)
+        return float(torch.sqrt(torch.dot(d, wd) / torch.dot(r64, w64)))
 
     # dominant kernel over the timed region
     tot = {kk: v[1] for kk, v in prof64.items()}
@@ -243,6 +253,19 @@ def main():
         out["mixed"] = {"value": ndof * args.steps / (ms32 * 1e-3), "ms_per_step": ms32 / args.steps,
                         "rel_err_vs_fp64_M_norm": err, "dtype": "fp32-mfma contractions, f64 state/PCG",
                         "speedup_substep": ms64 / ms32, "speedup_apply": apply64 / apply32}
+        # split-BF16 forms (hi/lo, hi/mid/lo) of the same contractions
+        for prec, name in ((BF16X2, "bf16x2"), (BF16X3, "bf16x3")):
+            ub, msb, _ = run(prec, args.steps, 1)
+            d = ub - u64
+            errb = float(torch.sqrt(torch.dot(d, h.mass_apply(d)) / torch.dot(u64, h.mass_apply(u64))))
+            out["mixed_" + name] = {
+                "value": ndof * args.steps / (msb * 1e-3), "ms_per_step": msb / args.steps,
+                "rel_err_vs_fp64_M_norm": errb,
+                "dtype": f"split-bf16 ({'hi/lo' if prec == BF16X2 else 'hi/mid/lo'}) mfma contractions, "
+                         "f64 state/PCG",
+                "speedup_substep": ms64 / msb, "apply_ms": apply_bf[prec], "speedup_apply": apply64 / apply_bf[prec]}
+        out["apply_rel_err_vs_fp64_Minv_norm"] = {"fp32_mfma": apply_err(FP32_MFMA), "bf16x2": apply_err(BF16X2),
+                                                  "bf16x3": apply_err(BF16X3)}
     if not args.no_projection:
         out["projection"] = out_proj
     if args.copy_calib:

@@ -66,9 +66,16 @@ typedef enum {
 
 typedef enum {
   HOPU_FP64 = 0,       /* all contractions in FP64 (MFMA f64) */
-  HOPU_FP32_MFMA = 1   /* basis contractions on FP32 MFMA with FP32 accumulation
+  HOPU_FP32_MFMA = 1,  /* basis contractions on FP32 MFMA with FP32 accumulation
                           inside a tile and FP64 across tiles; state, mass
                           inverse and diagnostics stay FP64 */
+  HOPU_BF16X2 = 2,     /* the same contractions on BF16 MFMA, each operand split
+                          into hi + lo bfloat16 terms (hh + hl + lh kept, about
+                          16 significant bits); FP32 accumulation inside a
+                          tile, FP64 across tiles.  Forward apply and substeps
+                          only (the adjoint returns HOPU_EUNSUPPORTED) */
+  HOPU_BF16X3 = 3      /* hi + mid + lo split (hh, hm, mh, hl, mm, lh kept: the
+                          24 bits of the FP32 value); otherwise as HOPU_BF16X2 */
 } hopu_precision;
 
 enum { HOPU_TERM_VOLUME = 1, HOPU_TERM_CENTRAL = 2, HOPU_TERM_UPWIND = 4, HOPU_TERM_ALL = 7 };

@@ -4,7 +4,7 @@ The compute lives in libhopu.so (hand-written HIP for gfx950); this package
 only marshals arguments.  Importing it does not load the library or touch the
 GPU; `Hopu(...)` does, and fails loudly if the library is missing.
 """
-from ._lib import (FP64, FP32_MFMA, TERM_VOLUME, TERM_CENTRAL, TERM_UPWIND, TERM_ALL,  # noqa: F401
+from ._lib import (FP64, FP32_MFMA, BF16X2, BF16X3, TERM_VOLUME, TERM_CENTRAL, TERM_UPWIND, TERM_ALL,  # noqa: F401
                    HopuError, LIB_PATH, lib)
 
 

@@ -32,6 +32,8 @@ struct hopu_ctx_s {
   DevMesh dm;
   DevTables<double> tb64;
   DevTables<float> tb32;
+  DevTables<BfPack<2>> tbb2;  // split-BF16 tables (hi/lo)
+  DevTables<BfPack<3>> tbb3;  // (hi/mid/lo)
   const double *mass_in = nullptr, *mass_out = nullptr, *prec_in = nullptr, *prec_out = nullptr;
   const float *prec_in32 = nullptr, *prec_out32 = nullptr;  // FP32 preconditioner tables
   const double* vol_dV64 = nullptr;
@@ -145,6 +147,33 @@ static hopu_status upload(hopu_ctx ctx, const T** dst, const std::vector<T>& src
 }
 
 static std::vector<float> to_f32(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+// the split-BF16 element-kernel tables with NS terms, from the FP32-layout set
+template <int NS>
+static hopu_status upload_bf16(hopu_ctx ctx, const FragTables& f32, int ns, DevTables<BfPack<NS>>& t,
+                               const double* wv, const double* wf, const int* pdeg) {
+  if (ns != NS) return HOPU_EINVAL;
+  BfTables b;
+  make_bf16_tables(f32, ctx->sz, NS, b);
+  auto up = [&](const BfPack<NS>** d, const std::vector<uint16_t>& v) {
+    const uint16_t* p = nullptr;
+    hopu_status st = upload(ctx, &p, v);
+    *d = reinterpret_cast<const BfPack<NS>*>(p);
+    return st;
+  };
+  hopu_status st;
+  if ((st = up(&t.modal, b.modal)) || (st = up(&t.vol_V, b.vol_V)) || (st = up(&t.vol_dVT, b.vol_dVT)) ||
+      (st = up(&t.fac_Tr, b.fac_Tr)) || (st = up(&t.fac_TrT, b.fac_TrT)) || (st = up(&t.fac_K, b.fac_K)) ||
+      (st = up(&t.fac_Psi, b.fac_Psi)) || (st = up(&t.fac_PsiT, b.fac_PsiT)) || (st = up(&t.fac_KT, b.fac_KT)) ||
+      (st = up(&t.dual, b.dual)))
+    return st;
+  t.vol_dV = nullptr;
+  t.vol_VT = nullptr;
+  t.wv = wv;
+  t.wf = wf;
+  t.psi_deg = pdeg;
+  return HOPU_OK;
+}
 
 #define DISPATCH(DIM, K, ...)                              \
   switch ((DIM) * 10 + (K)) {                               \
@@ -265,6 +294,8 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     a.wv = b.wv = wv;
     a.wf = b.wf = wf;
     a.psi_deg = b.psi_deg = pdeg;
+    TRY(upload_bf16(ctx, f32, 2, ctx->tbb2, wv, wf, pdeg));
+    TRY(upload_bf16(ctx, f32, 3, ctx->tbb3, wv, wf, pdeg));
     TRY(up64(&ctx->mass_in, f64.mass_in));
     TRY(up64(&ctx->mass_out, f64.mass_out));
     TRY(up64(&ctx->prec_in, f64.prec_in));
@@ -380,6 +411,8 @@ static hopu_status do_modal(hopu_ctx ctx, const double* u, hopu_precision prec, 
   float* d32 = second ? ctx->mu32 : ctx->m32;
   DISPATCH(ctx->dim, ctx->k, {
     if (prec == HOPU_FP64) launch_modal<double, D, KK>(ctx->stream, u, d64, ctx->dm, ctx->tb64.modal);
+    else if (prec == HOPU_BF16X2) launch_modal_bf<2, D, KK>(ctx->stream, u, d32, ctx->dm, ctx->tbb2.modal);
+    else if (prec == HOPU_BF16X3) launch_modal_bf<3, D, KK>(ctx->stream, u, d32, ctx->dm, ctx->tbb3.modal);
     else launch_modal<float, D, KK>(ctx->stream, u, d32, ctx->dm, ctx->tb32.modal);
   });
   prof_end(ctx);
@@ -393,6 +426,8 @@ static hopu_status do_apply(hopu_ctx ctx, const double* u, double* r, int terms,
   prof_begin(ctx, PROF_ELEM);
   DISPATCH(ctx->dim, ctx->k, {
     if (prec == HOPU_FP64) launch_elem<double, D, KK>(ctx->stream, ctx->m64, r, ctx->slot, ctx->dm, ctx->tb64, terms, diss_part, eta_nd);
+    else if (prec == HOPU_BF16X2) launch_elem_bf<2, D, KK>(ctx->stream, ctx->m32, r, ctx->slot, ctx->dm, ctx->tbb2, terms, diss_part);
+    else if (prec == HOPU_BF16X3) launch_elem_bf<3, D, KK>(ctx->stream, ctx->m32, r, ctx->slot, ctx->dm, ctx->tbb3, terms, diss_part);
     else launch_elem<float, D, KK>(ctx->stream, ctx->m32, r, ctx->slot, ctx->dm, ctx->tb32, terms, diss_part, eta_nd);
   });
   prof_end(ctx);
@@ -429,9 +464,10 @@ static void do_mass(hopu_ctx ctx, int mode, const double* x, double* y, const in
 }
 
 static hopu_status check_prec(hopu_ctx ctx, hopu_precision prec) {
-  if (prec != HOPU_FP64 && prec != HOPU_FP32_MFMA) return fail(ctx, HOPU_EINVAL, "unknown precision");
+  if ((int)prec < (int)HOPU_FP64 || (int)prec > (int)HOPU_BF16X3) return fail(ctx, HOPU_EINVAL, "unknown precision");
   return HOPU_OK;
 }
+static bool is_bf16(hopu_precision prec) { return prec == HOPU_BF16X2 || prec == HOPU_BF16X3; }
 
 extern "C" hopu_status hopu_convection_apply(hopu_ctx ctx, const double* u, double* r, int terms, hopu_precision prec) {
   if (!ctx) return HOPU_EINVAL;
@@ -767,7 +803,7 @@ extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_s
     else if (nh == 2) vec_comb3(s, w, wh[0], wh[1], 2.0, -1.0, 0.0, ctx->n_dof);
     else vec_comb3(s, w, wh[0], wh[1], 3.0, -3.0, 1.0, ctx->n_dof);
     int its = 0;
-    st = pcg(ctx, ctx->rc, w, ctx->rtol, ctx->max_it, &its, prec == HOPU_FP32_MFMA);
+    st = pcg(ctx, ctx->rc, w, ctx->rtol, ctx->max_it, &its, prec != HOPU_FP64);
     if (st) return st;
     if (diag_dev) vec_copy_diag(s, diag_dev + (int64_t)(st_i + 1) * 5 + 3, ctx->sc, ctx->flag);
     vec_axpy(s, u, w, -dt, ctx->n_dof);
@@ -956,6 +992,7 @@ extern "C" hopu_status hopu_convection_vjp(hopu_ctx ctx, const double* u, const 
   if (!ctx) return HOPU_EINVAL;
   if (!u || !mu || !out) return fail(ctx, HOPU_EINVAL, "NULL vector");
   if (check_prec(ctx, prec)) return HOPU_EINVAL;
+  if (is_bf16(prec)) return fail(ctx, HOPU_EUNSUPPORTED, "the adjoint has FP64 and FP32-MFMA forms only");
   refresh_dm(ctx);
   do_vjp(ctx, u, mu, out, prec);
   HCHECK(hipGetLastError());
@@ -974,7 +1011,7 @@ extern "C" int64_t hopu_substeps_vjp_workspace(hopu_ctx ctx, int n_steps, int ck
 static hopu_status substep(hopu_ctx ctx, double* u, double* w, double dt, hopu_precision prec) {
   hopu_status st = do_apply(ctx, u, ctx->rc, HOPU_TERM_ALL, prec, nullptr);
   if (st) return st;
-  st = pcg(ctx, ctx->rc, w, ctx->rtol, ctx->max_it, nullptr, prec == HOPU_FP32_MFMA);
+  st = pcg(ctx, ctx->rc, w, ctx->rtol, ctx->max_it, nullptr, prec != HOPU_FP64);
   if (st) return st;
   vec_axpy(ctx->stream, u, w, -dt, ctx->n_dof);
   return HOPU_OK;
@@ -987,6 +1024,7 @@ extern "C" hopu_status hopu_substeps_vjp(hopu_ctx ctx, const double* u0, double 
   if (!u0 || !lam_N || !lam_0 || !ws) return fail(ctx, HOPU_EINVAL, "NULL pointer");
   if (n_steps < 0 || ckpt_every < 1 || !std::isfinite(dt)) return fail(ctx, HOPU_EINVAL, "bad step arguments");
   if (check_prec(ctx, prec)) return HOPU_EINVAL;
+  if (is_bf16(prec)) return fail(ctx, HOPU_EUNSUPPORTED, "the adjoint has FP64 and FP32-MFMA forms only");
   const int64_t need = hopu_substeps_vjp_workspace(ctx, n_steps, ckpt_every);
   if (ws_bytes < need) return fail(ctx, HOPU_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
   refresh_dm(ctx);

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 namespace hopu {
@@ -411,6 +412,46 @@ FragDims frag_dims(const Sizes& s) {
   d.NJT = (s.n + 15) / 16;
   d.NMQ = 4 * d.NMT;
   return d;
+}
+
+std::vector<uint16_t> split_bf16_table(const std::vector<double>& t, int outer, int nsteps, int inner, int ns) {
+  const int ng = (nsteps + 3) / 4;
+  std::vector<uint16_t> out((size_t)outer * ng * inner * 64 * ns * 4, 0);
+  for (int o = 0; o < outer; ++o)
+    for (int sg = 0; sg < ng; ++sg)
+      for (int in = 0; in < inner; ++in)
+        for (int l = 0; l < 64; ++l)
+          for (int j = 0; j < 4; ++j) {
+            const int st = 4 * sg + j;
+            if (st >= nsteps) continue;
+            float r = (float)t[(((size_t)o * nsteps + st) * inner + in) * 64 + l];
+            uint16_t* dst = &out[((((size_t)o * ng + sg) * inner + in) * 64 + l) * ns * 4];
+            for (int term = 0; term < ns; ++term) {
+              uint32_t u;
+              std::memcpy(&u, &r, 4);
+              const uint32_t h = u & 0xFFFF0000u;
+              float hv;
+              std::memcpy(&hv, &h, 4);
+              dst[term * 4 + j] = (uint16_t)(h >> 16);
+              r -= hv;
+            }
+          }
+  return out;
+}
+
+void make_bf16_tables(const FragTables& f, const Sizes& s, int ns, BfTables& b) {
+  const FragDims d = frag_dims(s);
+  const int nfc = s.dim + 1;
+  b.modal = split_bf16_table(f.modal, d.NMT, d.NK, 1, ns);
+  b.vol_V = split_bf16_table(f.vol_V, d.NQVT, d.NPK, 1, ns);
+  b.vol_dVT = split_bf16_table(f.vol_dVT, d.NQVT, 4, s.dim * d.NAT, ns);
+  b.fac_Tr = split_bf16_table(f.fac_Tr, nfc * d.NQFT, d.NPK, 1, ns);
+  b.fac_TrT = split_bf16_table(f.fac_TrT, nfc * d.NQFT, 4, d.NAT, ns);
+  b.fac_K = split_bf16_table(f.fac_K, nfc * d.NFJT, d.NPK, 1, ns);
+  b.fac_Psi = split_bf16_table(f.fac_Psi, d.NQFT, d.NFK, 1, ns);
+  b.fac_PsiT = split_bf16_table(f.fac_PsiT, d.NQFT, 4, d.NFJT, ns);
+  b.fac_KT = split_bf16_table(f.fac_KT, nfc * d.NAT, d.NFK, 1, ns);
+  b.dual = split_bf16_table(f.dual, d.NJT * s.dim * d.NAT, 4, 1, ns);
 }
 
 void make_frag_tables(const RefTables& t, RowMap rm, FragTables& f) {

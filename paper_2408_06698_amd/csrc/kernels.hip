@@ -1,5 +1,6 @@
 // HIP kernels for gfx950.  See kernels.hpp for the batch/tile conventions.
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -33,6 +34,64 @@ template <> struct MF<float> {
 
 template <typename V> __device__ __forceinline__ V vzero() { V v = {0, 0, 0, 0}; return v; }
 
+// Split-BF16 contractions on the 16x16x16 BF16 MFMA with FP32 accumulation.
+// Four consecutive K steps of the 16x16x4 FP32 form make one MFMA: register
+// j of lane group g carries step 4s + j of that group on both operands, so
+// the FP32 form's per-lane values and output layout (row 4g + i in register
+// i) carry over unchanged, and the tables are the FP32 ones regrouped.  Each
+// operand is split by truncation into NS bfloat16 terms (hi, [mid,] lo; each
+// term the leading 8 bits of what the previous ones leave), and products two
+// levels below the leading one or lower are dropped: NS = 2 keeps hh, hl,
+// lh (about 16 significant bits), NS = 3 keeps hh, hm, mh, hl, mm, lh (the
+// 24 bits of the FP32 value).
+template <int NS>
+using BfTab = BfPack<(NS > 0 ? NS : 1)>;
+template <typename T, int NS>
+using TabT = std::conditional_t<NS == 0, T, BfTab<NS>>;
+
+template <int NS>
+__device__ __forceinline__ BfTab<NS> bf_split4(float b0, float b1, float b2, float b3) {
+  BfTab<NS> p;
+  const float v[4] = {b0, b1, b2, b3};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float r = v[j];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const uint32_t h = __float_as_uint(r) & 0xFFFF0000u;
+      p.v[t][j] = (short)(h >> 16);
+      r -= __uint_as_float(h);
+    }
+  }
+  return p;
+}
+
+// steps s0 .. s0+3 of a lane's per-step values (zero past the end)
+template <int NS, int N, typename T>
+__device__ __forceinline__ BfTab<NS> bf_steps(const T (&b)[N], int s0) {
+  return bf_split4<NS>(s0 < N ? (float)b[s0] : 0.f, s0 + 1 < N ? (float)b[s0 + 1] : 0.f,
+                       s0 + 2 < N ? (float)b[s0 + 2] : 0.f, s0 + 3 < N ? (float)b[s0 + 3] : 0.f);
+}
+
+__device__ __forceinline__ f4 mfma_bf(bf16x4_t a, bf16x4_t b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+// c += a b over one group of four steps, smaller products first
+template <int NS>
+__device__ __forceinline__ f4 mma_bf(const BfTab<NS>& a, const BfTab<NS>& b, f4 c) {
+  if constexpr (NS == 2) {
+    c = mfma_bf(a.v[1], b.v[0], c);
+    c = mfma_bf(a.v[0], b.v[1], c);
+  } else {
+    c = mfma_bf(a.v[2], b.v[0], c);
+    c = mfma_bf(a.v[1], b.v[1], c);
+    c = mfma_bf(a.v[0], b.v[2], c);
+    c = mfma_bf(a.v[1], b.v[0], c);
+    c = mfma_bf(a.v[0], b.v[1], c);
+  }
+  return mfma_bf(a.v[0], b.v[0], c);
+}
+
 // Batches are assigned so that consecutive batches land on the same XCD
 // (workgroups are dealt round-robin over the 8 XCDs).
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
@@ -53,9 +112,9 @@ __device__ __forceinline__ void load_J(const double* g, double J[D][D]) {
 
 // ------------------------------------------------------------------ modal
 // m_T = Dinv (S_T x_T): dual coefficients -> modal coefficients (rho layout).
-template <typename T, int D, int KK>
+template <typename T, int D, int KK, int NS = 0>
 __global__ __launch_bounds__(256) void k_modal(const double* __restrict__ x, T* __restrict__ m,
-                                               DevMesh mesh, const T* __restrict__ frag) {
+                                               DevMesh mesh, const TabT<T, NS>* __restrict__ frag) {
   using C = Cfg<D, KK>;
   using M = MF<T>;
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
@@ -82,11 +141,22 @@ __global__ __launch_bounds__(256) void k_modal(const double* __restrict__ x, T* 
     }
     xh[kk] = (T)v;
   }
+  constexpr int NG = (C::NK + 3) / 4;  // split-BF16 step groups
+  BfTab<NS> xs[NG];
+  if constexpr (NS > 0) {
+#pragma unroll
+    for (int sg = 0; sg < NG; ++sg) xs[sg] = bf_steps<NS>(xh, 4 * sg);
+  }
 #pragma unroll
   for (int mt = 0; mt < C::NMT; ++mt) {
     typename M::V acc = vzero<typename M::V>();
+    if constexpr (NS == 0) {
 #pragma unroll
-    for (int kk = 0; kk < C::NK; ++kk) acc = M::mma(frag[(mt * C::NK + kk) * 64 + lane], xh[kk], acc);
+      for (int kk = 0; kk < C::NK; ++kk) acc = M::mma(frag[(mt * C::NK + kk) * 64 + lane], xh[kk], acc);
+    } else {
+#pragma unroll
+      for (int sg = 0; sg < NG; ++sg) acc = mma_bf<NS>(frag[(mt * NG + sg) * 64 + lane], xs[sg], acc);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = 16 * mt + M::row(i, g);
@@ -149,10 +219,11 @@ template <int D, int NAT> struct ElemAcc<float, D, NAT> {
 //           with [[.]] = own - neighbour and n the own outward normal;
 // then r^ = S Dinv^T r_modal.  Facet rows go to per-element slots, interior
 // rows straight to r.
-template <typename T, int D, int KK>
+// NS > 0 (T = float): the contractions in split BF16 (see mma_bf).
+template <typename T, int D, int KK, int NS = 0>
 __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* __restrict__ r,
                                               double* __restrict__ rslot, DevMesh mesh,
-                                              DevTables<T> tb, int terms,
+                                              DevTables<TabT<T, NS>> tb, int terms,
                                               double* __restrict__ diss_part, double* __restrict__ eta_nd) {
   using C = Cfg<D, KK>;
   using M = MF<T>;
@@ -180,6 +251,15 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int kk = 0; kk < C::NPK; ++kk) mB[a][kk] = m[ee * C::NM + kk * 4 * D + 4 * a + g];
+  // split-BF16 form: the modal coefficients split once, in groups of four steps
+  constexpr int NGP = (C::NPK + 3) / 4;
+  BfTab<NS> mS[D][NGP];
+  if constexpr (NS > 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int sg = 0; sg < NGP; ++sg) mS[a][sg] = bf_steps<NS>(mB[a], 4 * sg);
+  }
 
   ElemAcc<T, D, C::NAT> acc;
   acc.init();
@@ -202,11 +282,20 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
       V u[D];
 #pragma unroll
       for (int a = 0; a < D; ++a) u[a] = vzero<V>();
+      if constexpr (NS == 0) {
 #pragma unroll
-      for (int kk = 0; kk < C::NPK; ++kk) {
-        const T av = tb.vol_V[(qt * C::NPK + kk) * 64 + lane];
+        for (int kk = 0; kk < C::NPK; ++kk) {
+          const T av = tb.vol_V[(qt * C::NPK + kk) * 64 + lane];
 #pragma unroll
-        for (int a = 0; a < D; ++a) u[a] = M::mma(av, mB[a][kk], u[a]);
+          for (int a = 0; a < D; ++a) u[a] = M::mma(av, mB[a][kk], u[a]);
+        }
+      } else {
+#pragma unroll
+        for (int sg = 0; sg < NGP; ++sg) {
+          const BfTab<NS> av = tb.vol_V[(qt * NGP + sg) * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < D; ++a) u[a] = mma_bf<NS>(av, mS[a][sg], u[a]);
+        }
       }
       // flux F_ab = w sgn/det^2 (G u^)_a u^_b formed per MFMA operand
       double uh[D][4], gu[D][4];
@@ -225,16 +314,34 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
         }
       }
       acc.begin();
+      if constexpr (NS == 0) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int bb = 0; bb < D; ++bb)
+          for (int bb = 0; bb < D; ++bb)
+#pragma unroll
+            for (int at = 0; at < C::NAT; ++at) {
+              const T av = tb.vol_dVT[(((qt * 4 + i) * D + bb) * C::NAT + at) * 64 + lane];
+#pragma unroll
+              for (int a = 0; a < D; ++a) acc.tile(a, at) = M::mma(av, (T)(gu[a][i] * uh[bb][i]), acc.tile(a, at));
+            }
+      } else {
+        // the four points i of the tile are one step group
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) {
+          BfTab<NS> fb[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a)
+            fb[a] = bf_split4<NS>((float)(gu[a][0] * uh[bb][0]), (float)(gu[a][1] * uh[bb][1]),
+                                  (float)(gu[a][2] * uh[bb][2]), (float)(gu[a][3] * uh[bb][3]));
 #pragma unroll
           for (int at = 0; at < C::NAT; ++at) {
-            const T av = tb.vol_dVT[(((qt * 4 + i) * D + bb) * C::NAT + at) * 64 + lane];
+            const BfTab<NS> av = tb.vol_dVT[((qt * D + bb) * C::NAT + at) * 64 + lane];
 #pragma unroll
-            for (int a = 0; a < D; ++a) acc.tile(a, at) = M::mma(av, (T)(gu[a][i] * uh[bb][i]), acc.tile(a, at));
+            for (int a = 0; a < D; ++a) acc.tile(a, at) = mma_bf<NS>(av, fb[a], acc.tile(a, at));
           }
+        }
+      }
       acc.end();
     }
   }
@@ -263,6 +370,13 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int kk = 0; kk < C::NPK; ++kk) nB[a][kk] = m[(int64_t)en * C::NM + kk * 4 * D + 4 * a + g];
+      BfTab<NS> nS[D][NGP];
+      if constexpr (NS > 0) {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int sg = 0; sg < NGP; ++sg) nS[a][sg] = bf_steps<NS>(nB[a], 4 * sg);
+      }
 
       // moments of the physical jump against psi_j (deg psi_j <= l)
       T c1[D][C::NFJT][4];
@@ -272,14 +386,27 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
           V ro[D], rn[D];
 #pragma unroll
           for (int a = 0; a < D; ++a) { ro[a] = vzero<V>(); rn[a] = vzero<V>(); }
+          if constexpr (NS == 0) {
 #pragma unroll
-          for (int kk = 0; kk < C::NPK; ++kk) {
-            const T ao = tb.fac_K[((f * C::NFJT + jt) * C::NPK + kk) * 64 + lane];
-            const T an = tb.fac_K[((fp * C::NFJT + jt) * C::NPK + kk) * 64 + lane];
+            for (int kk = 0; kk < C::NPK; ++kk) {
+              const T ao = tb.fac_K[((f * C::NFJT + jt) * C::NPK + kk) * 64 + lane];
+              const T an = tb.fac_K[((fp * C::NFJT + jt) * C::NPK + kk) * 64 + lane];
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-              ro[a] = M::mma(ao, mB[a][kk], ro[a]);
-              rn[a] = M::mma(an, nB[a][kk], rn[a]);
+              for (int a = 0; a < D; ++a) {
+                ro[a] = M::mma(ao, mB[a][kk], ro[a]);
+                rn[a] = M::mma(an, nB[a][kk], rn[a]);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int sg = 0; sg < NGP; ++sg) {
+              const BfTab<NS> ao = tb.fac_K[((f * C::NFJT + jt) * NGP + sg) * 64 + lane];
+              const BfTab<NS> an = tb.fac_K[((fp * C::NFJT + jt) * NGP + sg) * 64 + lane];
+#pragma unroll
+              for (int a = 0; a < D; ++a) {
+                ro[a] = mma_bf<NS>(ao, mS[a][sg], ro[a]);
+                rn[a] = mma_bf<NS>(an, nS[a][sg], rn[a]);
+              }
             }
           }
 #pragma unroll
@@ -309,22 +436,45 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
         V to[D], tn[D], pj[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) { to[a] = vzero<V>(); tn[a] = vzero<V>(); pj[a] = vzero<V>(); }
+        if constexpr (NS == 0) {
 #pragma unroll
-        for (int kk = 0; kk < C::NPK; ++kk) {
-          const T ao = tb.fac_Tr[((f * C::NQFT + qt) * C::NPK + kk) * 64 + lane];
-          const T an = tb.fac_Tr[((fp * C::NQFT + qt) * C::NPK + kk) * 64 + lane];
+          for (int kk = 0; kk < C::NPK; ++kk) {
+            const T ao = tb.fac_Tr[((f * C::NQFT + qt) * C::NPK + kk) * 64 + lane];
+            const T an = tb.fac_Tr[((fp * C::NQFT + qt) * C::NPK + kk) * 64 + lane];
 #pragma unroll
-          for (int a = 0; a < D; ++a) {
-            to[a] = M::mma(ao, mB[a][kk], to[a]);
-            tn[a] = M::mma(an, nB[a][kk], tn[a]);
+            for (int a = 0; a < D; ++a) {
+              to[a] = M::mma(ao, mB[a][kk], to[a]);
+              tn[a] = M::mma(an, nB[a][kk], tn[a]);
+            }
           }
-        }
-        if (up) {
+          if (up) {
 #pragma unroll
-          for (int jk = 0; jk < C::NFK; ++jk) {
-            const T ap = tb.fac_Psi[(qt * C::NFK + jk) * 64 + lane];
+            for (int jk = 0; jk < C::NFK; ++jk) {
+              const T ap = tb.fac_Psi[(qt * C::NFK + jk) * 64 + lane];
 #pragma unroll
-            for (int a = 0; a < D; ++a) pj[a] = M::mma(ap, c1[a][jk / 4][jk % 4], pj[a]);
+              for (int a = 0; a < D; ++a) pj[a] = M::mma(ap, c1[a][jk / 4][jk % 4], pj[a]);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int sg = 0; sg < NGP; ++sg) {
+            const BfTab<NS> ao = tb.fac_Tr[((f * C::NQFT + qt) * NGP + sg) * 64 + lane];
+            const BfTab<NS> an = tb.fac_Tr[((fp * C::NQFT + qt) * NGP + sg) * 64 + lane];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              to[a] = mma_bf<NS>(ao, mS[a][sg], to[a]);
+              tn[a] = mma_bf<NS>(an, nS[a][sg], tn[a]);
+            }
+          }
+          if (up) {
+            // steps jk = 4 jt + i of the moments: group jt holds c1[.][jt][0..3]
+#pragma unroll
+            for (int jt = 0; jt < C::NFJT; ++jt) {
+              const BfTab<NS> ap = tb.fac_Psi[(qt * C::NFJT + jt) * 64 + lane];
+#pragma unroll
+              for (int a = 0; a < D; ++a)
+                pj[a] = mma_bf<NS>(ap, bf_split4<NS>(c1[a][jt][0], c1[a][jt][1], c1[a][jt][2], c1[a][jt][3]), pj[a]);
+            }
           }
         }
         T h[D][4], aw[D][4];
@@ -372,24 +522,48 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
           }
         }
         acc.begin();
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int at = 0; at < C::NAT; ++at) {
-            const T av = tb.fac_TrT[(((f * C::NQFT + qt) * 4 + i) * C::NAT + at) * 64 + lane];
-#pragma unroll
-            for (int a = 0; a < D; ++a) acc.tile(a, at) = M::mma(av, h[a][i], acc.tile(a, at));
-          }
-        acc.end();
-        if (up) {
+        if constexpr (NS == 0) {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int jt = 0; jt < C::NFJT; ++jt) {
-              const T ap = tb.fac_PsiT[((qt * 4 + i) * C::NFJT + jt) * 64 + lane];
+            for (int at = 0; at < C::NAT; ++at) {
+              const T av = tb.fac_TrT[(((f * C::NQFT + qt) * 4 + i) * C::NAT + at) * 64 + lane];
 #pragma unroll
-              for (int a = 0; a < D; ++a) c2[a][jt] = M::mma(ap, aw[a][i], c2[a][jt]);
+              for (int a = 0; a < D; ++a) acc.tile(a, at) = M::mma(av, h[a][i], acc.tile(a, at));
             }
+        } else {
+          BfTab<NS> hb[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) hb[a] = bf_split4<NS>(h[a][0], h[a][1], h[a][2], h[a][3]);
+#pragma unroll
+          for (int at = 0; at < C::NAT; ++at) {
+            const BfTab<NS> av = tb.fac_TrT[((f * C::NQFT + qt) * C::NAT + at) * 64 + lane];
+#pragma unroll
+            for (int a = 0; a < D; ++a) acc.tile(a, at) = mma_bf<NS>(av, hb[a], acc.tile(a, at));
+          }
+        }
+        acc.end();
+        if (up) {
+          if constexpr (NS == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int jt = 0; jt < C::NFJT; ++jt) {
+                const T ap = tb.fac_PsiT[((qt * 4 + i) * C::NFJT + jt) * 64 + lane];
+#pragma unroll
+                for (int a = 0; a < D; ++a) c2[a][jt] = M::mma(ap, aw[a][i], c2[a][jt]);
+              }
+          } else {
+            BfTab<NS> ab[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) ab[a] = bf_split4<NS>(aw[a][0], aw[a][1], aw[a][2], aw[a][3]);
+#pragma unroll
+            for (int jt = 0; jt < C::NFJT; ++jt) {
+              const BfTab<NS> ap = tb.fac_PsiT[(qt * C::NFJT + jt) * 64 + lane];
+#pragma unroll
+              for (int a = 0; a < D; ++a) c2[a][jt] = mma_bf<NS>(ap, ab[a], c2[a][jt]);
+            }
+          }
         }
       }
       if (ETA && eta_nd) {
@@ -423,14 +597,29 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
             }
           }
         acc.begin();
+        if constexpr (NS == 0) {
 #pragma unroll
-        for (int jk = 0; jk < C::NFK; ++jk)
+          for (int jk = 0; jk < C::NFK; ++jk)
 #pragma unroll
-          for (int at = 0; at < C::NAT; ++at) {
-            const T av = tb.fac_KT[((f * C::NAT + at) * C::NFK + jk) * 64 + lane];
+            for (int at = 0; at < C::NAT; ++at) {
+              const T av = tb.fac_KT[((f * C::NAT + at) * C::NFK + jk) * 64 + lane];
 #pragma unroll
-            for (int a = 0; a < D; ++a) acc.tile(a, at) = M::mma(av, cc[a][jk / 4][jk % 4], acc.tile(a, at));
+              for (int a = 0; a < D; ++a) acc.tile(a, at) = M::mma(av, cc[a][jk / 4][jk % 4], acc.tile(a, at));
+            }
+        } else {
+#pragma unroll
+          for (int jt = 0; jt < C::NFJT; ++jt) {
+            BfTab<NS> cb[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) cb[a] = bf_split4<NS>(cc[a][jt][0], cc[a][jt][1], cc[a][jt][2], cc[a][jt][3]);
+#pragma unroll
+            for (int at = 0; at < C::NAT; ++at) {
+              const BfTab<NS> av = tb.fac_KT[((f * C::NAT + at) * C::NFJT + jt) * 64 + lane];
+#pragma unroll
+              for (int a = 0; a < D; ++a) acc.tile(a, at) = mma_bf<NS>(av, cb[a], acc.tile(a, at));
+            }
           }
+        }
         acc.end();
       }
     }
@@ -444,10 +633,18 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int at = 0; at < C::NAT; ++at)
+      for (int at = 0; at < C::NAT; ++at) {
+        if constexpr (NS == 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          o = M::mma(tb.dual[((((jt * D + a) * C::NAT + at) * 4) + i) * 64 + lane], (T)acc.get(a, at, i), o);
+          for (int i = 0; i < 4; ++i)
+            o = M::mma(tb.dual[((((jt * D + a) * C::NAT + at) * 4) + i) * 64 + lane], (T)acc.get(a, at, i), o);
+        } else {
+          o = mma_bf<NS>(tb.dual[((jt * D + a) * C::NAT + at) * 64 + lane],
+                         bf_split4<NS>((float)acc.get(a, at, 0), (float)acc.get(a, at, 1), (float)acc.get(a, at, 2),
+                                       (float)acc.get(a, at, 3)),
+                         o);
+        }
+      }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int j = 16 * jt + M::row(i, g);
@@ -913,6 +1110,12 @@ void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, con
   const int64_t blocks = (waves + 3) / 4;
   HOPU_LAUNCH((k_modal<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, x, m, mesh, frag);
 }
+template <int NS, int D, int KK>
+void launch_modal_bf(hipStream_t s, const double* x, float* m, const DevMesh& mesh, const BfPack<NS>* frag) {
+  const int64_t waves = (mesh.E + 15) / 16;
+  const int64_t blocks = (waves + 3) / 4;
+  HOPU_LAUNCH((k_modal<float, D, KK, NS>), dim3((unsigned)blocks), dim3(256), 0, s, x, m, mesh, frag);
+}
 
 template <typename T, int D, int KK>
 void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMesh& mesh,
@@ -922,6 +1125,13 @@ void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMe
   HOPU_LAUNCH((k_elem<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, m, r, slot, mesh, tb,
                      terms, diss_part, eta_nd);
   (void)sizeof(C);
+}
+template <int NS, int D, int KK>
+void launch_elem_bf(hipStream_t s, const float* m, double* r, double* slot, const DevMesh& mesh,
+                    const DevTables<BfPack<NS>>& tb, int terms, double* diss_part) {
+  const int64_t blocks = (mesh.nb + 3) / 4;
+  HOPU_LAUNCH((k_elem<float, D, KK, NS>), dim3((unsigned)blocks), dim3(256), 0, s, m, r, slot, mesh, tb, terms,
+              diss_part, nullptr);
 }
 
 template <int D, int KK>
@@ -979,6 +1189,14 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
                                            const DevTables<double>&, int, double*, double*);                \
   template void launch_elem<float, D, KK>(hipStream_t, const float*, double*, double*, const DevMesh&,      \
                                           const DevTables<float>&, int, double*, double*);                  \
+  template void launch_modal_bf<2, D, KK>(hipStream_t, const double*, float*, const DevMesh&,               \
+                                          const BfPack<2>*);                                                \
+  template void launch_modal_bf<3, D, KK>(hipStream_t, const double*, float*, const DevMesh&,               \
+                                          const BfPack<3>*);                                                \
+  template void launch_elem_bf<2, D, KK>(hipStream_t, const float*, double*, double*, const DevMesh&,       \
+                                         const DevTables<BfPack<2>>&, int, double*);                        \
+  template void launch_elem_bf<3, D, KK>(hipStream_t, const float*, double*, double*, const DevMesh&,       \
+                                         const DevTables<BfPack<3>>&, int, double*);                        \
   template int launch_mass<D, KK>(hipStream_t, int, const double*, double*, double*, const DevMesh&,        \
                                   const double*, const double*, const int*, double*, const float*,          \
                                   const float*);                                                            \

@@ -37,6 +37,15 @@ struct Cfg {
 };
 
 
+// Split-BF16 fragment of a 16x16x16 BF16 MFMA operand: a lane's four K
+// values as NS bfloat16 terms (hi, [mid,] lo) whose sum is the FP32 value
+// to 8 NS significant bits (raw bfloat16 bits).
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+template <int NS>
+struct BfPack {
+  bf16x4_t v[NS];
+};
+
 // Device pointers to one precision's fragment tables and weights.
 template <typename T>
 struct DevTables {

@@ -9,6 +9,13 @@ void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, con
 template <typename T, int D, int KK>
 void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMesh& mesh,
                  const DevTables<T>& tb, int terms, double* diss_part, double* eta_nd);
+// The same two kernels with split-BF16 contractions (NS = 2: hi/lo, 3:
+// hi/mid/lo), FP32 modal coefficients and the regrouped tables.
+template <int NS, int D, int KK>
+void launch_modal_bf(hipStream_t s, const double* x, float* m, const DevMesh& mesh, const BfPack<NS>* frag);
+template <int NS, int D, int KK>
+void launch_elem_bf(hipStream_t s, const float* m, double* r, double* slot, const DevMesh& mesh,
+                    const DevTables<BfPack<NS>>& tb, int terms, double* diss_part);
 // y = M x (mode 0) or the preconditioner applied to x (mode 1): interior rows
 // into out, facet rows as one contribution per side into fs ([2][F][NF]);
 // with part set, also the per-block partials of x . y.  With fin32/fout32

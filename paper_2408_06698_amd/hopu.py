@@ -7,7 +7,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from ._lib import check, FP64, FP32_MFMA, TERM_ALL
+from ._lib import check, FP64, FP32_MFMA, BF16X2, BF16X3, TERM_ALL  # noqa: F401
 
 
 def _ptr(t):

@@ -48,6 +48,8 @@ def test_fullsize_apply_vjp_mass(cfg):
     ref = O.residual(sp, x, l, elems=patch)
     _check(host(h.apply(u)), ref, rows_f, rows_i, 1e-12, "apply fp64")
     _check(host(h.apply(u, prec=1)), ref, rows_f, rows_i, 1e-5, "apply fp32")
+    _check(host(h.apply(u, prec=2)), ref, rows_f, rows_i, 3e-3, "apply bf16x2")
+    _check(host(h.apply(u, prec=3)), ref, rows_f, rows_i, 1e-5, "apply bf16x3")
     mu = np.random.default_rng(7).standard_normal(sp.n_dof)
     gref = O.vjp(sp, x, mu, l, elems=patch)
     _check(host(h.vjp(u, dev(mu))), gref, rows_f, rows_i, 1e-12, "vjp fp64")
@@ -70,6 +72,7 @@ def test_fullsize_channel_k5_apply():
     ref = O.residual(sp, x, c["l"], elems=patch)
     _check(host(h.apply(u)), ref, rows_f, rows_i, 1e-12, "apply fp64 k5")
     _check(host(h.apply(u, prec=1)), ref, rows_f, rows_i, 1e-5, "apply fp32 k5")
+    _check(host(h.apply(u, prec=3)), ref, rows_f, rows_i, 1e-5, "apply bf16x3 k5")
 
 
 def test_fullsize_projection_properties():

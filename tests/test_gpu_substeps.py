@@ -89,12 +89,16 @@ def test_diagnostics_and_energy_identity():
     assert abs(x @ r - D) <= 1e-11 * D
 
 
-@pytest.mark.parametrize("cfg,n,k", [(1, (16, 16), 2), (2, (4, 3, 3), 3)])
-def test_substeps_mixed_precision(cfg, n, k):
-    """Mixed-precision substeps (FP32-MFMA residual and preconditioner
-    contractions, FP64 state, mass operator and PCG): the PCG still meets the
-    FP64 tolerance at every substep, and the chain stays within the FP32
-    contraction error of the oracle's FP64 chain."""
+@pytest.mark.parametrize("cfg,n,k,prec", [(1, (16, 16), 2, 1), (2, (4, 3, 3), 3, 1), (1, (16, 16), 2, 2),
+                                         (2, (4, 3, 3), 3, 2), (2, (4, 3, 3), 3, 3)])
+def test_substeps_mixed_precision(cfg, n, k, prec):
+    """Mixed-precision substeps (FP32-MFMA or split-BF16 residual
+    contractions, FP32 preconditioner contractions, FP64 state, mass operator
+    and PCG): the PCG still meets the FP64 tolerance at every substep, and
+    the chain stays within the contraction error of the oracle's FP64 chain.
+    FP32-MFMA and hi/mid/lo: 1e-6.  hi/lo: its residual bound (3e-3, the
+    apply tests) times the chain's relative increment sum_i |u_i+1 - u_i|/|u_i|
+    (the state error is dt times the residual errors, summed), doubled."""
     mesh, sp, x, c = case(cfg, n, k)
     l = k - 1
     h = gpu_space(mesh, k)
@@ -102,10 +106,12 @@ def test_substeps_mixed_precision(cfg, n, k):
     h.set_solver(rtol=1e-13, max_it=2000)
     u = dev(x)
     steps, dt = 5, 1e-3
-    diag = host(h.substeps(u, dt, steps, prec=1, diag=True))
+    diag = host(h.substeps(u, dt, steps, prec=prec, diag=True))
     xs = O.substeps(sp, x, dt, steps, l, keep=True)
     e = rel_primal(sp, host(u), xs[-1])
-    print(f"mixed substeps cfg={cfg} k={k} rel={e:.2e} its={diag[1:, 3]}")
-    assert e <= 1e-6
+    incr = sum(rel_primal(sp, xs[i + 1], xs[i]) for i in range(steps))
+    bound = 2 * 3e-3 * incr if prec == 2 else 1e-6
+    print(f"mixed substeps prec={prec} cfg={cfg} k={k} rel={e:.2e} (bound {bound:.1e}) its={diag[1:, 3]}")
+    assert e <= bound
     assert np.all(diag[1:, 3] >= 1)
     assert np.all(diag[1:, 4] <= 1e-13)
