@@ -72,8 +72,9 @@ typedef enum {
   HOPU_BF16X2 = 2,     /* the same contractions on BF16 MFMA, each operand split
                           into hi + lo bfloat16 terms (hh + hl + lh kept, about
                           16 significant bits); FP32 accumulation inside a
-                          tile, FP64 across tiles.  Forward apply and substeps
-                          only (the adjoint returns HOPU_EUNSUPPORTED) */
+                          tile, FP64 across tiles.  Apply and substeps; the
+                          adjoint calls return HOPU_EUNSUPPORTED for the split
+                          BF16 forms */
   HOPU_BF16X3 = 3      /* hi + mid + lo split (hh, hm, mh, hl, mm, lh kept: the
                           24 bits of the FP32 value); otherwise as HOPU_BF16X2 */
 } hopu_precision;

@@ -442,7 +442,6 @@ std::vector<uint16_t> split_bf16_table(const std::vector<double>& t, int outer, 
 void make_bf16_tables(const FragTables& f, const Sizes& s, int ns, BfTables& b) {
   const FragDims d = frag_dims(s);
   const int nfc = s.dim + 1;
-  b.modal = split_bf16_table(f.modal, d.NMT, d.NK, 1, ns);
   b.vol_V = split_bf16_table(f.vol_V, d.NQVT, d.NPK, 1, ns);
   b.vol_dVT = split_bf16_table(f.vol_dVT, d.NQVT, 4, s.dim * d.NAT, ns);
   b.fac_Tr = split_bf16_table(f.fac_Tr, nfc * d.NQFT, d.NPK, 1, ns);
@@ -451,7 +450,6 @@ void make_bf16_tables(const FragTables& f, const Sizes& s, int ns, BfTables& b) 
   b.fac_Psi = split_bf16_table(f.fac_Psi, d.NQFT, d.NFK, 1, ns);
   b.fac_PsiT = split_bf16_table(f.fac_PsiT, d.NQFT, 4, d.NFJT, ns);
   b.fac_KT = split_bf16_table(f.fac_KT, nfc * d.NAT, d.NFK, 1, ns);
-  b.dual = split_bf16_table(f.dual, d.NJT * s.dim * d.NAT, 4, 1, ns);
 }
 
 void make_frag_tables(const RefTables& t, RowMap rm, FragTables& f) {

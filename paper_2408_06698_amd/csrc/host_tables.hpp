@@ -134,13 +134,14 @@ struct FragDims {
 FragDims frag_dims(const Sizes& s);
 void make_frag_tables(const RefTables& t, RowMap rm, FragTables& f);
 
-// Split-BF16 copies of the element kernels' FP32-layout tables.  A table is
+// Split-BF16 copies of the element kernel's FP32-layout tables (all but the
+// modal and dual transforms, which run in FP64).  A table is
 // viewed as [outer][nsteps][inner][64 lanes]; steps 4s .. 4s+3 of a lane
 // become one 16x16x16 BF16 fragment, stored as ns bfloat16 terms (raw bits;
 // hi, [mid,] lo by truncation of the FP32 value) laid out
 // [outer][ceil(nsteps/4)][inner][64][ns][4]; steps past nsteps are zero.
 struct BfTables {
-  std::vector<uint16_t> modal, vol_V, vol_dVT, fac_Tr, fac_TrT, fac_K, fac_Psi, fac_PsiT, fac_KT, dual;
+  std::vector<uint16_t> vol_V, vol_dVT, fac_Tr, fac_TrT, fac_K, fac_Psi, fac_PsiT, fac_KT;
 };
 std::vector<uint16_t> split_bf16_table(const std::vector<double>& t, int outer, int nsteps, int inner, int ns);
 void make_bf16_tables(const FragTables& f32, const Sizes& s, int ns, BfTables& b);

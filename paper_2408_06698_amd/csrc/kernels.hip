@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "bf16split.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
 #include "launch_events.hpp"
@@ -34,63 +35,6 @@ template <> struct MF<float> {
 
 template <typename V> __device__ __forceinline__ V vzero() { V v = {0, 0, 0, 0}; return v; }
 
-// Split-BF16 contractions on the 16x16x16 BF16 MFMA with FP32 accumulation.
-// Four consecutive K steps of the 16x16x4 FP32 form make one MFMA: register
-// j of lane group g carries step 4s + j of that group on both operands, so
-// the FP32 form's per-lane values and output layout (row 4g + i in register
-// i) carry over unchanged, and the tables are the FP32 ones regrouped.  Each
-// operand is split by truncation into NS bfloat16 terms (hi, [mid,] lo; each
-// term the leading 8 bits of what the previous ones leave), and products two
-// levels below the leading one or lower are dropped: NS = 2 keeps hh, hl,
-// lh (about 16 significant bits), NS = 3 keeps hh, hm, mh, hl, mm, lh (the
-// 24 bits of the FP32 value).
-template <int NS>
-using BfTab = BfPack<(NS > 0 ? NS : 1)>;
-template <typename T, int NS>
-using TabT = std::conditional_t<NS == 0, T, BfTab<NS>>;
-
-template <int NS>
-__device__ __forceinline__ BfTab<NS> bf_split4(float b0, float b1, float b2, float b3) {
-  BfTab<NS> p;
-  const float v[4] = {b0, b1, b2, b3};
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    float r = v[j];
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      const uint32_t h = __float_as_uint(r) & 0xFFFF0000u;
-      p.v[t][j] = (short)(h >> 16);
-      r -= __uint_as_float(h);
-    }
-  }
-  return p;
-}
-
-// steps s0 .. s0+3 of a lane's per-step values (zero past the end)
-template <int NS, int N, typename T>
-__device__ __forceinline__ BfTab<NS> bf_steps(const T (&b)[N], int s0) {
-  return bf_split4<NS>(s0 < N ? (float)b[s0] : 0.f, s0 + 1 < N ? (float)b[s0 + 1] : 0.f,
-                       s0 + 2 < N ? (float)b[s0 + 2] : 0.f, s0 + 3 < N ? (float)b[s0 + 3] : 0.f);
-}
-
-__device__ __forceinline__ f4 mfma_bf(bf16x4_t a, bf16x4_t b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-// c += a b over one group of four steps, smaller products first
-template <int NS>
-__device__ __forceinline__ f4 mma_bf(const BfTab<NS>& a, const BfTab<NS>& b, f4 c) {
-  if constexpr (NS == 2) {
-    c = mfma_bf(a.v[1], b.v[0], c);
-    c = mfma_bf(a.v[0], b.v[1], c);
-  } else {
-    c = mfma_bf(a.v[2], b.v[0], c);
-    c = mfma_bf(a.v[1], b.v[1], c);
-    c = mfma_bf(a.v[0], b.v[2], c);
-    c = mfma_bf(a.v[1], b.v[0], c);
-    c = mfma_bf(a.v[0], b.v[1], c);
-  }
-  return mfma_bf(a.v[0], b.v[0], c);
-}
 
 // Batches are assigned so that consecutive batches land on the same XCD
 // (workgroups are dealt round-robin over the 8 XCDs).
@@ -111,12 +55,16 @@ __device__ __forceinline__ void load_J(const double* g, double J[D][D]) {
 }
 
 // ------------------------------------------------------------------ modal
-// m_T = Dinv (S_T x_T): dual coefficients -> modal coefficients (rho layout).
-template <typename T, int D, int KK, int NS = 0>
-__global__ __launch_bounds__(256) void k_modal(const double* __restrict__ x, T* __restrict__ m,
-                                               DevMesh mesh, const TabT<T, NS>* __restrict__ frag) {
+// m_T = Dinv (S_T x_T): dual coefficients -> modal coefficients (rho layout),
+// stored as TS.  The contraction is FP64 in every precision form: the dual
+// basis' condition number grows quickly with k (about 4e5 at k = 5 in 3D),
+// so a reduced-precision transform would lose far more than the
+// contractions that follow it.
+template <typename TS, int D, int KK>
+__global__ __launch_bounds__(256) void k_modal(const double* __restrict__ x, TS* __restrict__ m,
+                                               DevMesh mesh, const double* __restrict__ frag) {
   using C = Cfg<D, KK>;
-  using M = MF<T>;
+  using M = MF<double>;
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t e = wave * 16 + c;
@@ -125,7 +73,7 @@ __global__ __launch_bounds__(256) void k_modal(const double* __restrict__ x, T* 
   const int64_t ee = valid ? e : 0;
   const double* G = mesh.geo + ee * GEO_STRIDE;
   const int64_t off = mesh.F * C::NF;
-  T xh[C::NK];
+  double xh[C::NK];
 #pragma unroll
   for (int kk = 0; kk < C::NK; ++kk) {
     const int j = 4 * kk + g;
@@ -139,28 +87,17 @@ __global__ __launch_bounds__(256) void k_modal(const double* __restrict__ x, T* 
         v = x[off + ee * C::NINT + (j - C::NFL)] * G[GEO_SI];
       }
     }
-    xh[kk] = (T)v;
-  }
-  constexpr int NG = (C::NK + 3) / 4;  // split-BF16 step groups
-  BfTab<NS> xs[NG];
-  if constexpr (NS > 0) {
-#pragma unroll
-    for (int sg = 0; sg < NG; ++sg) xs[sg] = bf_steps<NS>(xh, 4 * sg);
+    xh[kk] = v;
   }
 #pragma unroll
   for (int mt = 0; mt < C::NMT; ++mt) {
-    typename M::V acc = vzero<typename M::V>();
-    if constexpr (NS == 0) {
+    d4 acc = vzero<d4>();
 #pragma unroll
-      for (int kk = 0; kk < C::NK; ++kk) acc = M::mma(frag[(mt * C::NK + kk) * 64 + lane], xh[kk], acc);
-    } else {
-#pragma unroll
-      for (int sg = 0; sg < NG; ++sg) acc = mma_bf<NS>(frag[(mt * NG + sg) * 64 + lane], xs[sg], acc);
-    }
+    for (int kk = 0; kk < C::NK; ++kk) acc = M::mma(frag[(mt * C::NK + kk) * 64 + lane], xh[kk], acc);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = 16 * mt + M::row(i, g);
-      if (valid && row < C::NM) m[ee * C::NM + row] = acc[i];
+      if (valid && row < C::NM) m[ee * C::NM + row] = (TS)acc[i];
     }
   }
 }
@@ -625,29 +562,25 @@ __global__ __launch_bounds__(256) void k_elem(const T* __restrict__ m, double* _
     }
   }
 
-  // ---------------- dual transform and write-out
+  // ---------------- dual transform and write-out, in FP64 for every form
+  // (the conditioning of the dual basis; see k_modal), from the FP64 sums
+  // across tiles.  The reduced forms' table has the FP64 values with their
+  // own K order (modal row 4g + i at register i of lane group g).
   const int64_t off = mesh.F * C::NF;
+  const double* const dual = dual_f64(tb);
 #pragma unroll
   for (int jt = 0; jt < C::NJT; ++jt) {
-    V o = vzero<V>();
+    d4 o = vzero<d4>();
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-      for (int at = 0; at < C::NAT; ++at) {
-        if constexpr (NS == 0) {
+      for (int at = 0; at < C::NAT; ++at)
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            o = M::mma(tb.dual[((((jt * D + a) * C::NAT + at) * 4) + i) * 64 + lane], (T)acc.get(a, at, i), o);
-        } else {
-          o = mma_bf<NS>(tb.dual[((jt * D + a) * C::NAT + at) * 64 + lane],
-                         bf_split4<NS>((float)acc.get(a, at, 0), (float)acc.get(a, at, 1), (float)acc.get(a, at, 2),
-                                       (float)acc.get(a, at, 3)),
-                         o);
-        }
-      }
+        for (int i = 0; i < 4; ++i)
+          o = MF<double>::mma(dual[((((jt * D + a) * C::NAT + at) * 4) + i) * 64 + lane], acc.get(a, at, i), o);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int j = 16 * jt + M::row(i, g);
+      const int j = 16 * jt + MF<double>::row(i, g);
       if (valid && j < C::N) {
         if (j < C::NFL) rslot[ee * C::NFL + j] = (double)o[i] * Gr[GEO_NFN + j / C::NF];
         else r[off + ee * C::NINT + (j - C::NFL)] = (double)o[i] * Gr[GEO_SI];
@@ -1105,16 +1038,10 @@ void launch_fs_assemble(hipStream_t s, double* v, const double* fs, int64_t nfl,
 }
 
 template <typename T, int D, int KK>
-void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, const T* frag) {
+void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, const double* frag) {
   const int64_t waves = (mesh.E + 15) / 16;
   const int64_t blocks = (waves + 3) / 4;
   HOPU_LAUNCH((k_modal<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, x, m, mesh, frag);
-}
-template <int NS, int D, int KK>
-void launch_modal_bf(hipStream_t s, const double* x, float* m, const DevMesh& mesh, const BfPack<NS>* frag) {
-  const int64_t waves = (mesh.E + 15) / 16;
-  const int64_t blocks = (waves + 3) / 4;
-  HOPU_LAUNCH((k_modal<float, D, KK, NS>), dim3((unsigned)blocks), dim3(256), 0, s, x, m, mesh, frag);
 }
 
 template <typename T, int D, int KK>
@@ -1184,15 +1111,11 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
   template void launch_modal<double, D, KK>(hipStream_t, const double*, double*, const DevMesh&,            \
                                             const double*);                                                 \
   template void launch_modal<float, D, KK>(hipStream_t, const double*, float*, const DevMesh&,              \
-                                           const float*);                                                   \
+                                           const double*);                                                  \
   template void launch_elem<double, D, KK>(hipStream_t, const double*, double*, double*, const DevMesh&,    \
                                            const DevTables<double>&, int, double*, double*);                \
   template void launch_elem<float, D, KK>(hipStream_t, const float*, double*, double*, const DevMesh&,      \
                                           const DevTables<float>&, int, double*, double*);                  \
-  template void launch_modal_bf<2, D, KK>(hipStream_t, const double*, float*, const DevMesh&,               \
-                                          const BfPack<2>*);                                                \
-  template void launch_modal_bf<3, D, KK>(hipStream_t, const double*, float*, const DevMesh&,               \
-                                          const BfPack<3>*);                                                \
   template void launch_elem_bf<2, D, KK>(hipStream_t, const float*, double*, double*, const DevMesh&,       \
                                          const DevTables<BfPack<2>>&, int, double*);                        \
   template void launch_elem_bf<3, D, KK>(hipStream_t, const float*, double*, double*, const DevMesh&,       \

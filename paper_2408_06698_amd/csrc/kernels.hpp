@@ -61,10 +61,18 @@ struct DevTables {
   const T* fac_PsiT;
   const T* fac_KT;
   const T* dual;
+  const double* dual64;  // reduced forms: FP64 values of `dual` in their K order
   const double* wv;
   const double* wf;
   const int* psi_deg;
 };
+
+// The dual-transform table in FP64 (the transform runs in FP64 in every form).
+__host__ __device__ inline const double* dual_f64(const DevTables<double>& t) { return t.dual; }
+template <typename T>
+__host__ __device__ inline const double* dual_f64(const DevTables<T>& t) {
+  return t.dual64;
+}
 
 struct DevMesh {
   const double* geo;

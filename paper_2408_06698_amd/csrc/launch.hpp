@@ -4,15 +4,14 @@
 #include "kernels.hpp"
 
 namespace hopu {
+// frag: the FP64 modal table (the transform is FP64 for every storage type)
 template <typename T, int D, int KK>
-void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, const T* frag);
+void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, const double* frag);
 template <typename T, int D, int KK>
 void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMesh& mesh,
                  const DevTables<T>& tb, int terms, double* diss_part, double* eta_nd);
-// The same two kernels with split-BF16 contractions (NS = 2: hi/lo, 3:
+// The element kernel with split-BF16 contractions (NS = 2: hi/lo, 3:
 // hi/mid/lo), FP32 modal coefficients and the regrouped tables.
-template <int NS, int D, int KK>
-void launch_modal_bf(hipStream_t s, const double* x, float* m, const DevMesh& mesh, const BfPack<NS>* frag);
 template <int NS, int D, int KK>
 void launch_elem_bf(hipStream_t s, const float* m, double* r, double* slot, const DevMesh& mesh,
                     const DevTables<BfPack<NS>>& tb, int terms, double* diss_part);

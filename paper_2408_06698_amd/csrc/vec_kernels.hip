@@ -21,38 +21,32 @@ __global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// Sum of np partials by one block of 256 threads in a fixed order (thread t
-// adds part[t], part[t + 256], ..., then a fixed tree): every block that
-// calls it gets the same bits.  All threads of the block must call it.
+// Sum over a block of 256 threads of one value per thread in a fixed order:
+// a butterfly inside each wave (lane 0's result is taken), then the four
+// waves as (w0 + w1) + (w2 + w3).  Every block and every thread gets the
+// same bits.  All threads of the block must call it; sh holds 4 doubles.
+__device__ double block_sum_tree(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();  // sh may still be read from a previous call
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Sum of np partials: thread t adds part[t], part[t + 256], ... in order,
+// then block_sum_tree.
 __device__ double block_sum_fixed(const double* __restrict__ part, int np, double* sh) {
   double s = 0.0;
   for (int i = threadIdx.x; i < np; i += 256) s += part[i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  return sh[0];
-}
-
-// Sum over the block of one value per thread, the same fixed tree.
-__device__ double block_sum_tree(double v, double* sh) {
-  __syncthreads();
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  return sh[0];
+  return block_sum_tree(s, sh);
 }
 
 // Reduce partials in a fixed order and apply a PCG scalar operation.
 __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part, int np, double* sc, int* flag,
                                                 int op, double arg, double* dst) {
   if (op != OP_SET_TOL && op != OP_STORE && op != OP_STORE_HALF && flag && *flag) return;
-  __shared__ double sh[256];
+  __shared__ double sh[4];
   const double v0 = block_sum_fixed(part, np, sh);
   if (threadIdx.x != 0) return;
   const double v = v0;
@@ -131,7 +125,7 @@ __global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const d
                                                  const int* flag, const double* __restrict__ part, int np,
                                                  double* __restrict__ rr) {
   if (*flag) return;  // no launch of this kernel's iteration writes the flag
-  __shared__ double sh[256];
+  __shared__ double sh[4];
   double al;
   if (part) {
     al = sc[SC_RZ] / block_sum_fixed(part, np, sh);
@@ -172,7 +166,7 @@ __global__ __launch_bounds__(256) void k_xpay(double* __restrict__ x, double* __
                                               const double* __restrict__ z, const double* __restrict__ fs,
                                               int64_t nfl, int64_t n, double* sc, int* flag,
                                               const double* __restrict__ part, int np) {
-  __shared__ double sh[256];
+  __shared__ double sh[4];
   __shared__ int stop;
   // block 0 may raise the flag while other blocks start: each block reads it
   // once, so that the whole block takes one branch

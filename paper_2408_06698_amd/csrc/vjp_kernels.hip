@@ -361,20 +361,23 @@ __global__ __launch_bounds__(256) void k_vjp(const T* __restrict__ mu_m, const T
         for (int i = 0; i < 4; ++i) acc[a][at][i] += (double)t[a][at][i];
   }
 
+  // dual transform in FP64 for every form, from the FP64 sums: the dual
+  // basis' condition number grows quickly with k (about 4e5 at k = 5 in 3D)
   const int64_t off = mesh.F * C::NF;
+  const double* const dual = dual_f64(tb);
 #pragma unroll
   for (int jt = 0; jt < C::NJT; ++jt) {
-    V o = vz<V>();
+    d4 o = vz<d4>();
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int at = 0; at < C::NAT; ++at)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          o = M::mma(tb.dual[((((jt * D + a) * C::NAT + at) * 4) + i) * 64 + lane], (T)acc[a][at][i], o);
+          o = VM<double>::mma(dual[((((jt * D + a) * C::NAT + at) * 4) + i) * 64 + lane], acc[a][at][i], o);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int j = 16 * jt + M::row(i, g);
+      const int j = 16 * jt + VM<double>::row(i, g);
       if (valid && j < C::N) {
         if (j < C::NFL) oslot[ee * C::NFL + j] = (double)o[i] * Gr[GEO_NFN + j / C::NF];
         else out[off + ee * C::NINT + (j - C::NFL)] = (double)o[i] * Gr[GEO_SI];

@@ -142,16 +142,6 @@ def test_apply_bf16_term_subsets(terms):
         assert e <= BF16_TOL[prec], (prec, terms, e)
 
 
-def test_vjp_bf16_unsupported():
-    from paper_2408_06698_amd import HopuError
-    mesh, sp, x, c = case(2, (4, 3, 3), 3, noise=1e-3)
-    h = gpu_space(mesh, 3)
-    u = dev(x)
-    for prec in (2, 3):
-        with pytest.raises(HopuError, match="adjoint"):
-            h.vjp(u, u, prec=prec)
-
-
 @pytest.mark.parametrize("cfg,n,k", [(1, (5, 7), 3), (3, (3, 5, 3), 4), (4, (3, 3, 3), 2), (3, (3, 3, 4), 5)])
 def test_mass_apply(cfg, n, k):
     mesh, sp, x, c = case(cfg, n, k, noise=1e-3)

@@ -28,6 +28,34 @@ def test_vjp_matches_oracle(cfg, n, k):
         assert e <= 1e-12
 
 
+@pytest.mark.parametrize("cfg,n,k", [(1, (6, 5), 2), (2, (4, 3, 3), 3), (3, (3, 3, 4), 5)])
+def test_vjp_fp32_matches_oracle(cfg, n, k):
+    """FP32-MFMA adjoint against the FP64 oracle, with the FP32-MFMA bound of
+    the forward apply (the same contractions; modal and dual transforms in
+    FP64), up to k = 5 on the walled, graded, jittered mesh."""
+    mesh, sp, x, c = case(cfg, n, k, noise=1e-2)
+    mu = np.random.default_rng(11).standard_normal(sp.n_dof)
+    h = gpu_space(mesh, k)
+    h.set_upwind(k - 1)
+    g = host(h.vjp(dev(x), dev(mu), prec=1))
+    ref = O.vjp(sp, x, mu, k - 1)
+    e = rel_dual(sp, g, ref)
+    print(f"vjp fp32 cfg={cfg} k={k} rel={e:.2e}")
+    assert e <= 1e-5
+
+
+def test_vjp_bf16_unsupported():
+    from paper_2408_06698_amd import HopuError
+    mesh, sp, x, c = case(2, (4, 3, 3), 3, noise=1e-3)
+    h = gpu_space(mesh, 3)
+    u = dev(x)
+    for prec in (2, 3):
+        with pytest.raises(HopuError, match="adjoint"):
+            h.vjp(u, u, prec=prec)
+        with pytest.raises(HopuError, match="adjoint"):
+            h.substeps_vjp(u, 1e-3, 2, u, ckpt_every=1, prec=prec)
+
+
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
 def test_vjp_homogeneity_and_fd(prec, tol):
     """J_r(u) u = 2 r(u) (r is positively homogeneous of degree 2), and the
@@ -61,6 +89,12 @@ def test_chain_vjp_matches_oracle():
     ref = O.chain_vjp(sp, x, dt, n, 1, lamN)
     g = host(h.substeps_vjp(dev(x), dt, n, dev(lamN), ckpt_every=2))
     assert rel_dual(sp, g, ref) <= 1e-11
+    # FP32-MFMA reverse chain: lam_0 = lam_N + O(dt) terms, so its error
+    # relative to lam_0 is below that of one vjp
+    gp = host(h.substeps_vjp(dev(x), dt, n, dev(lamN), ckpt_every=2, prec=1))
+    e = rel_dual(sp, gp, ref)
+    print(f"chain vjp fp32 rel={e:.2e}")
+    assert e <= 1e-5
 
 
 def test_checkpointing_is_bitwise():
