@@ -204,10 +204,13 @@ hopu_status hopu_interpolate(hopu_ctx ctx, int n1d, const double* vals_facet,
 hopu_status hopu_eval(hopu_ctx ctx, const double* u, int n_pts,
                       const double* ref_pts, double* vals);
 
-/* Per-kernel timing with HIP events recorded on the context's stream around
- * each launch of the main kernels (for benchmarks and roofline reports).
- * hopu_profile_enable(ctx, 1, n) starts recording up to n launches (resets
- * earlier records); (ctx, 0, 0) stops.  hopu_profile_read returns, for one
+/* Per-kernel timing with HIP events attached to launches of the main kernels
+ * (for benchmarks and roofline reports).  hopu_profile_enable(ctx, s, n),
+ * s >= 1, starts recording every s-th launch of each kernel kind (s = 1:
+ * every launch), up to n recorded launches, and resets earlier records;
+ * (ctx, 0, 0) stops.  Events on a dispatch delay it by a few microseconds,
+ * so a stride keeps a timed run close to an uninstrumented one.  Launches
+ * that a converged PCG left queued are not counted.  hopu_profile_read returns, for one
  * kernel kind (0 element/convection kernel, 1 mass apply inside PCG,
  * 2 preconditioner inside PCG, 3 dual->modal transform, 4 transpose-Jacobian
  * kernel, 5 mass/preconditioner applies outside the PCG loop), the number of

@@ -72,12 +72,16 @@ struct hopu_ctx_s {
   int adapt_every = 0;
   double thr[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   bool prof = false;
+  int prof_stride = 1;                  // time every prof_stride-th launch of each kind
+  int64_t prof_count[8] = {};           // launches seen per kind
+  bool prof_armed = false;
   std::vector<hipEvent_t> events;       // pool, pairs
   std::vector<int> ev_kind;             // kernel id per used pair
   size_t ev_used = 0;
 };
 
 enum { PROF_ELEM = 0, PROF_MASS = 1, PROF_PREC = 2, PROF_MODAL = 3, PROF_VJP = 4, PROF_PLAIN = 5, PROF_N = 6 };
+static_assert(PROF_N <= 8, "prof_count holds 8 kinds");
 
 namespace hopu {
 static thread_local LaunchEvents tl_events;
@@ -97,13 +101,16 @@ void disarm_launch_events() { tl_armed = false; }
 // the next launch through HOPU_LAUNCH records its dispatch into a pair
 static void prof_begin(hopu_ctx ctx, int kind) {
   if (!ctx->prof || 2 * (ctx->ev_used + 1) > ctx->events.size()) return;
+  if (ctx->prof_count[kind]++ % ctx->prof_stride != 0) return;
   arm_launch_events(ctx->events[2 * ctx->ev_used], ctx->events[2 * ctx->ev_used + 1]);
   ctx->ev_kind[ctx->ev_used] = kind;
+  ctx->prof_armed = true;
 }
 static void prof_end(hopu_ctx ctx) {
-  if (!ctx->prof || 2 * (ctx->ev_used + 1) > ctx->events.size()) return;
+  if (!ctx->prof_armed) return;
   disarm_launch_events();
   ++ctx->ev_used;
+  ctx->prof_armed = false;
 }
 
 static std::string g_create_err;
@@ -551,10 +558,9 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
   if (conv && done > 0) vec_xfinal(s, x, ctx->p, n, ctx->sc);
   HCHECK(hipGetLastError());
   // launches queued after convergence returned at once: keep them out of the
-  // per-kernel timing
-  if (ctx->prof)
-    for (size_t i = (size_t)std::max(done, 0); i < prof_idx.size(); ++i)
-      for (size_t e2 = prof_idx[i]; e2 < prof_idx[i] + 2 && e2 < ctx->ev_used; ++e2) ctx->ev_kind[e2] = -1;
+  // per-kernel timing (the timed launches from iteration `done` on)
+  if (ctx->prof && (size_t)std::max(done, 0) < prof_idx.size())
+    for (size_t e2 = prof_idx[(size_t)std::max(done, 0)]; e2 < ctx->ev_used; ++e2) ctx->ev_kind[e2] = -1;
   ctx->last_its = done;
   if (iters) *iters = done;
   if (!conv) {
@@ -1092,6 +1098,7 @@ extern "C" hopu_status hopu_substeps_vjp(hopu_ctx ctx, const double* u0, double 
 // ------------------------------------------------------------------ profiling
 extern "C" hopu_status hopu_profile_enable(hopu_ctx ctx, int enable, int max_launches) {
   if (!ctx) return HOPU_EINVAL;
+  if (enable < 0) return fail(ctx, HOPU_EINVAL, "enable must be >= 0");
   if (enable && max_launches < 1) return fail(ctx, HOPU_EINVAL, "max_launches must be >= 1");
   HCHECK(hipStreamSynchronize(ctx->stream));
   if (enable) {
@@ -1105,6 +1112,9 @@ extern "C" hopu_status hopu_profile_enable(hopu_ctx ctx, int enable, int max_lau
   }
   ctx->ev_used = 0;
   ctx->prof = enable != 0;
+  ctx->prof_stride = enable > 0 ? enable : 1;
+  for (int64_t& c : ctx->prof_count) c = 0;
+  ctx->prof_armed = false;
   return HOPU_OK;
 }
 

@@ -171,7 +171,9 @@ class Hopu:
     PROF_KINDS = {"elem": 0, "mass": 1, "prec": 2, "modal": 3, "vjp": 4, "plain": 5}
 
     def profile(self, enable, max_launches=200000):
-        check(L.lib().hopu_profile_enable(self.h, 1 if enable else 0, int(max_launches)), self.h)
+        """enable: False/0 stops; True/1 times every launch of the main
+        kernels; an int s > 1 times every s-th launch of each kind."""
+        check(L.lib().hopu_profile_enable(self.h, int(enable), int(max_launches)), self.h)
 
     def profile_read(self, kind):
         n, ms = C.c_int64(), C.c_double()

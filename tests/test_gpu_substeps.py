@@ -115,3 +115,27 @@ def test_substeps_mixed_precision(cfg, n, k, prec):
     assert e <= bound
     assert np.all(diag[1:, 3] >= 1)
     assert np.all(diag[1:, 4] <= 1e-13)
+
+
+def test_profile_counts_and_stride():
+    """The library's launch timing counts one mass apply per PCG iteration
+    that ran (launches left queued after convergence are not counted), and
+    a stride times a subset of them."""
+    mesh, sp, x, c = case(2, (4, 3, 3), 3)
+    h = gpu_space(mesh, 3)
+    h.set_upwind(2)
+    h.set_solver(rtol=1e-13, max_it=2000, check_every=4)
+    steps, dt = 3, 1e-3
+    diag = host(h.substeps(dev(x), dt, steps, diag=True))
+    its = int(diag[1:, 3].sum())
+    h.profile(1)
+    h.substeps(dev(x), dt, steps)
+    n1, ms1 = h.profile_read("mass")
+    h.profile(4)
+    h.substeps(dev(x), dt, steps)
+    n4, ms4 = h.profile_read("mass")
+    h.profile(0)
+    print(f"PCG iterations {its}: timed mass launches {n1} (stride 1), {n4} (stride 4)")
+    assert n1 == its
+    assert 1 <= n4 <= its // 4 + steps
+    assert 0.5 < (ms4 / n4) / (ms1 / n1) < 2.0
