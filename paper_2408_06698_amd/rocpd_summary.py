@@ -86,10 +86,48 @@ def traffic(fetch_db, write_db, src):
         print(f"{key}_bytes_per_launch = {f * 1024 * fs + w * 1024 * ws:.0f}")
 
 
+BUSY_KERNELS = TRAFFIC_KERNELS + [("elem_bf16x2", "k_elem<float, 3, 3, 2>"), ("elem_bf16x3", "k_elem<float, 3, 3, 3>"),
+                                  ("prec_fp32", "k_mass_lds<float, 3, 3, 1>")]
+N_SIMD = 256 * 4  # MI355X: 256 CUs, 4 SIMDs each
+N_XCD = 8
+
+
+def busy(db):
+    """MFMA and VALU utilisation per kernel from one counter run.  The SQ
+    counters are summed over the chip's 1024 SIMDs; GRBM_GUI_ACTIVE reads the
+    sum over the 8 XCDs, so the dispatch's cycles are GRBM_GUI_ACTIVE / 8
+    (at 2.4 GHz that matches the launch durations).  SQ_WAVE_CYCLES and
+    SQ_ACTIVE_INST_VALU count quad-cycles, SQ_VALU_MFMA_BUSY_CYCLES cycles.
+    Per-launch medians over the launches at full size."""
+    names = ["GRBM_GUI_ACTIVE", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES",
+             "SQ_WAVE_CYCLES"]
+    vals = {n: _counter(db, n)[0] for n in names}
+    print("# cycles     = GRBM_GUI_ACTIVE / 8 XCDs")
+    print("# MFMA busy  = SQ_VALU_MFMA_BUSY_CYCLES / (cycles * 1024 SIMDs)")
+    print("# VALU busy  = 4 * SQ_ACTIVE_INST_VALU / (cycles * 1024 SIMDs)")
+    print("# waves/SIMD = 4 * SQ_WAVE_CYCLES / (cycles * 1024 SIMDs)  (mean resident waves)")
+    print("# per-launch medians over the launches at full size (GRBM_GUI_ACTIVE > 80% of the kernel's largest)")
+    print(f"{'key':<12} {'n':>4} {'cycles':>9} {'us@2.4GHz':>9} {'mfma_busy':>9} {'valu_busy':>9} {'waves/simd':>10}  kernel")
+    for key, pat in BUSY_KERNELS:
+        ks = [k for k in vals["GRBM_GUI_ACTIVE"] if pat in k]
+        if not ks:
+            continue
+        k = ks[0]
+        g = vals["GRBM_GUI_ACTIVE"][k]
+        keep = [i for i, x in enumerate(g) if x > 0.8 * max(g)]
+        med = {n: statistics.median([vals[n][k][i] for i in keep]) for n in names}
+        cyc = med["GRBM_GUI_ACTIVE"] / N_XCD
+        den = cyc * N_SIMD
+        print(f"{key:<12} {len(keep):4d} {cyc:9.0f} {cyc / 2400:9.1f} {med['SQ_VALU_MFMA_BUSY_CYCLES'] / den:9.3f} "
+              f"{4 * med['SQ_ACTIVE_INST_VALU'] / den:9.3f} {4 * med['SQ_WAVE_CYCLES'] / den:10.2f}  {k[:64]}")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 20)
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "busy":
+        busy(sys.argv[2])
     else:
         trace(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 20)
