@@ -9,7 +9,11 @@
 
 namespace hopu {
 
-static constexpr int64_t MASS_BLOCKS = 512;
+// Persistent mass kernels: one block of MASS_WPB waves per CU (two waves
+// per SIMD), so the tables are copied to LDS once per CU and every CU keeps
+// its waves for the whole launch.
+static constexpr int MASS_WPB = 8;
+static constexpr int64_t MASS_BLOCKS = 256;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -905,6 +909,25 @@ __device__ __forceinline__ double block_sum256(double v) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// the same over the NW waves of a block (64 NW lanes): per-wave sums, then
+// pairwise in a fixed order
+template <int NW>
+__device__ __forceinline__ double block_sum_waves(double v) {
+  __shared__ double red[NW];
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t[NW];
+#pragma unroll
+  for (int i = 0; i < NW; ++i) t[i] = red[i];
+#pragma unroll
+  for (int w = 1; w < NW; w *= 2)
+#pragma unroll
+    for (int i = 0; i < NW; i += 2 * w) t[i] = t[i] + t[i + w];
+  return t[0];
+}
+
 // one batch per wave
 // part (nullable): per-block partial of x . y
 template <int D, int KK, int MODE>
@@ -943,7 +966,7 @@ constexpr int mass_lds_doubles() {
 }
 
 template <typename T, int D, int KK, int MODE>
-__global__ __launch_bounds__(256, 2) void k_mass_lds(const double* __restrict__ x, double* __restrict__ out,
+__global__ __launch_bounds__(64 * MASS_WPB, 1) void k_mass_lds(const double* __restrict__ x, double* __restrict__ out,
                                                   double* __restrict__ fs, DevMesh mesh,
                                                   const T* __restrict__ fin,
                                                   const T* __restrict__ fout,
@@ -954,7 +977,7 @@ __global__ __launch_bounds__(256, 2) void k_mass_lds(const double* __restrict__ 
   if (flag && *flag) return;  // uniform over the launch
   constexpr int NIN = C::NMT * C::NK * 64;
   constexpr int NTOT = mass_lds_doubles<D, KK>();  // table entries (of type T)
-  for (int i = threadIdx.x; i < NTOT; i += 256) lds[i] = i < NIN ? fin[i] : fout[i - NIN];
+  for (int i = threadIdx.x; i < NTOT; i += 64 * MASS_WPB) lds[i] = i < NIN ? fin[i] : fout[i - NIN];
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   // Each XCD (blocks are dealt round-robin over the 8) walks a contiguous
@@ -964,8 +987,8 @@ __global__ __launch_bounds__(256, 2) void k_mass_lds(const double* __restrict__ 
   const int64_t xcd = blockIdx.x % nx;
   const int64_t nw_all = (mesh.E + 15) / 16;
   const int64_t nw = nw_all * (xcd + 1) / nx;  // end of this XCD's range
-  const int64_t stride = (int64_t)(gridDim.x / nx) * 4;
-  int64_t wave = nw_all * xcd / nx + (int64_t)(blockIdx.x / nx) * 4 + (threadIdx.x >> 6);
+  const int64_t stride = (int64_t)(gridDim.x / nx) * MASS_WPB;
+  int64_t wave = nw_all * xcd / nx + (int64_t)(blockIdx.x / nx) * MASS_WPB + (threadIdx.x >> 6);
   double dot = 0.0;
   // Two register sets alternate (no copy between them).  Every load and
   // store is issued unconditionally (prefetches past the last batch read
@@ -1003,7 +1026,7 @@ __global__ __launch_bounds__(256, 2) void k_mass_lds(const double* __restrict__ 
     }
   }
   if (part) {
-    dot = block_sum256(dot);
+    dot = block_sum_waves<MASS_WPB>(dot);
     if (threadIdx.x == 0) part[blockIdx.x] = dot;
   }
 }
@@ -1079,17 +1102,18 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
   constexpr size_t lds_bytes = (size_t)mass_lds_doubles<D, KK>() * sizeof(double);
   if (waves == 0) return 0;
   if constexpr (lds_bytes <= 64 * 1024) {
-    // two resident blocks per CU (the tables take up to 64 KB of LDS each)
-    const int64_t blocks = std::min<int64_t>((waves + 3) / 4, MASS_BLOCKS);
+    // one block of MASS_WPB waves per CU (the tables take up to 64 KB of LDS)
+    const int64_t blocks = std::min<int64_t>((waves + MASS_WPB - 1) / MASS_WPB, MASS_BLOCKS);
+    const dim3 thr(64 * MASS_WPB);
     if (mode == 0)
-      HOPU_LAUNCH((k_mass_lds<double, D, KK, 0>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, fs,
-                  mesh, fin, fout, flag, part);
+      HOPU_LAUNCH((k_mass_lds<double, D, KK, 0>), dim3((unsigned)blocks), thr, lds_bytes, s, x, out, fs, mesh, fin,
+                  fout, flag, part);
     else if (fin32 && fout32)
-      HOPU_LAUNCH((k_mass_lds<float, D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes / 2, s, x, out, fs,
-                  mesh, fin32, fout32, flag, part);
+      HOPU_LAUNCH((k_mass_lds<float, D, KK, 1>), dim3((unsigned)blocks), thr, lds_bytes / 2, s, x, out, fs, mesh,
+                  fin32, fout32, flag, part);
     else
-      HOPU_LAUNCH((k_mass_lds<double, D, KK, 1>), dim3((unsigned)blocks), dim3(256), lds_bytes, s, x, out, fs,
-                  mesh, fin, fout, flag, part);
+      HOPU_LAUNCH((k_mass_lds<double, D, KK, 1>), dim3((unsigned)blocks), thr, lds_bytes, s, x, out, fs, mesh, fin,
+                  fout, flag, part);
     return (int)blocks;
   } else {
     // (no FP32 form: its tables would not fit in LDS either)
