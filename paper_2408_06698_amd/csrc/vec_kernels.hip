@@ -257,9 +257,11 @@ void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag
   hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, s, part, np, sc, flag, op, arg, dst);
 }
 static bool al16(const void* a) { return (reinterpret_cast<uintptr_t>(a) & 15) == 0; }
+// at most 1024 blocks (four per CU): each block also reduces the scalar
+// step's partials, and on the 7.9M-DoF workload 1024 beat 512 and 2048
 static int grid_pairs(int64_t n) {
   const int64_t b = (n / 2 + 255) / 256;
-  return (int)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+  return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
 }
 
 int vec_rupdate(hipStream_t s, double* r, const double* q, const double* fs, int64_t nfl, int64_t n, double* sc,
