@@ -34,14 +34,14 @@ template <> struct VM<float> {
 template <typename V> __device__ __forceinline__ V vz() { V v = {0, 0, 0, 0}; return v; }
 
 template <typename T, int D, int KK>
-__global__ __launch_bounds__(256) void k_vjp(const T* __restrict__ mu_m, const T* __restrict__ mm_m,
+__global__ __launch_bounds__(64) void k_vjp(const T* __restrict__ mu_m, const T* __restrict__ mm_m,
                                              double* __restrict__ out, double* __restrict__ oslot, DevMesh mesh,
                                              DevTables<T> tb) {
   using C = Cfg<D, KK>;
   using M = VM<T>;
   using V = typename M::V;
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t b = blockIdx.x;  // one wave (batch) per block, as in the forward kernel
   if (b >= mesh.nb) return;
   const int32_t e = mesh.belem[b * 16 + c];
   const bool valid = e >= 0;
@@ -389,8 +389,7 @@ __global__ __launch_bounds__(256) void k_vjp(const T* __restrict__ mu_m, const T
 template <typename T, int D, int KK>
 void launch_vjp(hipStream_t s, const T* mu_u, const T* mu_mu, double* out, double* slot, const DevMesh& mesh,
                 const DevTables<T>& tb) {
-  const int64_t blocks = (mesh.nb + 3) / 4;
-  HOPU_LAUNCH((k_vjp<T, D, KK>), dim3((unsigned)blocks), dim3(256), 0, s, mu_u, mu_mu, out, slot, mesh, tb);
+  HOPU_LAUNCH((k_vjp<T, D, KK>), dim3((unsigned)mesh.nb), dim3(64), 0, s, mu_u, mu_mu, out, slot, mesh, tb);
 }
 
 #define HOPU_VJP_INST(D, KK)                                                                                  \
