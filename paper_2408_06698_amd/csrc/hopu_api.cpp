@@ -47,7 +47,13 @@ struct hopu_ctx_s {
   double* part = nullptr;   // partial sums (max(NPART, nb, waves))
   double* part2 = nullptr;  // partial sums of the vector updates (2 NPART)
   int64_t npart = 0;
-  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *rc = nullptr;
+  double *r = nullptr, *z = nullptr, *q = nullptr, *w = nullptr, *rc = nullptr;
+  // PCG search directions p_i, ring of nph vectors, with their alpha_i: the
+  // solution update x += sum alpha_i p_i is made in one pass at the end (and
+  // whenever the ring is full) instead of a read and write of x per iteration
+  double* phist = nullptr;
+  double* ahist = nullptr;
+  int nph = 0;
   // projection step (tables at create; workspace on the first hopu_project)
   const double *proj_b = nullptr, *proj_bt = nullptr, *proj_kab = nullptr;
   const int32_t* mfid = nullptr;
@@ -343,7 +349,13 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(dev_alloc(ctx, &ctx->part2, (size_t)(2 * NPART)));
     TRY(dev_alloc(ctx, &ctx->r, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->z, (size_t)n));
-    TRY(dev_alloc(ctx, &ctx->p, (size_t)n));
+    {
+      // direction history: up to 64 vectors within 8 GB, at least 4
+      const int64_t fit = (int64_t)(8.0e9 / (8.0 * (double)std::max<int64_t>(n, 1)));
+      ctx->nph = (int)std::max<int64_t>(4, std::min<int64_t>(64, fit));
+      TRY(dev_alloc(ctx, &ctx->phist, (size_t)ctx->nph * (size_t)n));
+      TRY(dev_alloc(ctx, &ctx->ahist, (size_t)ctx->nph));
+    }
     TRY(dev_alloc(ctx, &ctx->q, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->stage, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->w, (size_t)n));
@@ -526,36 +538,45 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
   // r = b - M x; z = P r (assembled straight into p); p = z
   mass_raw(ctx, 0, x, ctx->q, nullptr, false, false);
   vec_sub_fs(s, ctx->r, b, ctx->q, ctx->slot, nfl, n);
-  np = mass_raw(ctx, 1, ctx->r, ctx->p, nullptr, false, true, prec32);
-  launch_fs_assemble(s, ctx->p, ctx->slot, nfl, nullptr);
+  const int H = ctx->nph;
+  auto pdir = [&](int64_t i) { return ctx->phist + (i % H) * n; };
+  np = mass_raw(ctx, 1, ctx->r, pdir(0), nullptr, false, true, prec32);
+  launch_fs_assemble(s, pdir(0), ctx->slot, nfl, nullptr);
   vec_scalar(s, ctx->part, np, ctx->sc, fl, OP_SET_RZ, 0.0, nullptr);
   int it = 0;
+  int flushed = 0;  // x holds x_0 + sum_{i < flushed} alpha_i p_i
   bool conv = false;
   // the first chunk runs as many iterations as the previous solve needed
   // (warm-started solves converge in similar counts), then check_every.
   // q = M p and z = P r stay unassembled: their facet rows are summed from
   // the facet-side buffer by the update that reads them, and p . q, r . z
-  // come from the mass kernels' element-local partials.
+  // come from the mass kernels' element-local partials.  p_i lives in ring
+  // slot i % H; a chunk never overwrites a direction not yet added to x.
   std::vector<size_t> prof_idx;  // profile pairs of each launched iteration
   while (it < max_it) {
     const int want = (it == 0 && ctx->last_its > 1) ? ctx->last_its - 1 : ctx->check_every;
-    const int chunk = std::min(want, max_it - it);
+    const int chunk = std::min(std::min(want, max_it - it), H - 1 - (it - flushed));
     for (int c = 0; c < chunk; ++c) {
+      const int64_t i = it + c;
       prof_idx.push_back(ctx->ev_used);
-      np = mass_raw(ctx, 0, ctx->p, ctx->q, fl, true, true);
-      vec_rupdate(s, ctx->r, ctx->q, ctx->slot, nfl, n, ctx->sc, fl, ctx->part, np, nullptr);  // alpha; r -= alpha q
+      np = mass_raw(ctx, 0, pdir(i), ctx->q, fl, true, true);
+      // alpha (recorded for the solution update); r -= alpha q
+      vec_rupdate(s, ctx->r, ctx->q, ctx->slot, nfl, n, ctx->sc, fl, ctx->part, np, nullptr, ctx->ahist + i % H);
       np = mass_raw(ctx, 1, ctx->r, ctx->z, fl, true, true, prec32);
-      vec_xpay(s, x, ctx->p, ctx->z, ctx->slot, nfl, n, ctx->sc, fl, ctx->part, np);  // beta, test; x, p updates
+      // beta, test; p_{i+1} = z + beta p_i
+      vec_xpay(s, nullptr, pdir(i), pdir(i + 1), ctx->z, ctx->slot, nfl, n, ctx->sc, fl, ctx->part, np);
     }
     it += chunk;
     HCHECK(hipMemcpyAsync(ctx->hflag, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HCHECK(hipStreamSynchronize(s));
+    // every iteration counted in flag[1] has its alpha and direction (the
+    // one that converged included); those queued after it did nothing
+    const int ran = ctx->hflag[1];
+    if (ran > flushed) vec_xflush(s, x, ctx->phist, ctx->ahist, n, H, flushed, ran - flushed);
+    flushed = ran;
     if (ctx->hflag[0]) { conv = true; break; }
   }
   const int done = ctx->hflag[1];
-  // the iteration that converged skipped its k_xpay, and with it its x
-  // update (none to make up when the initial residual already met rtol)
-  if (conv && done > 0) vec_xfinal(s, x, ctx->p, n, ctx->sc);
   HCHECK(hipGetLastError());
   // launches queued after convergence returned at once: keep them out of the
   // per-kernel timing (the timed launches from iteration `done` on)
@@ -622,7 +643,7 @@ extern "C" hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* u
       // alpha; r -= alpha S_p p; partials of r.r into part2
       const int nr = vec_rupdate(s, ctx->pr, ctx->pr, ctx->pfs, nh, nh, ctx->sc, fl, ctx->part, np, ctx->part2);
       // beta, test; x += alpha p; p = r + beta p
-      vec_xpay(s, ctx->ph, ctx->pp, ctx->pr, ctx->pfs, 0, nh, ctx->sc, fl, ctx->part2, nr);
+      vec_xpay(s, ctx->ph, ctx->pp, ctx->pp, ctx->pr, ctx->pfs, 0, nh, ctx->sc, fl, ctx->part2, nr);
     }
     it += chunk;
     HCHECK(hipMemcpyAsync(ctx->hflag, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));

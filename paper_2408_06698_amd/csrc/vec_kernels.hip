@@ -117,13 +117,14 @@ template <> struct Rows<2> {
 // r -= alpha q (q unassembled).  With part: alpha = rz / (p.q), p.q the sum
 // of the np partials of the operator launch before, reduced by every block
 // in the same order (so every block holds the same alpha); block 0 records
-// alpha and the rz it divided.  With rr: each block's partial of r.r after
-// the update (the inner product of an unpreconditioned CG).
+// alpha (also in *arec if given) and the rz it divided.  With rr: each
+// block's partial of r.r after the update (the inner product of an
+// unpreconditioned CG).
 template <int W>
 __global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const double* __restrict__ q,
                                                  const double* __restrict__ fs, int64_t nfl, int64_t n, double* sc,
                                                  const int* flag, const double* __restrict__ part, int np,
-                                                 double* __restrict__ rr) {
+                                                 double* __restrict__ rr, double* __restrict__ arec) {
   if (*flag) return;  // no launch of this kernel's iteration writes the flag
   __shared__ double sh[4];
   double al;
@@ -132,6 +133,7 @@ __global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const d
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc[SC_ALPHA] = al;
       sc[SC_RZ_OLD] = sc[SC_RZ];
+      if (arec) *arec = al;
     }
   } else {
     al = sc[SC_ALPHA];
@@ -154,15 +156,16 @@ __global__ __launch_bounds__(256) void k_rupdate(double* __restrict__ r, const d
   }
 }
 
-// x += alpha p, then p = z + beta p (z unassembled): the solution update of
-// an iteration rides on the direction update that reads p anyway.  With
+// x += alpha p (x nullable), then pout = z + beta p (z unassembled; pout may
+// be p itself): the solution update of an iteration rides on the direction
+// update that reads p anyway.  With
 // part: beta = rz_new / rz_old and the convergence test from the np partials
 // of rz_new, reduced by every block in the same order; block 0 records them,
 // counts the iteration and raises the flag, and every block of the
 // iteration that converged returns without an update (the caller adds its
 // x update afterwards).
 template <int W>
-__global__ __launch_bounds__(256) void k_xpay(double* __restrict__ x, double* __restrict__ p,
+__global__ __launch_bounds__(256) void k_xpay(double* __restrict__ x, const double* p, double* pout,
                                               const double* __restrict__ z, const double* __restrict__ fs,
                                               int64_t nfl, int64_t n, double* sc, int* flag,
                                               const double* __restrict__ part, int np) {
@@ -191,17 +194,41 @@ __global__ __launch_bounds__(256) void k_xpay(double* __restrict__ x, double* __
     be = sc[SC_BETA];
   }
   for (int64_t i = W * ((int64_t)blockIdx.x * 256 + threadIdx.x); i < n; i += (int64_t)gridDim.x * 256 * W) {
-    Rows<W> pv, zv, xv;
+    Rows<W> pv, zv;
     pv.load(p, i);
     zv.load_fs(z, fs, nfl, i);
-    xv.load(x, i);
+    if (x) {
+      Rows<W> xv;
+      xv.load(x, i);
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      xv.v[w] += al * pv.v[w];
-      zv.v[w] += be * pv.v[w];
+      for (int w = 0; w < W; ++w) xv.v[w] += al * pv.v[w];
+      xv.store(x, i);
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) zv.v[w] += be * pv.v[w];
+    zv.store(pout, i);
+  }
+}
+
+// x += sum_{j < cnt} a_j p_j with p_j the ring slot (s0 + j) % H of hist
+// ([H][n]) and a_j its alpha: the PCG solution update of cnt iterations in
+// one pass, added in iteration order (the same roundings as one update per
+// iteration).
+template <int W>
+__global__ __launch_bounds__(256) void k_xflush(double* __restrict__ x, const double* __restrict__ hist,
+                                                const double* __restrict__ ahist, int64_t n, int H, int s0, int cnt) {
+  for (int64_t i = W * ((int64_t)blockIdx.x * 256 + threadIdx.x); i < n; i += (int64_t)gridDim.x * 256 * W) {
+    Rows<W> xv;
+    xv.load(x, i);
+    for (int j = 0; j < cnt; ++j) {
+      const int slot = (s0 + j) % H;
+      const double a = ahist[slot];
+      Rows<W> pv;
+      pv.load(hist + (int64_t)slot * n, i);
+#pragma unroll
+      for (int w = 0; w < W; ++w) xv.v[w] += a * pv.v[w];
     }
     xv.store(x, i);
-    zv.store(p, i);
   }
 }
 
@@ -265,22 +292,32 @@ static int grid_pairs(int64_t n) {
 }
 
 int vec_rupdate(hipStream_t s, double* r, const double* q, const double* fs, int64_t nfl, int64_t n, double* sc,
-                const int* flag, const double* part, int np, double* rr) {
+                const int* flag, const double* part, int np, double* rr, double* arec) {
   if (nfl % 2 == 0 && n % 2 == 0 && al16(r) && al16(q) && al16(fs)) {
     const int g = grid_pairs(n);
-    hipLaunchKernelGGL((k_rupdate<2>), dim3(g), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag, part, np, rr);
+    hipLaunchKernelGGL((k_rupdate<2>), dim3(g), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag, part, np, rr, arec);
     return g;
   }
   const int g = grid_for(n);
-  hipLaunchKernelGGL((k_rupdate<1>), dim3(g), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag, part, np, rr);
+  hipLaunchKernelGGL((k_rupdate<1>), dim3(g), dim3(256), 0, s, r, q, fs, nfl, n, sc, flag, part, np, rr, arec);
   return g;
 }
-void vec_xpay(hipStream_t s, double* x, double* p, const double* z, const double* fs, int64_t nfl, int64_t n,
-              double* sc, int* flag, const double* part, int np) {
-  if (nfl % 2 == 0 && n % 2 == 0 && al16(x) && al16(p) && al16(z) && al16(fs))
-    hipLaunchKernelGGL((k_xpay<2>), dim3(grid_pairs(n)), dim3(256), 0, s, x, p, z, fs, nfl, n, sc, flag, part, np);
+void vec_xpay(hipStream_t s, double* x, const double* p, double* pout, const double* z, const double* fs, int64_t nfl,
+              int64_t n, double* sc, int* flag, const double* part, int np) {
+  if (nfl % 2 == 0 && n % 2 == 0 && al16(x) && al16(p) && al16(pout) && al16(z) && al16(fs))
+    hipLaunchKernelGGL((k_xpay<2>), dim3(grid_pairs(n)), dim3(256), 0, s, x, p, pout, z, fs, nfl, n, sc, flag, part,
+                       np);
   else
-    hipLaunchKernelGGL((k_xpay<1>), dim3(grid_for(n)), dim3(256), 0, s, x, p, z, fs, nfl, n, sc, flag, part, np);
+    hipLaunchKernelGGL((k_xpay<1>), dim3(grid_for(n)), dim3(256), 0, s, x, p, pout, z, fs, nfl, n, sc, flag, part,
+                       np);
+}
+void vec_xflush(hipStream_t s, double* x, const double* hist, const double* ahist, int64_t n, int H, int s0,
+                int cnt) {
+  if (cnt <= 0) return;
+  if (n % 2 == 0 && al16(x) && al16(hist))
+    hipLaunchKernelGGL((k_xflush<2>), dim3(grid_pairs(n)), dim3(256), 0, s, x, hist, ahist, n, H, s0, cnt);
+  else
+    hipLaunchKernelGGL((k_xflush<1>), dim3(grid_for(n)), dim3(256), 0, s, x, hist, ahist, n, H, s0, cnt);
 }
 void vec_xfinal(hipStream_t s, double* x, const double* p, int64_t n, const double* sc) {
   hipLaunchKernelGGL(k_xfinal, dim3(grid_for(n)), dim3(256), 0, s, x, p, n, sc);
