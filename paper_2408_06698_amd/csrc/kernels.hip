@@ -164,15 +164,8 @@ template <int D, int NAT> struct ElemAcc<float, D, NAT> {
 // One wave (one batch) per block: the kernel holds one wave per SIMD, and a
 // block of one wave frees its SIMD as soon as it ends (with four-wave
 // blocks a SIMD waited for its block's slowest wave; FP64 1.26 -> 1.16 ms).
-// The FP32-MFMA form up to k = 3 in 3D is held to two waves per SIMD (256
-// registers; what spills costs less than the second wave gains: 0.82 ->
-// 0.77 ms on the 3D k = 3 workload); the other forms and orders lose by it.
-template <typename T, int D, int KK, int NS>
-constexpr int elem_min_waves() {
-  return sizeof(T) == 4 && NS == 0 && (D == 2 || KK <= 3) ? 2 : 1;
-}
 template <typename T, int D, int KK, int NS = 0>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(elem_min_waves<T, D, KK, NS>()))) void k_elem(const T* __restrict__ m, double* __restrict__ r,
+__global__ __launch_bounds__(64) void k_elem(const T* __restrict__ m, double* __restrict__ r,
                                               double* __restrict__ rslot, DevMesh mesh,
                                               DevTables<TabT<T, NS>> tb, int terms,
                                               double* __restrict__ diss_part, double* __restrict__ eta_nd) {
