@@ -546,15 +546,17 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
   int it = 0;
   int flushed = 0;  // x holds x_0 + sum_{i < flushed} alpha_i p_i
   bool conv = false;
-  // the first chunk runs as many iterations as the previous solve needed
-  // (warm-started solves converge in similar counts), then check_every.
+  // the first chunk runs one iteration more than the previous solve needed
+  // (warm-started solves converge in similar counts, so most solves end in
+  // it with a single host check; iterations queued past convergence return
+  // at once), then check_every.
   // q = M p and z = P r stay unassembled: their facet rows are summed from
   // the facet-side buffer by the update that reads them, and p . q, r . z
   // come from the mass kernels' element-local partials.  p_i lives in ring
   // slot i % H; a chunk never overwrites a direction not yet added to x.
   std::vector<size_t> prof_idx;  // profile pairs of each launched iteration
   while (it < max_it) {
-    const int want = (it == 0 && ctx->last_its > 1) ? ctx->last_its - 1 : ctx->check_every;
+    const int want = (it == 0 && ctx->last_its > 0) ? ctx->last_its + 1 : ctx->check_every;
     const int chunk = std::min(std::min(want, max_it - it), H - 1 - (it - flushed));
     for (int c = 0; c < chunk; ++c) {
       const int64_t i = it + c;
