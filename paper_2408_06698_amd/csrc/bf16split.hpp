@@ -1,4 +1,4 @@
-// Split-BF16 contraction helpers shared by the element and adjoint kernels.
+// Split-BF16 contraction helpers of the element kernel.
 #pragma once
 #include <hip/hip_runtime.h>
 
