@@ -229,7 +229,12 @@ void hopu_destroy(hopu_ctx ctx);
  * hopu_host_tables: reference tables for (dim, k): which = 0 volume points
  * [nqv][d], 1 volume weights, 2 V [nqv][nP] (internal modal basis), 3 facet
  * points [nqf][d-1], 4 facet weights, 5 psi [nqf][nf], 6 D [n][n],
- * 7 Dinv [n][n].  Writes at most cap doubles; returns the count or < 0.
+ * 7 Dinv [n][n]; the element kernel's fragment tables in the FP32 register
+ * layout: 8 vol_dVT [NQVT][4][d][NAT][64], 11 fac_Tr [d+1][NQFT][NPK][64],
+ * and their split-BF16 copies as raw bfloat16 bit patterns (one per
+ * double): 9 vol_dVT hi/lo, 10 vol_dVT hi/mid/lo, 12 fac_Tr hi/mid/lo, laid
+ * out [outer][ceil(steps/4)][inner][64][terms][4].  Writes at most cap
+ * doubles; returns the count or < 0.
  * hopu_host_mesh: topology/geometry of a mesh: which = 0 fid int32
  * [E][d+1], 1 nbr int32, 2 nbr_face (as int32), 3 geometry double
  * [E][32], 4 facet_elem int32 [F][2], 5 batches int32 [nb][16]. */

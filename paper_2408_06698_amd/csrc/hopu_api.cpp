@@ -972,6 +972,17 @@ extern "C" int64_t hopu_host_tables(int dim, int k, int which, double* out, int6
   std::string err;
   if (!make_ref_tables(dim, k, t, err)) return -2;
   const std::vector<double>* v = nullptr;
+  FragTables f32;
+  BfTables bf;
+  std::vector<double> bits;
+  if (which >= 8 && which <= 12) {
+    make_frag_tables(t, ROWMAP_F32, f32);
+    if (which == 9 || which == 10 || which == 12) {
+      make_bf16_tables(f32, t.sz, which == 9 ? 2 : 3, bf);
+      const std::vector<uint16_t>& b = which == 12 ? bf.fac_Tr : bf.vol_dVT;
+      bits.assign(b.begin(), b.end());
+    }
+  }
   switch (which) {
     case 0: v = &t.xv; break;
     case 1: v = &t.wv; break;
@@ -981,6 +992,11 @@ extern "C" int64_t hopu_host_tables(int dim, int k, int which, double* out, int6
     case 5: v = &t.Psi; break;
     case 6: v = &t.D; break;
     case 7: v = &t.Dinv; break;
+    case 8: v = &f32.vol_dVT; break;
+    case 11: v = &f32.fac_Tr; break;
+    case 9:
+    case 10:
+    case 12: v = &bits; break;
     default: return -1;
   }
   int64_t nwr = std::min<int64_t>(cap, (int64_t)v->size());

@@ -123,3 +123,48 @@ def test_host_mesh_errors():
     xyz = np.ascontiguousarray(np.random.default_rng(0).standard_normal((3, 3, 2)))
     assert L.lib().hopu_host_mesh(2, 3, vid.ctypes.data_as(C.c_void_p), xyz.ctypes.data_as(C.c_void_p), 0,
                                   None, 0) == -2
+
+
+def _bf16_terms_to_f32(bits):
+    """Raw bfloat16 bit patterns -> float32 values."""
+    return (np.asarray(bits, dtype=np.uint32) << 16).view(np.float32)
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (3, 3), (3, 5)])
+def test_host_bf16_split_tables(dim, k):
+    """The split-BF16 copies of the FP32-layout fragment tables: four steps of
+    a lane per fragment, terms that are successive 8-bit truncations of the
+    FP32 value (hi + mid + lo equal to it, hi + lo within 2^-15), zero past
+    the last step."""
+    nP = L.lib().hopu_host_sizes(dim, k, 3)
+    nqv = L.lib().hopu_host_sizes(dim, k, 4)
+    nqf = L.lib().hopu_host_sizes(dim, k, 5)
+    NQVT, NAT, NQFT = -(-nqv // 16), -(-nP // 16), -(-nqf // 16)
+    NPK = -(-nP // 4)
+    cases = [(8, 10, 3, NQVT, 4, dim * NAT), (8, 9, 2, NQVT, 4, dim * NAT), (11, 12, 3, (dim + 1) * NQFT, NPK, 1)]
+    for w32, wbf, ns, outer, steps, inner in cases:
+        t32 = _table(dim, k, w32).astype(np.float32).reshape(outer, steps, inner, 64)
+        ng = -(-steps // 4)
+        bits = _table(dim, k, wbf)
+        assert np.all(bits == np.round(bits)) and bits.min() >= 0 and bits.max() < 65536
+        b = bits.astype(np.uint32).reshape(outer, ng, inner, 64, ns, 4)
+        terms = _bf16_terms_to_f32(b)                      # [outer][ng][inner][64][ns][4]
+        for sg in range(ng):
+            for j in range(4):
+                st = 4 * sg + j
+                got = terms[:, sg, :, :, :, j]             # [outer][inner][64][ns]
+                if st >= steps:
+                    assert np.all(got == 0)
+                    continue
+                f = t32[:, st, :, :]
+                # each term: the FP32 remainder truncated to its leading 8 bits
+                r = f.copy()
+                for tt in range(ns):
+                    h = (r.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)
+                    assert np.array_equal(got[..., tt], h)
+                    r = (r - h).astype(np.float32)
+                tot = got.astype(np.float64).sum(axis=-1)
+                if ns == 3:
+                    assert np.array_equal(tot, f.astype(np.float64))
+                else:
+                    assert np.all(np.abs(tot - f) <= 2.0 ** -15 * np.abs(f))
