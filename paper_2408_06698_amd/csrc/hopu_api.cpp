@@ -432,12 +432,22 @@ extern "C" hopu_status hopu_set_solver(hopu_ctx ctx, double rtol, int max_it, in
 
 // ------------------------------------------------------------------ internals
 static hopu_status do_modal(hopu_ctx ctx, const double* u, hopu_precision prec, bool second = false) {
-  prof_begin(ctx, PROF_MODAL);
   double* d64 = second ? ctx->mu64 : ctx->m64;
   float* d32 = second ? ctx->mu32 : ctx->m32;
+  // the persistent mass kernel's gather reads a facet's rows in 16-byte pairs
+  if (reinterpret_cast<uintptr_t>(u) % 16 != 0) {
+    vec_copy(ctx->stream, ctx->stage, u, ctx->n_dof);
+    u = ctx->stage;
+  }
+  prof_begin(ctx, PROF_MODAL);
   DISPATCH(ctx->dim, ctx->k, {
-    if (prec == HOPU_FP64) launch_modal<double, D, KK>(ctx->stream, u, d64, ctx->dm, ctx->tb64.modal);
-    else launch_modal<float, D, KK>(ctx->stream, u, d32, ctx->dm, ctx->tb64.modal);  // FP64 transform, FP32 store
+    // FP64 transform in every form; FP32 store for the reduced ones
+    const bool f32 = prec != HOPU_FP64;
+    void* dst = f32 ? static_cast<void*>(d32) : static_cast<void*>(d64);
+    if (!launch_modal_mass<D, KK>(ctx->stream, u, dst, f32, ctx->slot, ctx->dm, ctx->mass_in)) {
+      if (f32) launch_modal<float, D, KK>(ctx->stream, u, d32, ctx->dm, ctx->tb64.modal);
+      else launch_modal<double, D, KK>(ctx->stream, u, d64, ctx->dm, ctx->tb64.modal);
+    }
   });
   prof_end(ctx);
   return HOPU_OK;

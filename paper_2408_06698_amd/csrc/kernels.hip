@@ -763,8 +763,8 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
   const bool valid = live && e < mesh.E;  // (a batch that is not live writes nothing)
   // facet rows scaled by |N_F| (mode 1: 1/2 |N_F|^-1, the facet split
   // included), interior rows by the interior scale (its inverse)
-  const double sfac = MODE == 0 ? md.nf : 0.5 / md.nf;
-  const double sint = MODE == 0 ? md.si : 1.0 / md.si;
+  const double sfac = MODE == 1 ? 0.5 / md.nf : md.nf;
+  const double sint = MODE == 1 ? 1.0 / md.si : md.si;
   // the lane's facet exists (an interior facet of a real element)
   const bool fok = valid && g <= D && md.ix.fid >= 0;
   T xh[C::NK];
@@ -802,6 +802,25 @@ __device__ __forceinline__ double mass_compute(const MassData<D, KK>& md,
     for (int mt = 0; mt < C::NMT; ++mt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) y[mt][i] = (double)acc[mt][i];
+  }
+  if constexpr (MODE >= 2) {
+    // the modal coefficients m = Dinv S x themselves (rho layout; register
+    // i of lane group g holds row 16 mt + 4 i + g), stored as double (2) or
+    // float (3); a fixed number of stores, the unused ones to trash slots
+#pragma unroll
+    for (int mt = 0; mt < C::NMT; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * mt + M::row(i, g);
+        const bool ok = valid && row < C::NM;
+        double* const t = trash + 2 + 2 * (4 * mt + i);
+        if constexpr (MODE == 2)
+          *(ok ? out + (valid ? e : 0) * C::NM + row : t) = y[mt][i];
+        else
+          *(ok ? reinterpret_cast<float*>(out) + (valid ? e : 0) * C::NM + row : reinterpret_cast<float*>(t)) =
+              (float)y[mt][i];
+      }
+    return 0.0;
   }
   // component mixing: quads rq = blk*D + a hold components a of one alpha block
   double Gm[D][D];
@@ -977,7 +996,8 @@ __global__ __launch_bounds__(64 * MASS_WPB, 1) void k_mass_lds(const double* __r
   T* const lds = reinterpret_cast<T*>(lds_raw);
   if (flag && *flag) return;  // uniform over the launch
   constexpr int NIN = C::NMT * C::NK * 64;
-  constexpr int NTOT = mass_lds_doubles<D, KK>();  // table entries (of type T)
+  // table entries (of type T); the modal modes use the first table only
+  constexpr int NTOT = MODE >= 2 ? NIN : mass_lds_doubles<D, KK>();
   for (int i = threadIdx.x; i < NTOT; i += 64 * MASS_WPB) lds[i] = i < NIN ? fin[i] : fout[i - NIN];
   __syncthreads();
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
@@ -1008,7 +1028,7 @@ __global__ __launch_bounds__(64 * MASS_WPB, 1) void k_mass_lds(const double* __r
     mass_load_data<D, KK>(x, mesh, wave, g, c, ib, da);
     mass_load_idx<D>(mesh, wave + stride, g, c, ib);
     asm volatile("" ::: "memory");  // the dummy stores follow the loads
-    mass_dummy_stores<C::NK>(trash);
+    mass_dummy_stores<(MODE >= 2 ? 4 * C::NMT : C::NK)>(trash);
     while (true) {
       mass_load_data<D, KK>(x, mesh, wave + stride, g, c, ib, db);
       mass_load_idx<D>(mesh, wave + 2 * stride, g, c, ib);
@@ -1128,6 +1148,33 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
   }
 }
 
+// m = Dinv S x through the persistent mass kernel (its gather, row order
+// and first contraction; modes 2/3 store m as double/float).  false: this
+// order's table does not fit in LDS (the caller uses k_modal).
+template <int D, int KK>
+bool launch_modal_mass(hipStream_t s, const double* x, void* m, bool f32, double* fs, const DevMesh& mesh,
+                       const double* fin) {
+  using C = Cfg<D, KK>;
+  constexpr size_t lds_bytes = (size_t)C::NMT * C::NK * 64 * sizeof(double);
+  if constexpr (lds_bytes <= 64 * 1024 && 2 + 8 * C::NMT <= MASS_TRASH_DOUBLES) {
+    const int64_t waves = (mesh.E + 15) / 16;
+    if (waves == 0) return true;
+    const int64_t blocks = std::min<int64_t>((waves + MASS_WPB - 1) / MASS_WPB, MASS_BLOCKS);
+    const dim3 thr(64 * MASS_WPB);
+    double* out = static_cast<double*>(m);
+    if (f32)
+      HOPU_LAUNCH((k_mass_lds<double, D, KK, 3>), dim3((unsigned)blocks), thr, lds_bytes, s, x, out, fs, mesh, fin,
+                  fin, nullptr, nullptr);
+    else
+      HOPU_LAUNCH((k_mass_lds<double, D, KK, 2>), dim3((unsigned)blocks), thr, lds_bytes, s, x, out, fs, mesh, fin,
+                  fin, nullptr, nullptr);
+    return true;
+  } else {
+    (void)s; (void)x; (void)m; (void)f32; (void)fs; (void)mesh; (void)fin;
+    return false;
+  }
+}
+
 #define HOPU_INST(D, KK)                                                                                     \
   template void launch_modal<double, D, KK>(hipStream_t, const double*, double*, const DevMesh&,            \
                                             const double*);                                                 \
@@ -1144,7 +1191,9 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
   template int launch_mass<D, KK>(hipStream_t, int, const double*, double*, double*, const DevMesh&,        \
                                   const double*, const double*, const int*, double*, const float*,          \
                                   const float*);                                                            \
-  template void launch_assemble<D, KK>(hipStream_t, double*, const double*, const DevMesh&, const int*);
+  template void launch_assemble<D, KK>(hipStream_t, double*, const double*, const DevMesh&, const int*);        \
+  template bool launch_modal_mass<D, KK>(hipStream_t, const double*, void*, bool, double*, const DevMesh&,   \
+                                         const double*);
 
 HOPU_INST(2, 1)
 HOPU_INST(2, 2)

@@ -10,6 +10,14 @@ void launch_modal(hipStream_t s, const double* x, T* m, const DevMesh& mesh, con
 template <typename T, int D, int KK>
 void launch_elem(hipStream_t s, const T* m, double* r, double* slot, const DevMesh& mesh,
                  const DevTables<T>& tb, int terms, double* diss_part, double* eta_nd);
+// m = Dinv S x (rho layout) by the persistent mass kernel's gather and first
+// contraction, stored as double or float (f32); mass_in table; fs: the
+// facet-side buffer (only its trash slots are written).  Returns false for
+// orders whose table does not fit in LDS (then launch_modal does it).  x
+// must be 16-byte aligned.
+template <int D, int KK>
+bool launch_modal_mass(hipStream_t s, const double* x, void* m, bool f32, double* fs, const DevMesh& mesh,
+                       const double* fin);
 // The element kernel with split-BF16 contractions (NS = 2: hi/lo, 3:
 // hi/mid/lo), FP32 modal coefficients and the regrouped tables.
 template <int NS, int D, int KK>

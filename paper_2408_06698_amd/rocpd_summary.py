@@ -17,7 +17,7 @@ TRAFFIC_KERNELS = [
     ("prec", "k_mass_lds<double, 3, 3, 1>"),
     ("elem", "k_elem<double, 3, 3, 0>"),
     ("elem_fp32", "k_elem<float, 3, 3, 0>"),
-    ("modal", "k_modal<double, 3, 3, 0>"),
+    ("modal", "k_mass_lds<double, 3, 3, 2>"),
     ("rupdate", "k_rupdate<2>("),
     ("xpay", "k_xpay<2>("),
     ("proj", "k_proj<3, 3, 0>"),

@@ -84,9 +84,10 @@ def test_diagnostics_and_energy_identity():
     assert dv <= 1e-12 * np.sqrt(2 * E)
     Dref = O.dissipation(sp, x, 1)
     assert abs(D - Dref) <= 1e-12 * Dref
-    # divergence-free input: u.r(u) = D
+    # divergence-free input: u.r(u) = D, up to the rounding of r and of the
+    # inner product, whose terms sum to |u|.|r| = 2.3 here while D = 9.7e-6
     r = host(h.apply(dev(x)))
-    assert abs(x @ r - D) <= 1e-11 * D
+    assert abs(x @ r - D) <= 1e-13 * np.sum(np.abs(x * r))
 
 
 @pytest.mark.parametrize("cfg,n,k,prec", [(1, (16, 16), 2, 1), (2, (4, 3, 3), 3, 1), (1, (16, 16), 2, 2),
