@@ -351,8 +351,11 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(dev_alloc(ctx, &ctx->z, (size_t)n));
     {
       // direction history: up to 64 vectors within 8 GB, at least 4
+      // (HOPU_TEST_RING=h sets h, for tests of the ring's wrap-around)
       const int64_t fit = (int64_t)(8.0e9 / (8.0 * (double)std::max<int64_t>(n, 1)));
       ctx->nph = (int)std::max<int64_t>(4, std::min<int64_t>(64, fit));
+      const char* ring = std::getenv("HOPU_TEST_RING");
+      if (ring && std::atoi(ring) >= 2 && std::atoi(ring) <= 64) ctx->nph = std::atoi(ring);
       TRY(dev_alloc(ctx, &ctx->phist, (size_t)ctx->nph * (size_t)n));
       TRY(dev_alloc(ctx, &ctx->ahist, (size_t)ctx->nph));
     }

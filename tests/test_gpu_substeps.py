@@ -140,3 +140,34 @@ def test_profile_counts_and_stride():
     assert n1 == its
     assert 1 <= n4 <= its // 4 + steps
     assert 0.5 < (ms4 / n4) / (ms1 / n1) < 2.0
+
+
+def test_pcg_direction_ring_wraps(monkeypatch):
+    """The PCG keeps its search directions in a ring and adds them to the
+    solution at each host check; with a ring of 2 or 3 (as on the largest
+    workloads, where the ring holds only a few vectors) the chunks stop at
+    the ring's capacity and the solve is bitwise the one with the full ring
+    (the same updates in the same order)."""
+    mesh, sp, x, c = case(2, (4, 3, 3), 3)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(sp.n_dof)
+    ref = None
+    for ring in (None, 3, 2):
+        if ring is None:
+            monkeypatch.delenv("HOPU_TEST_RING", raising=False)
+        else:
+            monkeypatch.setenv("HOPU_TEST_RING", str(ring))
+        h = gpu_space(mesh, 3)
+        h.set_solver(rtol=1e-13, max_it=2000, check_every=5)
+        w, its = h.mass_solve(dev(b), rtol=1e-13)
+        w = host(w)
+        h.close()
+        if ref is None:
+            ref, its_ref = w, its
+            assert its > 6
+        else:
+            assert its == its_ref
+            assert np.array_equal(w, ref), ring
+    monkeypatch.delenv("HOPU_TEST_RING", raising=False)
+    # and against the oracle's mass matrix
+    assert rel_dual(sp, O.mass_apply(sp, ref), b) <= 1e-12
