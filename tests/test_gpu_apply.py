@@ -188,3 +188,31 @@ def test_interpolate_and_eval(cfg, n, k):
     v = host(h.eval(dev(x_ref), pts))
     vr = sp.evaluate(x_ref, np.arange(sp.topo.n_elems), pts)
     assert np.abs(v - vr).max() <= 1e-13 * np.abs(vr).max()
+
+
+def test_argument_errors_and_no_op_calls():
+    """Calls through the C ABI reject bad arguments with HOPU_EINVAL and a
+    message, and change nothing; zero substeps leave u as it was."""
+    import ctypes as C
+    from paper_2408_06698_amd import _lib as L, HopuError
+    mesh, sp, x, c = case(2, (4, 3, 3), 3, noise=1e-3)
+    h = gpu_space(mesh, 3)
+    u = dev(x)
+    r = h.zeros()
+    lib = L.lib()
+    p = lambda t: C.c_void_p(t.data_ptr())
+    for prec in (-1, 4):
+        assert lib.hopu_convection_apply(h.h, p(u), p(r), 7, prec) == L.HOPU_EINVAL
+        assert "precision" in lib.hopu_last_error(h.h).decode()
+    assert lib.hopu_convection_apply(h.h, p(u), p(r), 8, 0) == L.HOPU_EINVAL
+    assert lib.hopu_convection_apply(h.h, None, p(r), 7, 0) == L.HOPU_EINVAL
+    assert lib.hopu_substeps(h.h, p(u), C.c_double(1e-3), -1, 0, None) == L.HOPU_EINVAL
+    assert lib.hopu_substeps(h.h, p(u), C.c_double(float("nan")), 1, 0, None) == L.HOPU_EINVAL
+    assert lib.hopu_mass_apply(h.h, p(u), None) == L.HOPU_EINVAL
+    torch.cuda.synchronize()
+    assert np.array_equal(host(u), x)
+    assert not np.any(host(r))
+    h.substeps(u, 1e-3, 0)
+    assert np.array_equal(host(u), x)
+    with pytest.raises(HopuError):
+        h.apply(u, prec=5)
