@@ -152,9 +152,10 @@ hopu_status hopu_mass_solve(hopu_ctx ctx, const double* r, double* w,
  * u~ is recovered element by element.  u_new is divergence-free and lies in
  * V_h.  ustar, unew: dev [n_dof], distinct (else HOPU_EINVAL).  rtol > 0,
  * max_it >= 1; *iters (host, nullable) receives the CG iteration count.
- * The first call allocates the step's workspace (E dim P^{k-1}^2 + 5 (F + W)
- * n_f doubles) and computes the element matrices A^-1; later calls allocate
- * nothing.  Syncs.  HOPU_ENOCONV if max_it is reached (unew is still
+ * The first call allocates the step's workspace (E dim P^{k-1}^2 + (4 + H)
+ * (F + W) n_f doubles; H, the CG's search-direction ring, is
+ * min(17, 8 GB / (8 (F + W) n_f)) and at least 4) and computes the element
+ * matrices A^-1; later calls allocate nothing.  Syncs.  HOPU_ENOCONV if max_it is reached (unew is still
  * written from the last iterate). */
 hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* unew,
                          double rtol, int max_it, int* iters);

@@ -57,7 +57,9 @@ struct hopu_ctx_s {
   // projection step (tables at create; workspace on the first hopu_project)
   const double *proj_b = nullptr, *proj_bt = nullptr, *proj_kab = nullptr;
   const int32_t* mfid = nullptr;
-  double *ainv = nullptr, *ph = nullptr, *pr = nullptr, *pp = nullptr, *pfs = nullptr;
+  double *ainv = nullptr, *ph = nullptr, *pr = nullptr, *pfs = nullptr;
+  double *pph = nullptr, *paht = nullptr;  // its CG's direction ring and alphas (as in the PCG)
+  int npph = 0;
   bool proj_ready = false;
   double* stage = nullptr;  // 16-byte aligned copy of a mass-kernel input that is not
   double* wh[3] = {nullptr, nullptr, nullptr};  // previous substep solutions (newest first)
@@ -622,9 +624,15 @@ extern "C" hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* u
   ProjDev pj{ctx->mfid, FW, ctx->mass_in, ctx->prec_in, ctx->prec_out, ctx->proj_b, ctx->proj_bt, nullptr};
   if (!ctx->proj_ready) {
     hopu_status st;
+    // direction ring: one chunk of 16 iterations and the next direction,
+    // within 8 GB (at least 4)
+    const int64_t fit = (int64_t)(8.0e9 / (8.0 * (double)std::max<int64_t>(nh, 1)));
+    ctx->npph = (int)std::max<int64_t>(4, std::min<int64_t>(17, fit));
     if ((st = dev_alloc(ctx, &ctx->ainv, (size_t)ctx->mesh.E * nQ * nQ)) ||
         (st = dev_alloc(ctx, &ctx->ph, (size_t)nh)) || (st = dev_alloc(ctx, &ctx->pr, (size_t)nh)) ||
-        (st = dev_alloc(ctx, &ctx->pp, (size_t)nh)) || (st = dev_alloc(ctx, &ctx->pfs, (size_t)2 * nh)))
+        (st = dev_alloc(ctx, &ctx->pfs, (size_t)2 * nh)) ||
+        (st = dev_alloc(ctx, &ctx->pph, (size_t)ctx->npph * (size_t)nh)) ||
+        (st = dev_alloc(ctx, &ctx->paht, (size_t)ctx->npph)))
       return st;
     // wall facets have one side: their second contribution stays zero
     HCHECK(hipMemsetAsync(ctx->pfs, 0, (size_t)2 * nh * sizeof(double), s));
@@ -639,7 +647,9 @@ extern "C" hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* u
   // r = g, p = r
   DISPATCH(ctx->dim, ctx->k, { launch_proj<D, KK>(s, 1, nullptr, ustar, ctx->pfs, ctx->dm, pj, nullptr); });
   launch_fs_assemble(s, ctx->pr, ctx->pfs, nh, nullptr);
-  vec_copy(s, ctx->pp, ctx->pr, nh);
+  const int H = ctx->npph;
+  auto pdir = [&](int64_t i) { return ctx->pph + (i % H) * nh; };
+  vec_copy(s, pdir(0), ctx->pr, nh);
   // ||r|| <= rtol (||g||^2 + ||u*_F||^2)^1/2: the facet block of u* (same
   // units as g) keeps the criterion meaningful when u* is (nearly)
   // divergence-free and g is rounding noise
@@ -649,24 +659,32 @@ extern "C" hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* u
   vec_dot(s, ctx->pr, ctx->pr, nh, ctx->part, nullptr);
   vec_scalar(s, ctx->part, NPART, ctx->sc, fl, OP_SET_RZ, 0.0, nullptr);
   int it = 0;
+  int flushed = 0;  // ph holds sum_{i < flushed} alpha_i p_i
   bool conv = false;
+  // the solution update is made from the ring at each host check, as in
+  // the PCG (one pass over the directions instead of an x read and write
+  // per iteration)
   while (it < max_it) {
-    const int chunk = std::min(16, max_it - it);
+    const int chunk = std::min(std::min(16, max_it - it), H - 1 - (it - flushed));
     for (int c = 0; c < chunk; ++c) {
+      const int64_t i = it + c;
       int np = 0;
-      DISPATCH(ctx->dim, ctx->k, { np = launch_proj<D, KK>(s, 0, ctx->pp, nullptr, ctx->pfs, ctx->dm, pj, ctx->part, fl); });
-      // alpha; r -= alpha S_p p; partials of r.r into part2
-      const int nr = vec_rupdate(s, ctx->pr, ctx->pr, ctx->pfs, nh, nh, ctx->sc, fl, ctx->part, np, ctx->part2);
-      // beta, test; x += alpha p; p = r + beta p
-      vec_xpay(s, ctx->ph, ctx->pp, ctx->pp, ctx->pr, ctx->pfs, 0, nh, ctx->sc, fl, ctx->part2, nr);
+      DISPATCH(ctx->dim, ctx->k, { np = launch_proj<D, KK>(s, 0, pdir(i), nullptr, ctx->pfs, ctx->dm, pj, ctx->part, fl); });
+      // alpha (recorded); r -= alpha S_p p; partials of r.r into part2
+      const int nr = vec_rupdate(s, ctx->pr, ctx->pr, ctx->pfs, nh, nh, ctx->sc, fl, ctx->part, np, ctx->part2,
+                                 ctx->paht + i % H);
+      // beta, test; p_{i+1} = r + beta p_i
+      vec_xpay(s, nullptr, pdir(i), pdir(i + 1), ctx->pr, ctx->pfs, 0, nh, ctx->sc, fl, ctx->part2, nr);
     }
     it += chunk;
     HCHECK(hipMemcpyAsync(ctx->hflag, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HCHECK(hipStreamSynchronize(s));
+    const int ran = ctx->hflag[1];
+    if (ran > flushed) vec_xflush(s, ctx->ph, ctx->pph, ctx->paht, nh, H, flushed, ran - flushed);
+    flushed = ran;
     if (ctx->hflag[0]) { conv = true; break; }
   }
   const int done = ctx->hflag[1];
-  if (conv && done > 0) vec_xfinal(s, ctx->ph, ctx->pp, nh, ctx->sc);
   // u_new = u* - u~
   DISPATCH(ctx->dim, ctx->k, { launch_proj<D, KK>(s, 2, ctx->ph, ustar, unew, ctx->dm, pj, nullptr); });
   HCHECK(hipGetLastError());

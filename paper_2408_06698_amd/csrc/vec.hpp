@@ -11,24 +11,23 @@ void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag
                 double* dst);
 // q, z, and q in vec_sub_fs are unassembled: facet rows [0, nfl) come from the
 // facet-side buffer fs ([2][nfl]), interior rows from the vector itself.
-// PCG updates: r -= alpha q; then x += alpha p, p = z + beta p; and, after
-// convergence, the last x += alpha p.  The scalar steps ride on the updates:
-// vec_rupdate takes alpha = rz / (p.q) from the np partials of p.q (part,
-// from the operator launch before it), records it in *arec if given and,
-// if rr is given, leaves one partial of r.r per block there (returns the
-// block count); vec_xpay takes beta and the convergence test from the np
-// partials of the new rz, counts the iteration in flag[1] and raises
-// flag[0] on convergence; it writes z + beta p to pout (may be p) and, if
-// x is given, adds alpha p to it.  part == nullptr: alpha / beta are read
-// from sc as they are.  vec_xflush adds cnt recorded directions to x in
-// order: x += sum_j ahist[(s0+j)%H] hist[(s0+j)%H][.] (hist [H][n]).
+// PCG updates: r -= alpha q; then x += alpha p, p = z + beta p.  The
+// scalar steps ride on the updates: vec_rupdate takes alpha = rz / (p.q)
+// from the np partials of p.q (part, from the operator launch before it),
+// records it in *arec if given and, if rr is given, leaves one partial of
+// r.r per block there (returns the block count); vec_xpay takes beta and
+// the convergence test from the np partials of the new rz, counts the
+// iteration in flag[1] and raises flag[0] on convergence; it writes
+// z + beta p to pout (may be p) and, if x is given, adds alpha p to it.
+// part == nullptr: alpha / beta are read from sc as they are.  vec_xflush
+// adds cnt recorded directions to x in order:
+// x += sum_j ahist[(s0+j)%H] hist[(s0+j)%H][.] (hist [H][n]).
 int vec_rupdate(hipStream_t s, double* r, const double* q, const double* fs, int64_t nfl, int64_t n, double* sc,
                 const int* flag, const double* part, int np, double* rr, double* arec = nullptr);
 void vec_xpay(hipStream_t s, double* x, const double* p, double* pout, const double* z, const double* fs, int64_t nfl,
               int64_t n, double* sc, int* flag, const double* part, int np);
 void vec_xflush(hipStream_t s, double* x, const double* hist, const double* ahist, int64_t n, int H, int s0,
                 int cnt);
-void vec_xfinal(hipStream_t s, double* x, const double* p, int64_t n, const double* sc);
 void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, const double* fs, int64_t nfl,
                 int64_t n);
 void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n);

@@ -232,13 +232,6 @@ __global__ __launch_bounds__(256) void k_xflush(double* __restrict__ x, const do
   }
 }
 
-// x += alpha p (the update of the iteration that converged, whose k_xpay was
-// skipped)
-__global__ void k_xfinal(double* __restrict__ x, const double* __restrict__ p, int64_t n, const double* sc) {
-  const double al = sc[SC_ALPHA];
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) x[i] += al * p[i];
-}
-
 // r = b - q (q unassembled)
 __global__ void k_sub_fs(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ q,
                          const double* __restrict__ fs, int64_t nfl, int64_t n) {
@@ -318,9 +311,6 @@ void vec_xflush(hipStream_t s, double* x, const double* hist, const double* ahis
     hipLaunchKernelGGL((k_xflush<2>), dim3(grid_pairs(n)), dim3(256), 0, s, x, hist, ahist, n, H, s0, cnt);
   else
     hipLaunchKernelGGL((k_xflush<1>), dim3(grid_for(n)), dim3(256), 0, s, x, hist, ahist, n, H, s0, cnt);
-}
-void vec_xfinal(hipStream_t s, double* x, const double* p, int64_t n, const double* sc) {
-  hipLaunchKernelGGL(k_xfinal, dim3(grid_for(n)), dim3(256), 0, s, x, p, n, sc);
 }
 void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, const double* fs, int64_t nfl,
                 int64_t n) {
