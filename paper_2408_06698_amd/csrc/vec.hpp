@@ -5,7 +5,7 @@
 namespace hopu {
 enum { NPART = 1024 };
 enum { SC_RZ = 0, SC_ALPHA = 1, SC_BETA = 2, SC_TOL2 = 3, SC_BPB = 4, SC_RES = 5, SC_RZ_OLD = 6, SC_N = 8 };
-enum { OP_SET_TOL = 0, OP_SET_RZ = 1, OP_STORE = 4, OP_STORE_HALF = 5 };
+enum { OP_SET_TOL = 0, OP_SET_RZ = 1, OP_STORE = 4 };
 void vec_dot(hipStream_t s, const double* a, const double* b, int64_t n, double* part, const int* flag);
 void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag, int op, double arg,
                 double* dst);
@@ -30,7 +30,6 @@ void vec_xflush(hipStream_t s, double* x, const double* hist, const double* ahis
                 int cnt);
 void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, const double* fs, int64_t nfl,
                 int64_t n);
-void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n);
 void vec_copy(hipStream_t s, double* y, const double* x, int64_t n);
 void vec_axpy(hipStream_t s, double* y, const double* x, double a, int64_t n);
 void vec_comb3(hipStream_t s, double* w, const double* h1, const double* h2, double a, double b, double c,

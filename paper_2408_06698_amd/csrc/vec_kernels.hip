@@ -45,7 +45,7 @@ __device__ double block_sum_fixed(const double* __restrict__ part, int np, doubl
 // Reduce partials in a fixed order and apply a PCG scalar operation.
 __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part, int np, double* sc, int* flag,
                                                 int op, double arg, double* dst) {
-  if (op != OP_SET_TOL && op != OP_STORE && op != OP_STORE_HALF && flag && *flag) return;
+  if (op != OP_SET_TOL && op != OP_STORE && flag && *flag) return;
   __shared__ double sh[4];
   const double v0 = block_sum_fixed(part, np, sh);
   if (threadIdx.x != 0) return;
@@ -64,9 +64,6 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part,
       break;
     case OP_STORE:
       *dst = v;
-      break;
-    case OP_STORE_HALF:
-      *dst = 0.5 * v;
       break;
     default:
       break;
@@ -239,11 +236,6 @@ __global__ void k_sub_fs(double* __restrict__ r, const double* __restrict__ b, c
     r[i] = b[i] - fs_row(q, fs, nfl, i);
 }
 
-__global__ void k_sub(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ q,
-                      int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) r[i] = b[i] - q[i];
-}
-
 __global__ void k_copy(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = x[i];
 }
@@ -315,9 +307,6 @@ void vec_xflush(hipStream_t s, double* x, const double* hist, const double* ahis
 void vec_sub_fs(hipStream_t s, double* r, const double* b, const double* q, const double* fs, int64_t nfl,
                 int64_t n) {
   hipLaunchKernelGGL(k_sub_fs, dim3(grid_for(n)), dim3(256), 0, s, r, b, q, fs, nfl, n);
-}
-void vec_sub(hipStream_t s, double* r, const double* b, const double* q, int64_t n) {
-  hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, s, r, b, q, n);
 }
 void vec_copy(hipStream_t s, double* y, const double* x, int64_t n) {
   hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, s, y, x, n);
