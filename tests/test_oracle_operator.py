@@ -3,6 +3,8 @@ adjoints against identities implied by the paper's definitions (HOPU form,
 eq. (hopudefinition); standard upwind, eq. (upwind); explicit substep of
 eq. (MCS_step1); mass matrix M_uu = M / dt)."""
 import math
+import os
+
 import numpy as np
 import pytest
 from scipy.linalg import null_space
@@ -277,9 +279,19 @@ def test_jump_indicator_properties(periodic2d):
 
 
 def test_adapt_order_intervals():
-    """The threshold rule of section 3.2 with the k = 3 thresholds
-    {0.1, 0.2, 0.3, 0.4}: eta_i < eta <= eta_{i+1} -> i, below eta_0 -> -1."""
-    th = [0.1, 0.2, 0.3, 0.4]
-    eta = np.array([0.0, 0.05, 0.1, 0.1000001, 0.2, 0.25, 0.3, 0.35, 0.4, 0.7, 1.0, 1.5, np.inf])
-    want = np.array([-1, -1, -1, 0, 0, 1, 1, 2, 2, 3, 3, 3, 3])
-    assert np.array_equal(O.adapt_order(eta, th, 3), want)
+    """The threshold rule of section 3.2 with the k = 3 thresholds of
+    section 4 {0.1, 0.2, 0.3, 0.4}: eta_i < eta <= eta_{i+1} -> i, below
+    eta_0 -> -1 (the hand-worked cases in tests/golden/adaptive_order_k3.txt)."""
+    th, eta, want = None, [], []
+    path = os.path.join(os.path.dirname(__file__), "golden", "adaptive_order_k3.txt")
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "thresholds":
+            th = [float(v) for v in f[1:]]
+        else:
+            eta.append(float(f[0]))
+            want.append(int(f[1]))
+    assert th == [0.1, 0.2, 0.3, 0.4] and len(eta) >= 10
+    assert np.array_equal(O.adapt_order(np.array(eta), th, 3), np.array(want))
