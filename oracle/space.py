@@ -86,7 +86,7 @@ class Space:
         J = t.J[elems]
         Ji = self.Jinv[elems]
         fac = self.S[elems] / t.detJ[elems][:, None]
-        g = np.einsum("bac,qicd,bde->bqiae", J, ref_grads, Ji)
+        g = J[:, None, None] @ ref_grads[None] @ Ji[:, None, None]
         return g * fac[:, None, :, None, None]
 
     def batches(self, n, size):
