@@ -88,7 +88,9 @@ enum { HOPU_TERM_VOLUME = 1, HOPU_TERM_CENTRAL = 2, HOPU_TERM_UPWIND = 4, HOPU_T
  * Host work: topology, geometry, tables; then device allocation and copies.
  * Device memory: about 15 vectors of n_dof doubles, the element workspaces
  * and the PCG search-direction ring (min(64, 8 GB / (8 n_dof)) vectors, at
- * least 4).  Syncs. */
+ * least 4; the environment variable HOPU_TEST_RING = h, 2 <= h <= 64, read
+ * here, sets h vectors instead, for tests of the ring's wrap-around).
+ * Syncs. */
 hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elems,
                         const int64_t* elem_vid, const double* elem_xyz,
                         void* hip_stream);
