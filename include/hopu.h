@@ -242,7 +242,13 @@ void hopu_destroy(hopu_ctx ctx);
  * doubles; returns the count or < 0.
  * hopu_host_mesh: topology/geometry of a mesh: which = 0 fid int32
  * [E][d+1], 1 nbr int32, 2 nbr_face (as int32), 3 geometry double
- * [E][32], 4 facet_elem int32 [F][2], 5 batches int32 [nb][16]. */
+ * [E][32], 4 facet_elem int32 [F][2] (free facets only; a wall side has
+ * nbr -1), 5 batches int32 [nb][16].  Writes at most cap entries; returns
+ * the array's full length (which may exceed cap), -1 for bad arguments, -2
+ * for a mesh the builder rejects.
+ * hopu_host_sizes: sizes of the space for (dim, k): which = 0 n_loc, 1 n_f
+ * (DoFs per facet), 2 n_int (interior DoFs per element), 3 dim P^k, 4 volume
+ * points, 5 facet points; -1 for an unsupported (dim, k) or which. */
 int64_t hopu_host_tables(int dim, int k, int which, double* out, int64_t cap);
 int64_t hopu_host_mesh(int dim, int64_t n_elems, const int64_t* elem_vid,
                        const double* elem_xyz, int which, void* out, int64_t cap);
