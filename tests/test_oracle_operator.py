@@ -115,6 +115,37 @@ def test_central_part_skew_symmetric(dim):
     assert np.abs(A + A.T).max() <= 1e-13 * np.abs(A).max()
 
 
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_upwind_dissipation_closed_form_layered_flow(k):
+    """u = (p(y), c) with p constant on each row of cells of a periodic 2D
+    Kuhn mesh lies in V_h (u.n is c on horizontal facets and p of the row on
+    the others) and is exactly divergence-free; its only jumps are
+    tangential, (p_j - p_{j+1}, 0) on the horizontal facets between rows j
+    and j+1, where |u.n| = |c|.  The standard upwind flux (eq. (upwind),
+    l = -1) then dissipates D = 1/2 |c| Lx sum_j (p_j - p_{j+1})^2 (rows
+    wrap), and u.r(u) = D because grad u = 0 in every element and the
+    central form is skew.  For l >= 0 the jump is a constant on each facet,
+    which Pi^l keeps, so nothing is dissipated."""
+    nx, ny = 3, 4
+    mesh = kuhn_mesh(2, (nx, ny), (1.0, 1.0), (True, True))
+    sp = S.Space(mesh.elem_vid, mesh.elem_xyz, k)
+    p = np.array([0.3, -0.7, 1.1, 0.2])
+    c = -0.6
+
+    def f(x):
+        row = np.floor(x[..., 1] * ny + 1e-9).astype(int) % ny
+        return np.stack([p[row], np.full(x.shape[:-1], c)], -1)
+
+    x = sp.interpolate(f)
+    D = 0.5 * abs(c) * 1.0 * np.sum((p - np.roll(p, -1)) ** 2)
+    assert O.dissipation(sp, x, -1) == pytest.approx(D, rel=1e-12)
+    r = O.residual(sp, x, -1)
+    assert x @ r == pytest.approx(D, rel=1e-11)
+    for l in range(0, k + 1):
+        assert O.dissipation(sp, x, l) <= 1e-24
+        assert abs(x @ O.residual(sp, x, l)) <= 1e-12 * D
+
+
 def test_central_part_skew_symmetric_periodic(periodic2d):
     sp, f = periodic2d
     w = sp.interpolate(f, nq1d=10)
