@@ -115,29 +115,36 @@ def test_central_part_skew_symmetric(dim):
     assert np.abs(A + A.T).max() <= 1e-13 * np.abs(A).max()
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
-def test_upwind_dissipation_closed_form_layered_flow(k):
-    """u = (p(y), c) with p constant on each row of cells of a periodic 2D
-    Kuhn mesh lies in V_h (u.n is c on horizontal facets and p of the row on
-    the others) and is exactly divergence-free; its only jumps are
-    tangential, (p_j - p_{j+1}, 0) on the horizontal facets between rows j
-    and j+1, where |u.n| = |c|.  The standard upwind flux (eq. (upwind),
-    l = -1) then dissipates D = 1/2 |c| Lx sum_j (p_j - p_{j+1})^2 (rows
-    wrap), and u.r(u) = D because grad u = 0 in every element and the
-    central form is skew.  For l >= 0 the jump is a constant on each facet,
-    which Pi^l keeps, so nothing is dissipated."""
-    nx, ny = 3, 4
-    mesh = kuhn_mesh(2, (nx, ny), (1.0, 1.0), (True, True))
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2)])
+def test_upwind_dissipation_closed_form_layered_flow(dim, k):
+    """u = (p(y), c) in 2D, (p(y), c, q(y)) in 3D, with p, q constant on
+    each row of cells of a periodic Kuhn mesh, lies in V_h (u.n is +-c on
+    the facets between rows and is taken inside one row on all others) and
+    is exactly divergence-free; its only jumps are tangential,
+    (p_j - p_{j+1}, 0, q_j - q_{j+1}) on the facets between rows j and j+1,
+    where |u.n| = |c|.  The standard upwind flux (eq. (upwind), l = -1)
+    then dissipates D = 1/2 |c| A sum_j |jump_j|^2 (rows wrap; A the area of
+    one row interface), and u.r(u) = D because grad u = 0 in every element
+    and the central form is skew.  For l >= 0 the jump is a constant on
+    each facet, which Pi^l keeps, so nothing is dissipated."""
+    ny = 4
+    n = (3, ny) if dim == 2 else (3, ny, 3)
+    lengths = (1.0, 1.0) if dim == 2 else (1.5, 1.0, 0.5)
+    mesh = kuhn_mesh(dim, n, lengths, (True,) * dim)
     sp = S.Space(mesh.elem_vid, mesh.elem_xyz, k)
     p = np.array([0.3, -0.7, 1.1, 0.2])
+    q = np.array([-0.4, 0.5, 0.0, 0.9])
     c = -0.6
 
     def f(x):
         row = np.floor(x[..., 1] * ny + 1e-9).astype(int) % ny
-        return np.stack([p[row], np.full(x.shape[:-1], c)], -1)
+        comps = [p[row], np.full(x.shape[:-1], c)] + ([q[row]] if dim == 3 else [])
+        return np.stack(comps, -1)
 
     x = sp.interpolate(f)
-    D = 0.5 * abs(c) * 1.0 * np.sum((p - np.roll(p, -1)) ** 2)
+    area = 1.0 if dim == 2 else lengths[0] * lengths[2]
+    jump2 = (p - np.roll(p, -1)) ** 2 + ((q - np.roll(q, -1)) ** 2 if dim == 3 else 0.0)
+    D = 0.5 * abs(c) * area * np.sum(jump2)
     assert O.dissipation(sp, x, -1) == pytest.approx(D, rel=1e-12)
     r = O.residual(sp, x, -1)
     assert x @ r == pytest.approx(D, rel=1e-11)
