@@ -151,6 +151,17 @@ def test_upwind_dissipation_closed_form_layered_flow(dim, k):
     for l in range(0, k + 1):
         assert O.dissipation(sp, x, l) <= 1e-24
         assert abs(x @ O.residual(sp, x, l)) <= 1e-12 * D
+    # jump indicator (end of section 3.2): |jump_j| / |<u>_j| on each facet
+    # between rows j and j+1 (nx of them in 2D, 2 nx nz triangles in 3D), 0
+    # on every other facet; 0 everywhere once Pi^l (l >= 0) removes the jump
+    pn, qn = np.roll(p, -1), np.roll(q, -1)
+    jmp = np.sqrt((p - pn) ** 2 + ((q - qn) ** 2 if dim == 3 else 0.0))
+    avg = np.sqrt(((p + pn) / 2) ** 2 + c * c + (((q + qn) / 2) ** 2 if dim == 3 else 0.0))
+    per_row = n[0] if dim == 2 else 2 * n[0] * n[2]
+    want = np.concatenate([np.repeat(jmp / avg, per_row), np.zeros(sp.topo.n_facets - ny * per_row)])
+    eta = O.jump_indicator(sp, x, -1)
+    assert np.allclose(np.sort(eta), np.sort(want), rtol=1e-12, atol=1e-12)
+    assert np.abs(O.jump_indicator(sp, x, 0)).max() <= 1e-12
 
 
 def test_central_part_skew_symmetric_periodic(periodic2d):
