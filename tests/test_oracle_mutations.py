@@ -1,11 +1,13 @@
 """Planted mistakes in the oracle (on the CPU only) must each break a pin.
 This checks that the pins can see plausible errors: a flipped normal, a
-wrong projection degree, a transposed Jacobian, a dropped facet scaling."""
+wrong projection degree, a transposed Jacobian, a dropped facet scaling, a
+doubled upwind weight."""
 import numpy as np
 import pytest
 
 import synth
 from synth import fields
+from synth.mesh import kuhn_mesh
 from oracle import space as S, operator as O
 
 VOL, CEN, UP = O.TERM_VOLUME, O.TERM_CENTRAL, O.TERM_UPWIND
@@ -62,3 +64,38 @@ def test_dropped_facet_scaling_is_caught():
     # reproduces the constant, so the zero pin fails
     r = O.residual(sp, x, 1)
     assert np.abs(r).max() > 1e-8
+
+
+def _layered_dissipation_ok():
+    """The closed-form upwind dissipation of the layered flow u = (p(y), c)
+    (one constant per row of cells): 1/2 |c| sum_j (p_j - p_{j+1})^2."""
+    mesh = kuhn_mesh(2, (3, 4), (1.0, 1.0), (True, True))
+    sp = S.Space(mesh.elem_vid, mesh.elem_xyz, 2)
+    p, c = np.array([0.3, -0.7, 1.1, 0.2]), -0.6
+
+    def f(x):
+        row = np.floor(x[..., 1] * 4 + 1e-9).astype(int) % 4
+        return np.stack([p[row], np.full(x.shape[:-1], c)], -1)
+
+    x = sp.interpolate(f)
+    D = 0.5 * abs(c) * np.sum((p - np.roll(p, -1)) ** 2)
+    # the identity u.r(u) = D holds with or without the mistake below; only
+    # the closed form sees it
+    return abs(x @ O.residual(sp, x, -1) - O.dissipation(sp, x, -1)) <= 1e-11 * D, \
+        abs(O.dissipation(sp, x, -1) - D) <= 1e-12 * D
+
+
+def test_doubled_upwind_weight_is_caught(monkeypatch):
+    assert _layered_dissipation_ok() == (True, True)
+
+    class DoubledAbs:
+        """numpy with |.| doubled: the upwind weight 1/2 |u.n| becomes |u.n|"""
+        def __getattr__(self, name):
+            return getattr(np, name)
+
+        @staticmethod
+        def abs(v):
+            return 2.0 * np.abs(v)
+
+    monkeypatch.setattr(O, "np", DoubledAbs())
+    assert _layered_dissipation_ok() == (True, False)
