@@ -42,6 +42,11 @@
  *   - work is queued on the context's stream; calls marked "syncs" wait for
  *     it before returning; others are asynchronous;
  *   - a context is not thread-safe; calls on one context must not overlap.
+ *
+ * Test hooks (environment variables, for tests of failure and wrap-around
+ * paths; unset in normal use): HOPU_TEST_FAIL_ALLOC=1 makes every device
+ * allocation of the library fail with HOPU_ENOMEM; HOPU_TEST_RING=h sets
+ * the PCG search-direction ring to h vectors (see hopu_create).
  */
 #ifndef HOPU_H
 #define HOPU_H

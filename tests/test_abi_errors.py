@@ -64,8 +64,10 @@ def test_malformed_meshes():
 
 
 def test_alloc_failure_is_reported():
-    """HOPU_TEST_FAIL_ALLOC=1 makes the first device allocation fail:
-    create returns HOPU_ENOMEM (run in a child process with the env set)."""
+    """HOPU_TEST_FAIL_ALLOC=1 makes every device allocation fail, so the
+    first one in create does: create returns HOPU_ENOMEM, frees what it
+    holds and leaves the handle NULL (run in a child process with the env
+    set)."""
     code = (
         "import ctypes as C, numpy as np, synth\n"
         "from paper_2408_06698_amd import _lib as L\n"
