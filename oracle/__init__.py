@@ -26,6 +26,7 @@ transitional turbulent flows"):
 
 Everything is evaluated in physical coordinates with element and facet loops
 (vectorised over batches).  Parity status of each function is stated in its
-docstring; items the paper does not fix are listed in the design doc.
+docstring, and so is each reading taken where the paper does not fix an
+item (the quadrature rule, the basis, the adaptive thresholds' ties).
 """
 from . import quadrature, basis, mesh, space, operator  # noqa: F401
