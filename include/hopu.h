@@ -66,7 +66,7 @@ typedef enum {
   HOPU_ENOMEM = -3,       /* device allocation failed */
   HOPU_EHIP = -4,         /* HIP runtime error */
   HOPU_ENOCONV = -5,      /* PCG did not reach the tolerance in max_it */
-  HOPU_EUNSUPPORTED = -6  /* valid request this build does not implement */
+  HOPU_EUNSUPPORTED = -6  /* valid request the library does not implement */
 } hopu_status;
 
 typedef enum {
