@@ -162,6 +162,11 @@ def test_upwind_dissipation_closed_form_layered_flow(dim, k):
     eta = O.jump_indicator(sp, x, -1)
     assert np.allclose(np.sort(eta), np.sort(want), rtol=1e-12, atol=1e-12)
     assert np.abs(O.jump_indicator(sp, x, 0)).max() <= 1e-12
+    # kinetic energy 1/2 int |u|^2 and divergence of the piecewise-constant field
+    vol_row = np.prod(lengths) / ny
+    E = 0.5 * vol_row * np.sum(p ** 2 + c * c + (q ** 2 if dim == 3 else 0.0))
+    assert O.energy(sp, x) == pytest.approx(E, rel=1e-13)
+    assert O.divergence_l2(sp, x) <= 1e-13
 
 
 def test_central_part_skew_symmetric_periodic(periodic2d):
