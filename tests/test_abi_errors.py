@@ -82,3 +82,15 @@ def test_alloc_failure_is_reported():
     env = dict(os.environ, HOPU_TEST_FAIL_ALLOC="1", PYTHONPATH=root)
     res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, cwd=root)
     assert res.returncode == 0, res.stderr + res.stdout
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No CPU fallback: without libhopu.so the binding's entry to the
+    library raises, naming the build command, and so does reading the
+    error of a failed call."""
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libhopu.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(ImportError, match="build"):
+        L.lib()
+    with pytest.raises(ImportError):
+        L.check(L.HOPU_OK + 1)
