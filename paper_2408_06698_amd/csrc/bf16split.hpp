@@ -19,8 +19,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // operand is split by truncation into NS bfloat16 terms (hi, [mid,] lo; each
 // term the leading 8 bits of what the previous ones leave), and products two
 // levels below the leading one or lower are dropped: NS = 2 keeps hh, hl,
-// lh (about 16 significant bits), NS = 3 keeps hh, hm, mh, hl, mm, lh (the
-// 24 bits of the FP32 value).
+// lh (each operand to about 16 significant bits, each product to about
+// 13), NS = 3 keeps hh, hm, mh, hl, mm, lh (each FP32 operand exactly, each
+// product to about 21 bits against FP32's 24).
 template <int NS>
 using BfTab = BfPack<(NS > 0 ? NS : 1)>;
 template <typename T, int NS>
