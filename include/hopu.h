@@ -162,8 +162,8 @@ hopu_status hopu_mass_solve(hopu_ctx ctx, const double* r, double* w,
  * The first call allocates the step's workspace (E dim P^{k-1}^2 + (4 + H)
  * (F + W) n_f doubles; H, the CG's search-direction ring, is
  * min(17, 8 GB / (8 (F + W) n_f)) and at least 4) and computes the element
- * matrices A^-1; later calls allocate nothing.  Syncs.  HOPU_ENOCONV if max_it is reached (unew is still
- * written from the last iterate). */
+ * matrices A^-1; later calls allocate nothing.  Syncs.  HOPU_ENOCONV if
+ * max_it is reached (unew is still written from the last iterate). */
 hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* unew,
                          double rtol, int max_it, int* iters);
 
@@ -220,11 +220,12 @@ hopu_status hopu_eval(hopu_ctx ctx, const double* u, int n_pts,
  * every launch), up to n recorded launches, and resets earlier records;
  * (ctx, 0, 0) stops.  Events on a dispatch delay it by a few microseconds,
  * so a stride keeps a timed run close to an uninstrumented one.  Launches
- * that a converged PCG left queued are not counted.  hopu_profile_read returns, for one
- * kernel kind (0 element/convection kernel, 1 mass apply inside PCG,
- * 2 preconditioner inside PCG, 3 dual->modal transform, 4 transpose-Jacobian
- * kernel, 5 mass/preconditioner applies outside the PCG loop), the number of
- * recorded launches and their summed duration in ms.  Both sync. */
+ * that a converged PCG left queued are not counted.  hopu_profile_read
+ * returns, for one kernel kind (0 element/convection kernel, 1 mass apply
+ * inside PCG, 2 preconditioner inside PCG, 3 dual->modal transform,
+ * 4 transpose-Jacobian kernel, 5 mass/preconditioner applies outside the
+ * PCG loop), the number of recorded launches and their summed duration in
+ * ms.  Both sync. */
 hopu_status hopu_profile_enable(hopu_ctx ctx, int enable, int max_launches);
 hopu_status hopu_profile_read(hopu_ctx ctx, int kind, int64_t* launches, double* total_ms);
 
