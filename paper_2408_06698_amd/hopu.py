@@ -14,9 +14,16 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _dev(t):
-    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise ValueError("expected a contiguous float64 tensor on the GPU")
+def _dev(t, n=None, dtype=torch.float64, what="vector"):
+    """A tensor whose data pointer goes to the library: checked here, since
+    the library cannot tell a short, host or mistyped buffer from a good one
+    (n: the number of entries the call reads or writes)."""
+    if not torch.is_tensor(t):
+        raise TypeError(f"{what}: expected a torch tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{what}: expected {n} entries, got {t.numel()}")
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{what}: expected a contiguous {dtype} tensor on the GPU")
     return t
 
 
@@ -69,12 +76,14 @@ class Hopu:
         return torch.zeros(self.n_dof, dtype=torch.float64, device=self.device)
 
     def set_upwind(self, l, l_per_facet=None):
-        self._lfac = l_per_facet
+        if l_per_facet is not None:
+            _dev(l_per_facet, self.n_facets, torch.int8, "l_per_facet")
+        self._lfac = l_per_facet  # the library keeps the pointer
         check(L.lib().hopu_set_upwind(self.h, int(l), _ptr(l_per_facet)), self.h)
 
     def jump_indicator(self, u):
         eta = torch.empty(self.n_facets, dtype=torch.float64, device=self.device)
-        check(L.lib().hopu_jump_indicator(self.h, _ptr(_dev(u)), _ptr(eta)), self.h)
+        check(L.lib().hopu_jump_indicator(self.h, _ptr(_dev(u, self.n_dof)), _ptr(eta)), self.h)
         return eta
 
     def set_adaptive(self, every, thresholds=None, l_initial=-1):
@@ -86,7 +95,7 @@ class Hopu:
                                         int(l_initial)), self.h)
 
     def adapt_upwind(self, u):
-        check(L.lib().hopu_adapt_upwind(self.h, _ptr(_dev(u))), self.h)
+        check(L.lib().hopu_adapt_upwind(self.h, _ptr(_dev(u, self.n_dof))), self.h)
 
     def facet_orders(self):
         """The context's current per-facet orders (adaptive mode), int8."""
@@ -99,18 +108,18 @@ class Hopu:
 
     def apply(self, u, r=None, terms=TERM_ALL, prec=FP64):
         r = self.zeros() if r is None else r
-        check(L.lib().hopu_convection_apply(self.h, _ptr(_dev(u)), _ptr(_dev(r)), terms, prec), self.h)
+        check(L.lib().hopu_convection_apply(self.h, _ptr(_dev(u, self.n_dof)), _ptr(_dev(r, self.n_dof)), terms, prec), self.h)
         return r
 
     def mass_apply(self, u, y=None):
         y = self.zeros() if y is None else y
-        check(L.lib().hopu_mass_apply(self.h, _ptr(_dev(u)), _ptr(_dev(y))), self.h)
+        check(L.lib().hopu_mass_apply(self.h, _ptr(_dev(u, self.n_dof)), _ptr(_dev(y, self.n_dof))), self.h)
         return y
 
     def mass_solve(self, r, w=None, rtol=0.0, max_it=1000):
         w = self.zeros() if w is None else w
         its = C.c_int()
-        check(L.lib().hopu_mass_solve(self.h, _ptr(_dev(r)), _ptr(_dev(w)), float(rtol), int(max_it),
+        check(L.lib().hopu_mass_solve(self.h, _ptr(_dev(r, self.n_dof)), _ptr(_dev(w, self.n_dof)), float(rtol), int(max_it),
                                       C.byref(its)), self.h)
         return w, its.value
 
@@ -118,18 +127,18 @@ class Hopu:
         """u_new = u* - u~ (projection step); returns (u_new, CG iterations)."""
         out = self.zeros() if out is None else out
         its = C.c_int()
-        check(L.lib().hopu_project(self.h, _ptr(_dev(ustar)), _ptr(_dev(out)), float(rtol), int(max_it),
+        check(L.lib().hopu_project(self.h, _ptr(_dev(ustar, self.n_dof)), _ptr(_dev(out, self.n_dof)), float(rtol), int(max_it),
                                    C.byref(its)), self.h)
         return out, its.value
 
     def substeps(self, u, dt, n_steps, prec=FP64, diag=False):
         d = torch.zeros((n_steps + 1, 5), dtype=torch.float64, device=self.device) if diag else None
-        check(L.lib().hopu_substeps(self.h, _ptr(_dev(u)), float(dt), int(n_steps), prec, _ptr(d)), self.h)
+        check(L.lib().hopu_substeps(self.h, _ptr(_dev(u, self.n_dof)), float(dt), int(n_steps), prec, _ptr(d)), self.h)
         return d
 
     def vjp(self, u, mu, out=None, prec=FP64):
         out = self.zeros() if out is None else out
-        check(L.lib().hopu_convection_vjp(self.h, _ptr(_dev(u)), _ptr(_dev(mu)), _ptr(_dev(out)), prec), self.h)
+        check(L.lib().hopu_convection_vjp(self.h, _ptr(_dev(u, self.n_dof)), _ptr(_dev(mu, self.n_dof)), _ptr(_dev(out, self.n_dof)), prec), self.h)
         return out
 
     def substeps_vjp(self, u0, dt, n_steps, lam_N, ckpt_every=5, prec=FP64):
@@ -138,14 +147,14 @@ class Hopu:
             check(int(nb), self.h)
         ws = torch.empty(max(int(nb), 8), dtype=torch.uint8, device=self.device)
         lam0 = self.zeros()
-        check(L.lib().hopu_substeps_vjp(self.h, _ptr(_dev(u0)), float(dt), int(n_steps), int(ckpt_every),
-                                        _ptr(_dev(lam_N)), _ptr(lam0), prec, _ptr(ws), int(ws.numel())),
+        check(L.lib().hopu_substeps_vjp(self.h, _ptr(_dev(u0, self.n_dof)), float(dt), int(n_steps), int(ckpt_every),
+                                        _ptr(_dev(lam_N, self.n_dof)), _ptr(lam0), prec, _ptr(ws), int(ws.numel())),
               self.h)
         return lam0
 
     def diagnostics(self, u):
         e, dv, ds = C.c_double(), C.c_double(), C.c_double()
-        check(L.lib().hopu_diagnostics(self.h, _ptr(_dev(u)), C.byref(e), C.byref(dv), C.byref(ds)), self.h)
+        check(L.lib().hopu_diagnostics(self.h, _ptr(_dev(u, self.n_dof)), C.byref(e), C.byref(dv), C.byref(ds)), self.h)
         return e.value, dv.value, ds.value
 
     def interp_points(self, n1d):
@@ -162,8 +171,8 @@ class Hopu:
         [..., d] tensors), sampled at the library's points."""
         n1d = n1d or (self.k + 2)
         pf, pv = self.interp_points(n1d)
-        vf = field(pf).contiguous()
-        vv = field(pv).contiguous()
+        vf = _dev(field(pf).contiguous(), pf.numel(), what="field values at facet points")
+        vv = _dev(field(pv).contiguous(), pv.numel(), what="field values at volume points")
         u = self.zeros()
         check(L.lib().hopu_interpolate(self.h, int(n1d), _ptr(vf), _ptr(vv), _ptr(u)), self.h)
         return u
@@ -182,9 +191,11 @@ class Hopu:
 
     def eval(self, u, ref_pts):
         ref = np.ascontiguousarray(ref_pts, dtype=np.float64)
+        if ref.ndim != 2 or ref.shape[1] != self.dim:
+            raise ValueError(f"ref_pts: expected shape [n_pts][{self.dim}], got {ref.shape}")
         out = torch.empty((self.n_elems, ref.shape[0], self.dim), dtype=torch.float64, device=self.device)
-        check(L.lib().hopu_eval(self.h, _ptr(_dev(u)), ref.shape[0], ref.ctypes.data_as(C.c_void_p), _ptr(out)),
-              self.h)
+        check(L.lib().hopu_eval(self.h, _ptr(_dev(u, self.n_dof)), ref.shape[0],
+                                ref.ctypes.data_as(C.c_void_p), _ptr(out)), self.h)
         return out
 
 

@@ -94,3 +94,18 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         L.lib()
     with pytest.raises(ImportError):
         L.check(L.HOPU_OK + 1)
+
+
+def test_binding_checks_buffers_before_the_library():
+    """Device pointers cannot be checked by the library, so the binding
+    refuses short, host-resident, mistyped or non-tensor buffers first."""
+    import torch
+    from paper_2408_06698_amd.hopu import _dev
+    with pytest.raises(TypeError):
+        _dev(np.zeros(4), 4)
+    with pytest.raises(ValueError, match="expected 4 entries"):
+        _dev(torch.zeros(3, dtype=torch.float64), 4)
+    with pytest.raises(ValueError, match="on the GPU"):
+        _dev(torch.zeros(4, dtype=torch.float64), 4)
+    with pytest.raises(ValueError, match="expected 5 entries"):
+        _dev(torch.zeros(4, dtype=torch.int8), 5, torch.int8, "l_per_facet")
