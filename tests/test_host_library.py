@@ -168,3 +168,17 @@ def test_host_bf16_split_tables(dim, k):
                     assert np.array_equal(tot, f.astype(np.float64))
                 else:
                     assert np.all(np.abs(tot - f) <= 2.0 ** -15 * np.abs(f))
+
+
+def test_build_flags():
+    """Every HIP source is compiled for gfx950 with packed FP32 instructions
+    switched off (the compiler would otherwise form v_pk_* FP32 ops from
+    ordinary float code), and every source file in csrc is built."""
+    import glob
+    import os
+    from paper_2408_06698_amd import build as B
+    assert "--offload-arch=gfx950" in B.FLAGS
+    i = B.FLAGS.index("-packed-fp32-ops")
+    assert B.FLAGS[i - 3:i] == ["-Xclang", "-target-feature", "-Xclang"]
+    srcs = glob.glob(os.path.join(B.CSRC, "*.hip")) + glob.glob(os.path.join(B.CSRC, "*.cpp"))
+    assert {os.path.basename(p) for p in srcs} == set(B.SOURCES)
