@@ -185,10 +185,13 @@ def mass_matrix(sp):
     return M
 
 
-def mass_solve(sp, r):
-    """w = M^{-1} r: sparse LU for small spaces, CG to 1e-15 otherwise."""
+def mass_solve(sp, r, method=None):
+    """w = M^{-1} r: sparse LU for small spaces, CG to 1e-15 otherwise.
+    method "cg" asks for the CG solve at any size (the LU's fill on large 3D
+    meshes costs minutes; CG reaches relative residuals near 1e-13 there,
+    enough for convergence-order checks, not for 1e-12 parity)."""
     M = mass_matrix(sp)
-    if sp.n_dof <= 200000:
+    if sp.n_dof <= 200000 and method != "cg":
         lu = getattr(sp, "_mass_lu", None)
         if lu is None:
             lu = spla.splu(M.tocsc())
@@ -374,6 +377,80 @@ def assemble_picard(sp, w, l, terms=TERM_ALL):
                     v += np.sum(ds * 0.5 * np.abs(un) * np.sum(jjp * jip, -1))
                 C[gi, gj] += v
     return C
+
+
+def assemble_jacobian(sp, w, l, terms=TERM_ALL):
+    """Dense Jacobian J(w)_ij = d r_i / d u_j at u = w, by double loops over
+    physical basis products of the linearised residual (tiny meshes only).
+    Differentiating each term of the residual in the direction phi_j:
+      volume   - int (phi_j x w + w x phi_j) : grad phi_i
+      central  + int (<phi_j>.n) <w>.[[phi_i]] + (w.n) <phi_j>.[[phi_i]]
+      upwind   + int 1/2 sgn(w.n) (<phi_j>.n) (I-Pi)[[w]] . (I-Pi)[[phi_i]]
+                     + 1/2 |w.n| (I-Pi)[[phi_j]] . (I-Pi)[[phi_i]]
+    with sgn(0) = 0 (|.| is not differentiable at 0; the reading used for
+    the adjoint).  Written independently of vjp(): J^T mu must equal
+    vjp(w, mu), and J(w) w = 2 r(w) (r is homogeneous of degree 2)."""
+    t = sp.topo
+    N = sp.n_dof
+    Jm = np.zeros((N, N))
+    if terms & TERM_VOLUME:
+        for e in range(t.n_elems):
+            eb = np.array([e])
+            phi = sp.phys_vals(eb, sp.ref_vals)[0]      # [q][n][d]
+            gphi = sp.phys_grads(eb, sp.ref_grads)[0]   # [q][n][a][c] = d_c phi_a
+            u = np.einsum("qid,i->qd", phi, sp.local(w, eb)[0])
+            wdx = sp.wq * abs(t.detJ[e])
+            g = sp.gdof[e]
+            for a_ in range(sp.n):
+                if g[a_] < 0:
+                    continue
+                for b_ in range(sp.n):
+                    if g[b_] < 0:
+                        continue
+                    pj = phi[:, b_]
+                    # (phi_j x w + w x phi_j) : grad phi_i, sum over a, c
+                    v = np.einsum("qa,qc,qac->q", pj, u, gphi[:, a_]) + \
+                        np.einsum("qa,qc,qac->q", u, pj, gphi[:, a_])
+                    Jm[g[a_], g[b_]] -= np.sum(wdx * v)
+    if terms & (TERM_CENTRAL | TERM_UPWIND):
+        lf_all = sp.facet_l(l)
+        for f in range(t.n_facets):
+            fb = np.array([f])
+            T, T2, phiT, phiT2, nvec, ds = _facet_traces(sp, fb)
+            phiT, phiT2, nvec, ds = phiT[0], phiT2[0], nvec[0], ds[0]
+            wT = np.einsum("qid,i->qd", phiT, sp.local(w, T)[0])
+            wT2 = np.einsum("qid,i->qd", phiT2, sp.local(w, T2)[0])
+            wavg = 0.5 * (wT + wT2)
+            wn = wavg @ nvec
+            P = _projector(sp, lf_all[fb])[0]
+            wjp = (wT - wT2) - P @ (wT - wT2)
+            gT, gT2 = sp.gdof[T[0]], sp.gdof[T2[0]]
+            idx = sorted(set(gT[gT >= 0]) | set(gT2[gT2 >= 0]))
+            tr1, tr2 = {}, {}
+            for gg in idx:
+                a1 = np.zeros((len(ds), sp.dim))
+                a2 = np.zeros((len(ds), sp.dim))
+                for loc in np.nonzero(gT == gg)[0]:
+                    a1 += phiT[:, loc]
+                for loc in np.nonzero(gT2 == gg)[0]:
+                    a2 += phiT2[:, loc]
+                tr1[gg], tr2[gg] = a1, a2
+            for gi in idx:
+                ji = tr1[gi] - tr2[gi]
+                jip = ji - P @ ji
+                for gj in idx:
+                    aj = 0.5 * (tr1[gj] + tr2[gj])
+                    ajn = aj @ nvec
+                    jj = tr1[gj] - tr2[gj]
+                    jjp = jj - P @ jj
+                    v = 0.0
+                    if terms & TERM_CENTRAL:
+                        v += np.sum(ds * (ajn * np.sum(wavg * ji, -1) + wn * np.sum(aj * ji, -1)))
+                    if terms & TERM_UPWIND:
+                        v += np.sum(ds * 0.5 * np.sign(wn) * ajn * np.sum(wjp * jip, -1))
+                        v += np.sum(ds * 0.5 * np.abs(wn) * np.sum(jjp * jip, -1))
+                    Jm[gi, gj] += v
+    return Jm
 
 
 def assemble_mass_dense(sp):

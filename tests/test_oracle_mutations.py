@@ -99,3 +99,30 @@ def test_doubled_upwind_weight_is_caught(monkeypatch):
 
     monkeypatch.setattr(O, "np", DoubledAbs())
     assert _layered_dissipation_ok() == (True, False)
+
+
+def _divergence_ok():
+    from tests.test_oracle_pins import walled_parabola_case
+    sp, x, want = walled_parabola_case(3, 2)
+    return abs(O.divergence_l2(sp, x) - want) <= 1e-13 * want
+
+
+class _NumpyWith:
+    """numpy with one function replaced (a planted mistake)"""
+    def __init__(self, **repl):
+        self.repl = repl
+
+    def __getattr__(self, name):
+        return self.repl.get(name, getattr(np, name))
+
+
+def test_divergence_mistakes_are_caught(monkeypatch):
+    """The closed-form divergence pin sees a dropped |det J| weight, a
+    missing square root and a doubled value."""
+    assert _divergence_ok()
+    monkeypatch.setattr(O, "np", _NumpyWith(abs=lambda v: np.ones_like(np.abs(v))))
+    assert not _divergence_ok()
+    monkeypatch.setattr(O, "np", _NumpyWith(sqrt=lambda v: v))
+    assert not _divergence_ok()
+    monkeypatch.setattr(O, "np", _NumpyWith(sqrt=lambda v: 2.0 * np.sqrt(v)))
+    assert not _divergence_ok()

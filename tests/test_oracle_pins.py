@@ -260,3 +260,39 @@ def test_normal_continuity_random_coefficients():
                    / sp.topo.NF_norm[T, sp.topo.facet_local[:, 0]][:, None])
     xf = x[:sp.topo.n_facets * sp.nf].reshape(-1, sp.nf)
     assert np.abs(un - xf @ sp.psi_q.T).max() < 1e-12 * np.abs(un).max()
+
+
+# ------------------------------------------------------------ diagnostics
+def walled_parabola_case(dim, k, jitter=0.05):
+    """u = (0, y(1 - y)) in 2D, (0, y(1 - y), 0) in 3D, on a box of lengths
+    (1.3, 1) or (1.5, 1, 0.5), periodic in x (and z), with walls at y = 0, 1,
+    graded in y and jittered.  u is a polynomial of degree 2 with u.n = 0 on
+    the walls, so it lies in V_h for k >= 2 and the canonical interpolant
+    reproduces it; div u = 1 - 2y, so ||div u||^2 = (box area across y) / 3."""
+    from synth.mesh import graded_nodes
+    n = (3, 4) if dim == 2 else (3, 4, 3)
+    lengths = (1.3, 1.0) if dim == 2 else (1.5, 1.0, 0.5)
+    periodic = (True, False) if dim == 2 else (True, False, True)
+    y = graded_nodes(n[1], 1.4, 1.0)
+    nodes = [None] * dim
+    nodes[1] = y / y[-1]
+    mesh = kuhn_mesh(dim, n, lengths, periodic, nodes, jitter=jitter, jitter_seed=17)
+    sp = S.Space(mesh.elem_vid, mesh.elem_xyz, k)
+
+    def f(x):
+        yy = x[..., 1]
+        comps = [0.0 * yy, yy * (1.0 - yy)] + ([0.0 * yy] if dim == 3 else [])
+        return np.stack(comps, -1)
+
+    area = lengths[0] * (lengths[2] if dim == 3 else 1.0)
+    return sp, sp.interpolate(f), math.sqrt(area / 3.0)
+
+
+@pytest.mark.parametrize("dim,k", [(2, 2), (2, 3), (3, 2), (3, 3)])
+def test_divergence_l2_closed_form(dim, k):
+    """||div u_h||_L2 (the substep diagnostic, with div u|_T = div^ u^/det J)
+    equals the closed form for a parabola in V_h on a graded, jittered,
+    walled mesh; the same field scaled by 3 gives 3 times the value."""
+    sp, x, want = walled_parabola_case(dim, k)
+    assert O.divergence_l2(sp, x) == pytest.approx(want, rel=1e-13)
+    assert O.divergence_l2(sp, 3.0 * x) == pytest.approx(3.0 * want, rel=1e-13)
