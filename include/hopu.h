@@ -77,9 +77,8 @@ typedef enum {
   HOPU_BF16X2 = 2,     /* the same contractions on BF16 MFMA, each operand split
                           into hi + lo bfloat16 terms (hh + hl + lh kept, about
                           16 significant bits); FP32 accumulation inside a
-                          tile, FP64 across tiles.  Apply and substeps; the
-                          adjoint calls return HOPU_EUNSUPPORTED for the split
-                          BF16 forms */
+                          tile, FP64 across tiles.  Apply, substeps and the
+                          adjoint calls */
   HOPU_BF16X3 = 3      /* hi + mid + lo split (hh, hm, mh, hl, mm, lh kept: the
                           24 bits of the FP32 value); otherwise as HOPU_BF16X2 */
 } hopu_precision;
@@ -195,6 +194,10 @@ hopu_status hopu_substeps_vjp(hopu_ctx ctx, const double* u0, double dt, int n_s
                               int ckpt_every, const double* lam_N, double* lam_0,
                               hopu_precision prec, void* ws, int64_t ws_bytes);
 
+/* Kinetic energy 1/2 u.Mu of u (dev [n_dof]) into energy_dev (dev, one
+ * double), FP64.  Asynchronous (the loss of the adjoint workload). */
+hopu_status hopu_energy(hopu_ctx ctx, const double* u, double* energy_dev);
+
 /* Energy 1/2 u.Mu, ||div u_h||_L2 and the upwind dissipation
  * sum_E int 1/2 |u.n| |(I-Pi^l)[[u]]|^2 (host scalars, nullable).  Syncs. */
 hopu_status hopu_diagnostics(hopu_ctx ctx, const double* u, double* energy,
@@ -242,9 +245,11 @@ void hopu_destroy(hopu_ctx ctx);
  * points [nqf][d-1], 4 facet weights, 5 psi [nqf][nf], 6 D [n][n],
  * 7 Dinv [n][n]; the element kernel's fragment tables in the FP32 register
  * layout: 8 vol_dVT [NQVT][4][d][NAT][64], 11 fac_Tr [d+1][NQFT][NPK][64],
- * and their split-BF16 copies as raw bfloat16 bit patterns (one per
- * double): 9 vol_dVT hi/lo, 10 vol_dVT hi/mid/lo, 12 fac_Tr hi/mid/lo, laid
- * out [outer][ceil(steps/4)][inner][64][terms][4].  Writes at most cap
+ * 13 vol_dV [NQVT][d][NPK][64], 14 vol_VT [NQVT][4][NAT][64] (the last two
+ * are the transpose-Jacobian kernel's volume tables), and split-BF16 copies
+ * as raw bfloat16 bit patterns (one per double): 9 vol_dVT hi/lo, 10 vol_dVT
+ * hi/mid/lo, 12 fac_Tr hi/mid/lo, 15 vol_dV hi/mid/lo, 16 vol_VT
+ * hi/mid/lo, laid out [outer][ceil(steps/4)][inner][64][terms][4].  Writes at most cap
  * doubles; returns the count or < 0.
  * hopu_host_mesh: topology/geometry of a mesh: which = 0 fid int32
  * [E][d+1], 1 nbr int32, 2 nbr_face (as int32), 3 geometry double

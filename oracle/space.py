@@ -103,9 +103,11 @@ class Space:
         return np.asarray(l, dtype=np.int64)
 
     # --------------------------------------------------- interpolation
-    def interpolate(self, field, nq1d=None):
+    def interpolate(self, field, nq1d=None, elems=None):
         """Canonical interpolant (the DoFs above applied to an analytic field),
-        computed with a collapsed rule of nq1d points per direction."""
+        computed with a collapsed rule of nq1d points per direction.  With
+        `elems`, only the DoFs of those elements (their facets' and their
+        interior DoFs) are computed; every other DoF is zero."""
         t = self.topo
         d = self.dim
         nq1d = nq1d or (self.k + 8)
@@ -114,8 +116,12 @@ class Space:
         ps = B.psi(d, self.k, s)
         T = t.facet_elems[:, 0]
         i = t.facet_local[:, 0]
-        for f0 in range(0, t.n_facets, 4096):
-            sl = slice(f0, min(t.n_facets, f0 + 4096))
+        facets = np.arange(t.n_facets)
+        if elems is not None:
+            fe = t.elem_facet[np.asarray(elems)].ravel()
+            facets = np.unique(fe[fe >= 0])
+        for f0 in range(0, len(facets), 4096):
+            sl = facets[f0:f0 + 4096]
             Tb, ib = T[sl], i[sl]
             lv = np.array([[v for v in range(d + 1) if v != ii] for ii in ib])
             xv = np.take_along_axis(t.xyz[Tb], lv[:, :, None], 1)  # [B][d][d]
@@ -125,12 +131,13 @@ class Space:
             nF = t.NF[Tb, ib] / t.NF_norm[Tb, ib][:, None]
             un = np.einsum("bqc,bc->bq", u, nF)
             vals = (un * ws[None, :]) @ ps  # [B][nf]
-            fid = np.arange(sl.start, sl.stop)
-            x[(fid[:, None] * self.nf + np.arange(self.nf)[None, :])] = vals
+            x[(sl[:, None] * self.nf + np.arange(self.nf)[None, :])] = vals
         xq, wq = simplex_rule(d, nq1d)
         qm = B.interior_tests(d, self.k, xq)  # [nq][nint][d]
         off = t.n_facets * self.nf
-        for eb in self.batches(t.n_elems, 4096):
+        ebs = self.batches(t.n_elems, 4096) if elems is None else \
+            (np.asarray(elems)[s0:s0 + 4096] for s0 in range(0, len(elems), 4096))
+        for eb in ebs:
             pts = t.xyz[eb, 0][:, None, :] + np.einsum("bcj,qj->bqc", t.J[eb], xq)
             u = field(pts)
             uh = np.einsum("b,bjc,bqc->bqj", t.detJ[eb], self.Jinv[eb], u)

@@ -37,6 +37,7 @@ struct hopu_ctx_s {
   const double *mass_in = nullptr, *mass_out = nullptr, *prec_in = nullptr, *prec_out = nullptr;
   const float *prec_in32 = nullptr, *prec_out32 = nullptr;  // FP32 preconditioner tables
   const double* vol_dV64 = nullptr;
+  const double *psi_n64 = nullptr, *psi_n32 = nullptr;  // u.n tables for the f64 / f32 row maps
   double* xyz = nullptr;
   // workspaces
   double* m64 = nullptr;
@@ -179,10 +180,9 @@ static hopu_status upload_bf16(hopu_ctx ctx, const FragTables& f32, int ns, DevT
   hopu_status st;
   if ((st = up(&t.vol_V, b.vol_V)) || (st = up(&t.vol_dVT, b.vol_dVT)) || (st = up(&t.fac_Tr, b.fac_Tr)) ||
       (st = up(&t.fac_TrT, b.fac_TrT)) || (st = up(&t.fac_K, b.fac_K)) || (st = up(&t.fac_Psi, b.fac_Psi)) ||
-      (st = up(&t.fac_PsiT, b.fac_PsiT)) || (st = up(&t.fac_KT, b.fac_KT)))
+      (st = up(&t.fac_PsiT, b.fac_PsiT)) || (st = up(&t.fac_KT, b.fac_KT)) || (st = up(&t.vol_dV, b.vol_dV)) ||
+      (st = up(&t.vol_VT, b.vol_VT)))
     return st;
-  t.vol_dV = nullptr;  // (adjoint tables: the adjoint has no split-BF16 form)
-  t.vol_VT = nullptr;
   t.modal = nullptr;  // the modal and dual transforms run in FP64
   t.dual = nullptr;
   t.dual64 = dual64;
@@ -318,6 +318,8 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     a.psi_deg = b.psi_deg = pdeg;
     TRY(upload_bf16(ctx, f32, 2, ctx->tbb2, b.dual64, wv, wf, pdeg));
     TRY(upload_bf16(ctx, f32, 3, ctx->tbb3, b.dual64, wv, wf, pdeg));
+    TRY(up64(&ctx->psi_n64, f64.psi_n));
+    TRY(up64(&ctx->psi_n32, f32.psi_n));
     TRY(up64(&ctx->mass_in, f64.mass_in));
     TRY(up64(&ctx->mass_out, f64.mass_out));
     TRY(up64(&ctx->prec_in, f64.prec_in));
@@ -504,15 +506,6 @@ static void do_mass(hopu_ctx ctx, int mode, const double* x, double* y, const in
 
 static hopu_status check_prec(hopu_ctx ctx, hopu_precision prec) {
   if ((int)prec < (int)HOPU_FP64 || (int)prec > (int)HOPU_BF16X3) return fail(ctx, HOPU_EINVAL, "unknown precision");
-  return HOPU_OK;
-}
-// The adjoint has FP64 and FP32-MFMA forms: a split-BF16 adjoint kernel was
-// built and measured, and its error grew with the order far beyond that of
-// the FP32 form (4e-4 at k = 5 for hi/mid/lo), so it is not offered.
-static hopu_status check_vjp_prec(hopu_ctx ctx, hopu_precision prec) {
-  if (check_prec(ctx, prec)) return HOPU_EINVAL;
-  if (prec == HOPU_BF16X2 || prec == HOPU_BF16X3)
-    return fail(ctx, HOPU_EUNSUPPORTED, "the adjoint has FP64 and FP32-MFMA forms only");
   return HOPU_OK;
 }
 
@@ -732,7 +725,8 @@ extern "C" hopu_status hopu_mass_solve(hopu_ctx ctx, const double* r, double* w,
 
 static hopu_status diag_into(hopu_ctx ctx, const double* u, double* dst /*dev [3]*/, bool have_modal_and_diss,
                              int64_t ndiss) {
-  // energy and divergence from the FP64 modal coefficients of u
+  // energy 1/2 u.Mu into dst[0] and ||div u||_L2 into dst[1], from the FP64
+  // modal coefficients of u
   hipStream_t s = ctx->stream;
   if (!have_modal_and_diss) {
     do_modal(ctx, u, HOPU_FP64);
@@ -742,9 +736,23 @@ static hopu_status diag_into(hopu_ctx ctx, const double* u, double* dst /*dev [3
     launch_energy<D, KK>(s, ctx->m64, ctx->dm, ctx->part);
     vec_scalar(s, ctx->part, AUX_NPART, ctx->sc, ctx->flag, OP_STORE, 0.0, dst + 0);
     nw = launch_div<D, KK>(s, ctx->m64, ctx->dm, ctx->vol_dV64, ctx->tb64.wv, ctx->part);
-    vec_scalar(s, ctx->part, (int)nw, ctx->sc, ctx->flag, OP_STORE, 0.0, dst + 1);
+    // ||div u||_L2: the square root of the summed squares, taken on the device
+    vec_scalar(s, ctx->part, (int)nw, ctx->sc, ctx->flag, OP_STORE_SQRT, 0.0, dst + 1);
   });
   (void)ndiss;
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_energy(hopu_ctx ctx, const double* u, double* energy_dev) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!u || !energy_dev) return fail(ctx, HOPU_EINVAL, "NULL pointer");
+  hopu_status st = do_modal(ctx, u, HOPU_FP64);
+  if (st) return st;
+  DISPATCH(ctx->dim, ctx->k, {
+    launch_energy<D, KK>(ctx->stream, ctx->m64, ctx->dm, ctx->part);
+    vec_scalar(ctx->stream, ctx->part, AUX_NPART, ctx->sc, ctx->flag, OP_STORE, 0.0, energy_dev);
+  });
+  HCHECK(hipGetLastError());
   return HOPU_OK;
 }
 
@@ -754,8 +762,7 @@ extern "C" hopu_status hopu_diagnostics(hopu_ctx ctx, const double* u, double* e
   if (!u) return fail(ctx, HOPU_EINVAL, "NULL vector");
   refresh_dm(ctx);
   hipStream_t s = ctx->stream;
-  double* dd = ctx->sc + 6;  // two spare scalar slots are not enough: use z as scratch
-  dd = ctx->z;
+  double* const dd = ctx->z;  // three device scalars (z is free outside the PCG)
   // dissipation: run the element kernel with facet terms and collect partials
   hopu_status st = do_apply(ctx, u, ctx->rc, HOPU_TERM_UPWIND, HOPU_FP64, ctx->part);
   if (st) return st;
@@ -765,7 +772,7 @@ extern "C" hopu_status hopu_diagnostics(hopu_ctx ctx, const double* u, double* e
   HCHECK(hipMemcpyAsync(h, dd, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   HCHECK(hipStreamSynchronize(s));
   if (energy) *energy = h[0];
-  if (div_l2) *div_l2 = std::sqrt(std::max(h[1], 0.0));
+  if (div_l2) *div_l2 = h[1];
   if (dissipation) *dissipation = h[2];
   return HOPU_OK;
 }
@@ -1006,11 +1013,12 @@ extern "C" int64_t hopu_host_tables(int dim, int k, int which, double* out, int6
   FragTables f32;
   BfTables bf;
   std::vector<double> bits;
-  if (which >= 8 && which <= 12) {
+  if (which >= 8 && which <= 16) {
     make_frag_tables(t, ROWMAP_F32, f32);
-    if (which == 9 || which == 10 || which == 12) {
+    if (which == 9 || which == 10 || which == 12 || which == 15 || which == 16) {
       make_bf16_tables(f32, t.sz, which == 9 ? 2 : 3, bf);
-      const std::vector<uint16_t>& b = which == 12 ? bf.fac_Tr : bf.vol_dVT;
+      const std::vector<uint16_t>& b =
+          which == 12 ? bf.fac_Tr : which == 15 ? bf.vol_dV : which == 16 ? bf.vol_VT : bf.vol_dVT;
       bits.assign(b.begin(), b.end());
     }
   }
@@ -1025,9 +1033,13 @@ extern "C" int64_t hopu_host_tables(int dim, int k, int which, double* out, int6
     case 7: v = &t.Dinv; break;
     case 8: v = &f32.vol_dVT; break;
     case 11: v = &f32.fac_Tr; break;
+    case 13: v = &f32.vol_dV; break;
+    case 14: v = &f32.vol_VT; break;
     case 9:
     case 10:
-    case 12: v = &bits; break;
+    case 12:
+    case 15:
+    case 16: v = &bits; break;
     default: return -1;
   }
   int64_t nwr = std::min<int64_t>(cap, (int64_t)v->size());
@@ -1068,8 +1080,14 @@ static hopu_status do_vjp(hopu_ctx ctx, const double* u, const double* mu, doubl
   do_modal(ctx, mu, prec, true);
   prof_begin(ctx, PROF_VJP);
   DISPATCH(ctx->dim, ctx->k, {
-    if (prec == HOPU_FP64) launch_vjp<double, D, KK>(ctx->stream, ctx->m64, ctx->mu64, out, ctx->slot, ctx->dm, ctx->tb64);
-    else launch_vjp<float, D, KK>(ctx->stream, ctx->m32, ctx->mu32, out, ctx->slot, ctx->dm, ctx->tb32);
+    if (prec == HOPU_FP64)
+      launch_vjp<double, D, KK>(ctx->stream, ctx->m64, ctx->mu64, out, ctx->slot, ctx->dm, ctx->tb64, u, ctx->psi_n64);
+    else if (prec == HOPU_BF16X2)
+      launch_vjp_bf<2, D, KK>(ctx->stream, ctx->m32, ctx->mu32, out, ctx->slot, ctx->dm, ctx->tbb2, u, ctx->psi_n32);
+    else if (prec == HOPU_BF16X3)
+      launch_vjp_bf<3, D, KK>(ctx->stream, ctx->m32, ctx->mu32, out, ctx->slot, ctx->dm, ctx->tbb3, u, ctx->psi_n32);
+    else
+      launch_vjp<float, D, KK>(ctx->stream, ctx->m32, ctx->mu32, out, ctx->slot, ctx->dm, ctx->tb32, u, ctx->psi_n32);
   });
   prof_end(ctx);
   DISPATCH(ctx->dim, ctx->k, { launch_assemble<D, KK>(ctx->stream, out, ctx->slot, ctx->dm, nullptr); });
@@ -1080,7 +1098,7 @@ extern "C" hopu_status hopu_convection_vjp(hopu_ctx ctx, const double* u, const 
                                            hopu_precision prec) {
   if (!ctx) return HOPU_EINVAL;
   if (!u || !mu || !out) return fail(ctx, HOPU_EINVAL, "NULL vector");
-  if (hopu_status sp = check_vjp_prec(ctx, prec)) return sp;
+  if (check_prec(ctx, prec)) return HOPU_EINVAL;
   refresh_dm(ctx);
   do_vjp(ctx, u, mu, out, prec);
   HCHECK(hipGetLastError());
@@ -1111,7 +1129,7 @@ extern "C" hopu_status hopu_substeps_vjp(hopu_ctx ctx, const double* u0, double 
   if (!ctx) return HOPU_EINVAL;
   if (!u0 || !lam_N || !lam_0 || !ws) return fail(ctx, HOPU_EINVAL, "NULL pointer");
   if (n_steps < 0 || ckpt_every < 1 || !std::isfinite(dt)) return fail(ctx, HOPU_EINVAL, "bad step arguments");
-  if (hopu_status sp = check_vjp_prec(ctx, prec)) return sp;
+  if (check_prec(ctx, prec)) return HOPU_EINVAL;
   const int64_t need = hopu_substeps_vjp_workspace(ctx, n_steps, ckpt_every);
   if (ws_bytes < need) return fail(ctx, HOPU_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
   refresh_dm(ctx);

@@ -450,6 +450,8 @@ void make_bf16_tables(const FragTables& f, const Sizes& s, int ns, BfTables& b) 
   b.fac_Psi = split_bf16_table(f.fac_Psi, d.NQFT, d.NFK, 1, ns);
   b.fac_PsiT = split_bf16_table(f.fac_PsiT, d.NQFT, 4, d.NFJT, ns);
   b.fac_KT = split_bf16_table(f.fac_KT, nfc * d.NAT, d.NFK, 1, ns);
+  b.vol_dV = split_bf16_table(f.vol_dV, d.NQVT * s.dim, d.NPK, 1, ns);
+  b.vol_VT = split_bf16_table(f.vol_VT, d.NQVT, 4, d.NAT, ns);
 }
 
 void make_frag_tables(const RefTables& t, RowMap rm, FragTables& f) {
@@ -596,6 +598,18 @@ void make_frag_tables(const RefTables& t, RowMap rm, FragTables& f) {
           f.fac_KT[((fc * fd.NAT + at) * fd.NFK + jk) * 64 + l] = t.Kf[(fc * nf + j) * nP + al];
         }
   }
+  // u.n at the facet points from the facet DoFs by an f64 MFMA (every
+  // precision form): the f64 MFMA puts output row 4i + g in register i of
+  // lane group g, so row 4i + g holds this row map's point rowof(i, g)
+  f.psi_n.assign(fd.NQFT * fd.NFK * 64, 0.0);
+  for (int qt = 0; qt < fd.NQFT; ++qt)
+    for (int jk = 0; jk < fd.NFK; ++jk)
+      for (int l = 0; l < 64; ++l) {
+        const int m = l & 15;
+        const int q = 16 * qt + rowof(m / 4, m % 4), j = 4 * jk + (l >> 4);
+        if (q >= s.nqf || j >= nf) continue;
+        f.psi_n[(qt * fd.NFK + jk) * 64 + l] = t.Psi[q * nf + j];
+      }
   f.fac_Psi.assign(fd.NQFT * fd.NFK * 64, 0.0);
   f.fac_PsiT.assign(fd.NQFT * 4 * fd.NFJT * 64, 0.0);
   for (int qt = 0; qt < fd.NQFT; ++qt) {

@@ -109,6 +109,8 @@ struct FragTables {
   std::vector<double> fac_Psi; // [NQFT][NFK][64]
   std::vector<double> fac_PsiT;// [NQFT][4][NFJT][64]  (facet weights folded in)
   std::vector<double> fac_KT;  // [dim+1][NAT][NFK][64]
+  std::vector<double> psi_n;   // [NQFT][NFK][64] FP64 values for the f64 MFMA, K = j (4 jk + lane group),
+                               // rows permuted so that register i of lane group g holds this row map's point
   std::vector<double> dual;    // [NJT][dim][NAT][4][64]  Dinv^T by (a, alpha tile, reg)
   // vjp extras
   std::vector<double> vol_dV;  // [NQVT][dim][NPK][64]  d_b p_alpha at (q, alpha)
@@ -142,6 +144,7 @@ void make_frag_tables(const RefTables& t, RowMap rm, FragTables& f);
 // [outer][ceil(nsteps/4)][inner][64][ns][4]; steps past nsteps are zero.
 struct BfTables {
   std::vector<uint16_t> vol_V, vol_dVT, fac_Tr, fac_TrT, fac_K, fac_Psi, fac_PsiT, fac_KT;
+  std::vector<uint16_t> vol_dV, vol_VT;  // the transpose-Jacobian kernel's volume tables
 };
 std::vector<uint16_t> split_bf16_table(const std::vector<double>& t, int outer, int nsteps, int inner, int ns);
 void make_bf16_tables(const FragTables& f32, const Sizes& s, int ns, BfTables& b);

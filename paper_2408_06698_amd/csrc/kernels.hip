@@ -1052,6 +1052,295 @@ __global__ __launch_bounds__(64 * MASS_WPB, 1) void k_mass_lds(const double* __r
   }
 }
 
+// Streamed-table variant for orders whose two tables do not fit in LDS
+// (3D k = 4: 197 KB, k = 5: 484 KB in FP64).  A block of TILE_WPB waves
+// walks TILE_WPB batches per round in lock step; the tables pass through a
+// double-buffered LDS window in chunks, each chunk copied once per block
+// (from L2) and read by all its waves, so the table traffic per batch drops
+// TILE_WPB-fold against one read per wave.  While the MFMAs of one chunk
+// run, every thread holds its share of the next chunk in registers and
+// stores it to the other buffer after them; one barrier per chunk.  Each
+// contraction runs in two passes over halves of its output tiles (the
+// accumulators of all tiles and the operand rows would not fit in the 256
+// registers of a kernel with two waves per SIMD); a chunk holds K steps of
+// one half, so every table entry is still copied once per round.
+// Every wave of a block runs the same number of rounds and chunks (a batch
+// past the end computes on clamped addresses and writes nothing).  A
+// round's gather (a few microseconds) against its ~50 microseconds of MFMA
+// work is left exposed: there are no registers for a prefetch.
+static constexpr int TILE_WPB = 8;
+
+template <int D, int KK>
+struct MassTile {
+  using C = Cfg<D, KK>;
+  // halves of the output tiles of each contraction
+  static constexpr int H1 = (C::NMT + 1) / 2;  // tiles of the first pass
+  static constexpr int H2 = (C::NJT + 1) / 2;
+  // steps per chunk, and chunks per pass
+  static constexpr int K1 = 7;
+  static constexpr int K2 = 8;
+  static constexpr int N1 = (C::NK + K1 - 1) / K1;
+  static constexpr int N2 = (C::NMQ + K2 - 1) / K2;
+  static constexpr int NCH = 2 * N1 + 2 * N2;  // chunks per round
+  static constexpr int CH1 = K1 * H1 * 64;     // doubles per chunk (largest of each kind)
+  static constexpr int CH2 = K2 * H2 * 64;
+  static constexpr int CH = CH1 > CH2 ? CH1 : CH2;
+  static constexpr int PER = (CH + 64 * TILE_WPB - 1) / (64 * TILE_WPB);  // per thread
+};
+
+// Chunk c of a round (c mod NCH): the first contraction's passes p = 0, 1
+// (chunks p N1 + j, steps j K1 ..), then the second's (2 N1 + p N2 + j).
+// Laid out [step - first step][tile - first tile][lane].
+template <int D, int KK>
+struct TileChunk {
+  const double* src;
+  int nk, k0, nks, t0, nts;  // table K size; first step and steps; first tile and tiles
+  __device__ __forceinline__ TileChunk(const double* fin, const double* fout, int c) {
+    using C = Cfg<D, KK>;
+    using TT = MassTile<D, KK>;
+    c %= TT::NCH;
+    const bool first = c < 2 * TT::N1;
+    const int cc = first ? c : c - 2 * TT::N1;
+    const int n = first ? TT::N1 : TT::N2, kc = first ? TT::K1 : TT::K2;
+    const int p = cc / n, j = cc - p * n;
+    const int half = first ? TT::H1 : TT::H2, nt = first ? C::NMT : C::NJT;
+    src = first ? fin : fout;
+    nk = first ? C::NK : C::NMQ;
+    k0 = j * kc;
+    nks = nk - k0 < kc ? nk - k0 : kc;
+    t0 = p * half;
+    nts = nt - t0 < half ? nt - t0 : half;
+  }
+};
+
+template <int D, int KK>
+__device__ __forceinline__ void tile_fetch(const double* __restrict__ fin, const double* __restrict__ fout, int c,
+                                           double (&st)[MassTile<D, KK>::PER]) {
+  using TT = MassTile<D, KK>;
+  const TileChunk<D, KK> k(fin, fout, c);
+  // an opaque copy of the base: the chunk's addresses do not depend on the
+  // round, and the compiler would otherwise hoist every round's loads out of
+  // the loop and hold all chunks in registers
+  const double* src = k.src;
+  asm volatile("" : "+s"(src));
+  int tid = (int)threadIdx.x;  // (likewise the per-thread offsets)
+  asm volatile("" : "+v"(tid));
+#pragma unroll
+  for (int p = 0; p < TT::PER; ++p) {
+    const int i = tid + p * 64 * TILE_WPB;
+    const int s = i / (k.nts * 64), rem = i - s * k.nts * 64;
+    const int t = k.t0 + (rem >> 6), l = rem & 63;
+    const bool ok = s < k.nks;
+    st[p] = src[ok ? (((t * k.nk + k.k0 + s) << 6) + l) : 0];
+  }
+}
+template <int D, int KK>
+__device__ __forceinline__ void tile_store(double* __restrict__ buf, const double (&st)[MassTile<D, KK>::PER]) {
+#pragma unroll
+  for (int p = 0; p < MassTile<D, KK>::PER; ++p) {
+    const int i = (int)threadIdx.x + p * 64 * TILE_WPB;
+    if (i < MassTile<D, KK>::CH) buf[i] = st[p];
+  }
+}
+
+// One pass of a contraction over tiles [T0, T0 + NT) of its output, K steps
+// 0 .. NKT in chunks of KC from the LDS window: acc[t] += A(step, T0 + t) b[step].
+// c: the round's index of the pass's first chunk; cb: the buffer holding it.
+template <int D, int KK, int NT, int NKT, int KC, int NB>
+__device__ __forceinline__ void tile_pass(const double* __restrict__ fin, const double* __restrict__ fout,
+                                          double (*buf)[MassTile<D, KK>::CH], int c, int& cb,
+                                          double (&st)[MassTile<D, KK>::PER], const double (&b)[NB], d4 (&acc)[NT],
+                                          int lane) {
+  using M = MF<double>;
+  constexpr int NCHK = (NKT + KC - 1) / KC;
+#pragma unroll
+  for (int ch = 0; ch < NCHK; ++ch) {
+    tile_fetch<D, KK>(fin, fout, c + ch + 1, st);  // the round's next chunk
+    const double* const a = buf[cb];
+    const int nks = NKT - ch * KC < KC ? NKT - ch * KC : KC;
+    double fr[2][NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) fr[0][t] = a[t * 64 + lane];
+#pragma unroll
+    for (int s = 0; s < KC; ++s) {
+      if (s < nks) {
+        if (s + 1 < nks) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) fr[(s + 1) & 1][t] = a[((s + 1) * NT + t) * 64 + lane];
+        }
+        MASS_SCHED_FENCE();
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = M::mma(fr[s & 1][t], b[ch * KC + s], acc[t]);
+        MASS_SCHED_FENCE();
+      }
+    }
+    tile_store<D, KK>(buf[cb ^ 1], st);
+    cb ^= 1;
+    __syncthreads();
+  }
+}
+
+template <int D, int KK, int MODE>
+__global__ __launch_bounds__(64 * TILE_WPB, 1) void k_mass_tiled(const double* __restrict__ x,
+                                                                 double* __restrict__ out, double* __restrict__ fs,
+                                                                 DevMesh mesh, const double* __restrict__ fin,
+                                                                 const double* __restrict__ fout,
+                                                                 const int* __restrict__ flag,
+                                                                 double* __restrict__ part) {
+  using C = Cfg<D, KK>;
+  using TT = MassTile<D, KK>;
+  static_assert(D == 3, "the streamed-table kernel serves the 3D orders only");
+  __shared__ double buf[2][TT::CH];
+  if (flag && *flag) return;  // uniform over the launch
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int nx = gridDim.x % 8 == 0 ? 8 : 1;
+  const int64_t xcd = blockIdx.x % nx;
+  const int64_t nw_all = (mesh.E + 15) / 16;
+  const int64_t lo = nw_all * xcd / nx, hi = nw_all * (xcd + 1) / nx;
+  const int64_t per_round = (int64_t)(gridDim.x / nx) * TILE_WPB;
+  const int64_t rounds = (hi - lo + per_round - 1) / per_round;
+  const int64_t first = lo + (int64_t)(blockIdx.x / nx) * TILE_WPB + (threadIdx.x >> 6);
+  const int64_t off = mesh.F * C::NF;
+  double* const trash = fs + 2 * mesh.F * C::NF;
+  double dot = 0.0;
+  double st[TT::PER];
+  tile_fetch<D, KK>(fin, fout, 0, st);  // the round's first chunk
+  tile_store<D, KK>(buf[0], st);
+  __syncthreads();
+  int cb = 0;  // the buffer holding the chunk about to be used
+  for (int64_t r = 0; r < rounds; ++r) {
+    const int64_t wave = first + r * per_round;
+    const bool live = wave < hi;
+    MassIdx ix;
+    MassData<D, KK> md;
+    mass_load_idx<D>(mesh, live ? wave : lo, g, c, ix);
+    mass_load_data<D, KK>(x, mesh, live ? wave : lo, g, c, ix, md);
+    const int64_t e = wave * 16 + c;
+    const bool valid = live && e < mesh.E;
+    const double sfac = MODE == 1 ? 0.5 / md.nf : md.nf;
+    const double sint = MODE == 1 ? 1.0 / md.si : md.si;
+    const bool fok = valid && g <= D && md.ix.fid >= 0;
+    double xh[C::NK];
+#pragma unroll
+    for (int kk = 0; kk < C::NK; ++kk) {
+      const bool ok = mass_is_facet<D, KK>(kk, g) ? fok : valid && mass_int_row<D, KK>(kk, g) < C::NINT;
+      xh[kk] = ok ? md.x[kk] * (mass_is_facet<D, KK>(kk, g) ? sfac : sint) : 0.0;
+    }
+    // ---- first contraction y = fin . xh, in two passes over its tiles
+    double y[C::NMT][4];
+    {
+      d4 acc[TT::H1];
+#pragma unroll
+      for (int t = 0; t < TT::H1; ++t) acc[t] = vzero<d4>();
+      tile_pass<D, KK, TT::H1, C::NK, TT::K1, C::NK>(fin, fout, buf, 0, cb, st, xh, acc, lane);
+#pragma unroll
+      for (int t = 0; t < TT::H1; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[t][i] = acc[t][i];
+    }
+    {
+      constexpr int NT = C::NMT - TT::H1;
+      d4 acc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = vzero<d4>();
+      tile_pass<D, KK, NT, C::NK, TT::K1, C::NK>(fin, fout, buf, TT::N1, cb, st, xh, acc, lane);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[TT::H1 + t][i] = acc[t][i];
+    }
+    // ---- component mixing (as in mass_compute) and the local x . y share;
+    // the geometry is read again here rather than held through the MFMAs
+    {
+      const double* Gr = mesh.geo + (live ? wave * 16 + c < mesh.E ? wave * 16 + c : 0 : lo * 16) * GEO_STRIDE;
+      load_J<D>(Gr, md.J);
+      md.det = Gr[GEO_DET];
+    }
+    double Gm[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int bb = 0; bb < D; ++bb) {
+        double s = 0;
+#pragma unroll
+        for (int r2 = 0; r2 < D; ++r2) s += md.J[r2][a] * md.J[r2][bb];
+        Gm[a][bb] = s;
+      }
+    double Gs[D][D];
+    const double sd = 1.0 / fabs(md.det);
+    if (MODE == 0) {
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) Gs[a][bb] = Gm[a][bb] * sd;
+    } else {
+      // G^-1 |det| = adj(G) / |det|  (det G = det^2)
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) {
+          const int a1 = (bb + 1) % 3, a2 = (bb + 2) % 3, b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+          Gs[a][bb] = (Gm[a1][b1] * Gm[a2][b2] - Gm[a1][b2] * Gm[a2][b1]) * sd;
+        }
+    }
+    double yb[C::NMQ];  // the mixed rows, by step of the second contraction
+#pragma unroll
+    for (int blk = 0; blk < C::NPK; ++blk) {
+      double t[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double s = 0;
+#pragma unroll
+        for (int bb = 0; bb < D; ++bb) {
+          const int rq = blk * D + bb;
+          s += Gs[a][bb] * y[rq / 4][rq % 4];
+        }
+        t[a] = s;
+      }
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        dot += y[(blk * D + a) / 4][(blk * D + a) % 4] * t[a];
+        yb[blk * D + a] = t[a];
+      }
+    }
+#pragma unroll
+    for (int rq = D * C::NPK; rq < C::NMQ; ++rq) yb[rq] = 0.0;
+    // ---- second contraction o = fout . yb, in two passes, stored per pass
+    double* const fsrow = fs + ((int64_t)md.ix.side * mesh.F + (md.ix.fid >= 0 ? md.ix.fid : 0)) * C::NF;
+    double* const irow = out + off + (valid ? e : 0) * C::NINT;
+    auto store = [&](const d4& ot, int jt) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int s = 4 * jt + i;  // register i of tile jt holds step s of this lane
+        if (s < C::NK)
+          mass_store<D, KK>(s, g, ot[i], i % 2 == 0 && i < 3 ? ot[i + 1] : 0.0, sfac, sint, fok, fsrow, valid,
+                            irow, trash);
+      }
+    };
+    {
+      d4 o[TT::H2];
+#pragma unroll
+      for (int t = 0; t < TT::H2; ++t) o[t] = vzero<d4>();
+      tile_pass<D, KK, TT::H2, C::NMQ, TT::K2, C::NMQ>(fin, fout, buf, 2 * TT::N1, cb, st, yb, o, lane);
+#pragma unroll
+      for (int t = 0; t < TT::H2; ++t) store(o[t], t);
+    }
+    {
+      constexpr int NT = C::NJT - TT::H2;
+      d4 o[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) o[t] = vzero<d4>();
+      tile_pass<D, KK, NT, C::NMQ, TT::K2, C::NMQ>(fin, fout, buf, 2 * TT::N1 + TT::N2, cb, st, yb, o, lane);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) store(o[t], TT::H2 + t);
+    }
+  }
+  if (part) {
+    dot = block_sum_waves<TILE_WPB>(dot);
+    if (threadIdx.x == 0) part[blockIdx.x] = dot;
+  }
+}
+
 // facet rows: r_F = slot(T) + slot(T'), lower element first (deterministic)
 template <int NF, int NFL>
 __global__ void k_assemble_flag(double* __restrict__ r, const double* __restrict__ slot, DevMesh mesh,
@@ -1132,8 +1421,22 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
       HOPU_LAUNCH((k_mass_lds<double, D, KK, 1>), dim3((unsigned)blocks), thr, lds_bytes, s, x, out, fs, mesh, fin,
                   fout, flag, part);
     return (int)blocks;
+  } else if constexpr (D == 3) {
+    // tables streamed through LDS by blocks of TILE_WPB waves (one block
+    // per CU); no FP32 form (the preconditioner runs in FP64)
+    const int64_t blocks = std::min<int64_t>((waves + TILE_WPB - 1) / TILE_WPB, MASS_BLOCKS);
+    const dim3 thr(64 * TILE_WPB);
+    if (mode == 0)
+      HOPU_LAUNCH((k_mass_tiled<D, KK, 0>), dim3((unsigned)blocks), thr, 0, s, x, out, fs, mesh, fin, fout, flag,
+                  part);
+    else
+      HOPU_LAUNCH((k_mass_tiled<D, KK, 1>), dim3((unsigned)blocks), thr, 0, s, x, out, fs, mesh, fin, fout, flag,
+                  part);
+    (void)sizeof(C);
+    (void)fin32;
+    (void)fout32;
+    return (int)blocks;
   } else {
-    // (no FP32 form: its tables would not fit in LDS either)
     const int64_t blocks = (waves + 3) / 4;
     if (mode == 0)
       HOPU_LAUNCH((k_mass<D, KK, 0>), dim3((unsigned)blocks), dim3(256), 0, s, x, out, fs, mesh, fin, fout, flag,

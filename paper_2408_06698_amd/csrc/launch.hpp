@@ -36,7 +36,13 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
 void launch_fs_assemble(hipStream_t s, double* v, const double* fs, int64_t nfl, const int* flag);
 template <int D, int KK>
 void launch_assemble(hipStream_t s, double* r, const double* slot, const DevMesh& mesh, const int* flag);
+// udual: the FP64 state (its facet DoFs give u.n); psi_n: the f64 MFMA
+// table of the facet polynomials in the point order of T's row map
 template <typename T, int D, int KK>
 void launch_vjp(hipStream_t s, const T* mu_u, const T* mu_mu, double* out, double* slot, const DevMesh& mesh,
-                const DevTables<T>& tb);
+                const DevTables<T>& tb, const double* udual, const double* psi_n);
+// the transpose-Jacobian kernel with split-BF16 contractions (as launch_elem_bf)
+template <int NS, int D, int KK>
+void launch_vjp_bf(hipStream_t s, const float* mu_u, const float* mu_mu, double* out, double* slot,
+                   const DevMesh& mesh, const DevTables<BfPack<NS>>& tb, const double* udual, const double* psi_n);
 }  // namespace hopu

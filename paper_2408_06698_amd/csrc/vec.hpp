@@ -5,7 +5,7 @@
 namespace hopu {
 enum { NPART = 1024 };
 enum { SC_RZ = 0, SC_ALPHA = 1, SC_BETA = 2, SC_TOL2 = 3, SC_BPB = 4, SC_RES = 5, SC_RZ_OLD = 6, SC_N = 8 };
-enum { OP_SET_TOL = 0, OP_SET_RZ = 1, OP_STORE = 4 };
+enum { OP_SET_TOL = 0, OP_SET_RZ = 1, OP_STORE = 4, OP_STORE_SQRT = 5 };
 void vec_dot(hipStream_t s, const double* a, const double* b, int64_t n, double* part, const int* flag);
 void vec_scalar(hipStream_t s, const double* part, int np, double* sc, int* flag, int op, double arg,
                 double* dst);

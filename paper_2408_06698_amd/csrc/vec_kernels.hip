@@ -45,7 +45,7 @@ __device__ double block_sum_fixed(const double* __restrict__ part, int np, doubl
 // Reduce partials in a fixed order and apply a PCG scalar operation.
 __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part, int np, double* sc, int* flag,
                                                 int op, double arg, double* dst) {
-  if (op != OP_SET_TOL && op != OP_STORE && flag && *flag) return;
+  if (op != OP_SET_TOL && op != OP_STORE && op != OP_STORE_SQRT && flag && *flag) return;
   __shared__ double sh[4];
   const double v0 = block_sum_fixed(part, np, sh);
   if (threadIdx.x != 0) return;
@@ -64,6 +64,9 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ part,
       break;
     case OP_STORE:
       *dst = v;
+      break;
+    case OP_STORE_SQRT:  // a norm from its squared partials
+      *dst = sqrt(fmax(v, 0.0));
       break;
     default:
       break;

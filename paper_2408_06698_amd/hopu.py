@@ -152,6 +152,12 @@ class Hopu:
               self.h)
         return lam0
 
+    def energy(self, u, out=None):
+        """1/2 u.Mu as a 0-dim device tensor (no host synchronisation)."""
+        out = torch.zeros((), dtype=torch.float64, device=self.device) if out is None else out
+        check(L.lib().hopu_energy(self.h, _ptr(_dev(u, self.n_dof)), _ptr(_dev(out, 1, what="energy"))), self.h)
+        return out
+
     def diagnostics(self, u):
         e, dv, ds = C.c_double(), C.c_double(), C.c_double()
         check(L.lib().hopu_diagnostics(self.h, _ptr(_dev(u, self.n_dof)), C.byref(e), C.byref(dv), C.byref(ds)), self.h)
@@ -219,15 +225,17 @@ class SubstepChain(torch.autograd.Function):
 
 
 class MassEnergy(torch.autograd.Function):
-    """E(u) = 1/2 u.Mu with gradient M u."""
+    """E(u) = 1/2 u.Mu (the library's energy) with gradient M u (the
+    library's mass apply), scaled by the incoming gradient."""
 
     @staticmethod
     def forward(ctx, u, space):
-        Mu = space.mass_apply(u.detach().contiguous())
-        ctx.save_for_backward(Mu)
-        return 0.5 * torch.dot(u.detach(), Mu)
+        u = u.detach().contiguous()
+        ctx.space = space
+        ctx.save_for_backward(u)
+        return space.energy(u)
 
     @staticmethod
     def backward(ctx, g):
-        (Mu,) = ctx.saved_tensors
-        return g * Mu, None
+        (u,) = ctx.saved_tensors
+        return g * ctx.space.mass_apply(u), None

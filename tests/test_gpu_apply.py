@@ -7,7 +7,7 @@ import torch
 
 from synth.mesh import two_element_mesh
 from oracle import space as S, operator as O
-from gpu_util import case, gpu_space, dev, host, rel_dual, rel_primal
+from gpu_util import case, gpu_space, dev, host, rel_dual, rel_primal, check_dual, check_mixed, check_primal
 
 pytestmark = pytest.mark.gpu
 
@@ -35,9 +35,7 @@ def test_apply_fp64_all_l(cfg, n, k):
         h.set_upwind(l)
         r = host(h.apply(u))
         ref = O.residual(sp, x, l)
-        e = rel_dual(sp, r, ref)
-        print(f"cfg={cfg} n={n} k={k} l={l} rel={e:.2e}")
-        assert e <= 1e-12, (l, e)
+        check_dual(sp, r, ref, 1e-12, f"fp64 cfg={cfg} n={n} k={k} l={l}")
 
 
 @pytest.mark.parametrize("cfg,n,k", [(1, (5, 7), 3), (2, (4, 3, 3), 3), (3, (3, 5, 3), 2)])
@@ -49,7 +47,7 @@ def test_apply_term_subsets(cfg, n, k):
     for terms in (VOL, CEN, UP, VOL | CEN, CEN | UP):
         r = host(h.apply(u, terms=terms))
         ref = O.residual(sp, x, k - 1, terms)
-        assert rel_dual(sp, r, ref) <= 1e-12, terms
+        check_dual(sp, r, ref, 1e-12, f"terms={terms}")
 
 
 def test_apply_per_facet_l():
@@ -60,7 +58,7 @@ def test_apply_per_facet_l():
     h.set_upwind(0, lt)
     r = host(h.apply(dev(x)))
     ref = O.residual(sp, x, lf.astype(np.int64))
-    assert rel_dual(sp, r, ref) <= 1e-12
+    check_dual(sp, r, ref, 1e-12, "per-facet l")
 
 
 @pytest.mark.parametrize("dim,k", [(2, 1), (2, 3), (3, 1), (3, 2), (3, 4)])
@@ -89,6 +87,15 @@ def test_apply_is_deterministic(cfg, n, k, prec):
     assert np.array_equal(a, b)
 
 
+# The reduced-precision forms are held to the 1e-6 target in 3D.  The 2D
+# k = 2 workload misses it: there the volume and central terms are each
+# about 8 times the residual (M^-1 norms 25.6 and 25.4 against 3.2) and
+# cancel, so the FP32 rounding of each (2.7e-7 of its own size) appears
+# 8-fold in the sum; its measured error (2.3e-6 to 2.5e-6) is held to 3e-6.
+def mixed_tol(cfg):
+    return 3e-6 if cfg == 1 else 1e-6
+
+
 @pytest.mark.parametrize("cfg,n,k", [(1, (16, 16), 2), (2, (4, 3, 3), 3), (3, (3, 5, 3), 4), (3, (3, 3, 4), 5)])
 def test_apply_fp32_mfma(cfg, n, k):
     mesh, sp, x, c = case(cfg, n, k, noise=1e-3)
@@ -96,9 +103,7 @@ def test_apply_fp32_mfma(cfg, n, k):
     h.set_upwind(k - 1)
     r = host(h.apply(dev(x), prec=1))
     ref = O.residual(sp, x, k - 1)
-    e = rel_dual(sp, r, ref)
-    print(f"fp32 cfg={cfg} k={k} rel={e:.2e}")
-    assert e <= 1e-5
+    check_mixed(sp, r, ref, mixed_tol(cfg), f"fp32 cfg={cfg} k={k}")
 
 
 # Split-BF16 bounds.  Truncating an FP32 value to its leading 8 bits leaves a
@@ -110,8 +115,8 @@ def test_apply_fp32_mfma(cfg, n, k):
 # these meshes the FP32-MFMA residual error is at most about 42 times its
 # unit 2^-24 (2.5e-6 in 2D at k = 2), the amplification of the sums over
 # quadrature points and modes; the same factor on 2^-14 gives 2.6e-3, the
-# hi/lo bound below.
-BF16_TOL = {2: 3e-3, 3: 1e-5}
+# hi/lo bound below (hi/lo cannot meet the 1e-6 target by construction).
+BF16_TOL = {2: 3e-3, 3: 1e-6}
 
 
 @pytest.mark.parametrize("cfg,n,k", [(1, (16, 16), 2), (2, (4, 3, 3), 3), (3, (3, 5, 3), 4), (3, (3, 3, 4), 5)])
@@ -122,11 +127,8 @@ def test_apply_bf16_split(cfg, n, k, prec):
     h.set_upwind(k - 1)
     r = host(h.apply(dev(x), prec=prec))
     ref = O.residual(sp, x, k - 1)
-    e = rel_dual(sp, r, ref)
-    r32 = host(h.apply(dev(x), prec=1))
-    e32 = rel_dual(sp, r32, ref)
-    print(f"bf16x{prec} cfg={cfg} k={k} rel={e:.2e} (fp32-mfma {e32:.2e})")
-    assert e <= BF16_TOL[prec]
+    tol = mixed_tol(cfg) if prec == 3 else BF16_TOL[2]
+    check_mixed(sp, r, ref, tol, f"bf16x{prec} cfg={cfg} k={k}")
 
 
 @pytest.mark.parametrize("terms", [VOL, CEN, UP, CEN | UP])
@@ -137,9 +139,7 @@ def test_apply_bf16_term_subsets(terms):
     ref = O.residual(sp, x, 2, terms=terms)
     for prec in (2, 3):
         r = host(h.apply(dev(x), terms=terms, prec=prec))
-        e = rel_dual(sp, r, ref)
-        print(f"bf16x{prec} terms={terms} rel={e:.2e}")
-        assert e <= BF16_TOL[prec], (prec, terms, e)
+        check_mixed(sp, r, ref, BF16_TOL[prec], f"bf16x{prec} terms={terms}")
 
 
 @pytest.mark.parametrize("cfg,n,k", [(1, (5, 7), 3), (3, (3, 5, 3), 4), (4, (3, 3, 3), 2), (3, (3, 3, 4), 5)])
@@ -148,7 +148,7 @@ def test_mass_apply(cfg, n, k):
     h = gpu_space(mesh, k)
     y = host(h.mass_apply(dev(x)))
     ref = O.mass_apply(sp, x)
-    assert rel_dual(sp, y, ref) <= 1e-13
+    check_dual(sp, y, ref, 1e-13, f"mass cfg={cfg} k={k}")
 
 
 def _odd_view(a):

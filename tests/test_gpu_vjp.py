@@ -8,7 +8,7 @@ import torch
 import synth
 from synth.configs import fd_directions
 from oracle import operator as O
-from gpu_util import case, gpu_space, dev, host, rel_dual, rel_primal
+from gpu_util import case, gpu_space, dev, host, rel_dual, rel_primal, check_dual, check_mixed
 
 pytestmark = pytest.mark.gpu
 
@@ -23,9 +23,7 @@ def test_vjp_matches_oracle(cfg, n, k):
         h.set_upwind(l)
         g = host(h.vjp(dev(x), dev(mu)))
         ref = O.vjp(sp, x, mu, l)
-        e = rel_dual(sp, g, ref)
-        print(f"vjp cfg={cfg} k={k} l={l} rel={e:.2e}")
-        assert e <= 1e-12
+        check_dual(sp, g, ref, 1e-12, f"vjp cfg={cfg} k={k} l={l}")
 
 
 @pytest.mark.parametrize("cfg,n,k", [(1, (6, 5), 2), (2, (4, 3, 3), 3), (3, (3, 3, 4), 5)])
@@ -39,24 +37,58 @@ def test_vjp_fp32_matches_oracle(cfg, n, k):
     h.set_upwind(k - 1)
     g = host(h.vjp(dev(x), dev(mu), prec=1))
     ref = O.vjp(sp, x, mu, k - 1)
-    e = rel_dual(sp, g, ref)
-    print(f"vjp fp32 cfg={cfg} k={k} rel={e:.2e}")
-    assert e <= 1e-5
+    # 1e-6 in 3D; the 2D k = 2 case carries the cancellation of the forward
+    # apply (volume and central parts each 8 times the sum): 3e-6
+    check_mixed(sp, g, ref, 3e-6 if cfg == 1 else 1e-6, f"vjp fp32 cfg={cfg} k={k}")
 
 
-def test_vjp_bf16_unsupported():
-    from paper_2408_06698_amd import HopuError
-    mesh, sp, x, c = case(2, (4, 3, 3), 3, noise=1e-3)
+def test_vjp_at_zero_normal_velocity():
+    """The shear field (p(y), 0, q(y)) on the walled, graded, jittered mesh
+    has u.n = 0 on every facet whose normal is along y (and no jumps): the
+    transpose Jacobian there (reading sgn(0) = 0) matches the oracle."""
+    from synth import fields
+    mesh, sp, _, c = case(3, (3, 5, 3), 3, noise=0.0)
+    x = sp.interpolate(fields.shear_field([0.2, 1.0, -0.8], [0.1, -0.5, 0.3]))
+    mu = np.random.default_rng(12).standard_normal(sp.n_dof)
     h = gpu_space(mesh, 3)
-    u = dev(x)
-    for prec in (2, 3):
-        with pytest.raises(HopuError, match="adjoint"):
-            h.vjp(u, u, prec=prec)
-        with pytest.raises(HopuError, match="adjoint"):
-            h.substeps_vjp(u, 1e-3, 2, u, ckpt_every=1, prec=prec)
+    for l in (-1, 2):
+        h.set_upwind(l)
+        g = host(h.vjp(dev(x), dev(mu)))
+        check_dual(sp, g, O.vjp(sp, x, mu, l), 1e-12, f"vjp shear l={l}")
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+@pytest.mark.parametrize("cfg,n,k", [(2, (4, 3, 3), 3), (3, (3, 5, 3), 4), (3, (3, 3, 4), 5)])
+@pytest.mark.parametrize("prec", [2, 3])
+def test_vjp_bf16_split_matches_oracle(cfg, n, k, prec):
+    """Split-BF16 transpose Jacobian (the forward kernel's split contractions
+    plus split copies of its two volume tables) against the FP64 oracle:
+    hi/mid/lo carries the FP32 operands exactly and is held to 1e-6; hi/lo
+    to its apply bound 3e-3."""
+    mesh, sp, x, c = case(cfg, n, k, noise=1e-2)
+    mu = np.random.default_rng(11).standard_normal(sp.n_dof)
+    h = gpu_space(mesh, k)
+    h.set_upwind(k - 1)
+    ref = O.vjp(sp, x, mu, k - 1)
+    g = host(h.vjp(dev(x), dev(mu), prec=prec))
+    check_mixed(sp, g, ref, 1e-6 if prec == 3 else 3e-3, f"vjp bf16x{prec} cfg={cfg} k={k}")
+
+
+def test_chain_vjp_bf16x3():
+    """The checkpointed reverse chain with hi/mid/lo contractions on the
+    walled, graded mesh at k = 4 against the oracle's chain adjoint."""
+    mesh, sp, x, c = case(3, (3, 4, 3), 4, noise=1e-2)
+    h = gpu_space(mesh, 4)
+    h.set_upwind(3)
+    h.set_solver(rtol=1e-13, max_it=2000)
+    dt, n = 1e-3, 3
+    xN = O.substeps(sp, x, dt, n, 3)
+    lamN = O.mass_apply(sp, xN)
+    ref = O.chain_vjp(sp, x, dt, n, 3, lamN)
+    g = host(h.substeps_vjp(dev(x), dt, n, dev(lamN), ckpt_every=2, prec=3))
+    check_mixed(sp, g, ref, 1e-6, "chain vjp bf16x3 (k = 4)")
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)])
 def test_vjp_homogeneity_and_fd(prec, tol):
     """J_r(u) u = 2 r(u) (r is positively homogeneous of degree 2), and the
     dot-product test <J_r delta, mu> = <delta, J_r^T mu> with central FD."""
@@ -92,9 +124,7 @@ def test_chain_vjp_matches_oracle():
     # FP32-MFMA reverse chain: lam_0 = lam_N + O(dt) terms, so its error
     # relative to lam_0 is below that of one vjp
     gp = host(h.substeps_vjp(dev(x), dt, n, dev(lamN), ckpt_every=2, prec=1))
-    e = rel_dual(sp, gp, ref)
-    print(f"chain vjp fp32 rel={e:.2e}")
-    assert e <= 1e-5
+    check_mixed(sp, gp, ref, 3e-6, "chain vjp fp32 (2D k = 2)")
 
 
 def test_checkpointing_is_bitwise():
@@ -139,25 +169,38 @@ def test_adjoint_fd_curl_workload():
     assert torch.equal(x.grad, lam0)
     nrm0 = float(torch.sqrt(torch.dot(u0, h.mass_apply(u0))))
     dirs = fd_directions(4, cfg["fd_dirs"], h.n_dof)
-    hh = cfg["fd_h"]
     gnorm = float(torch.sqrt(torch.dot(lam0, h.mass_solve(lam0.clone(), rtol=1e-14, max_it=4000)[0])))
-    errs, nerrs = [], []
-    for i in range(cfg["fd_dirs"]):
-        d = dev(dirs[i])
-        d *= nrm0 / float(torch.sqrt(torch.dot(d, h.mass_apply(d))))
-        up, um = final(u0 + hh * d), final(u0 - hh * d)
-        # (L+ - L-)/2h written as 1/2 (u+ - u-)^T M (u+ + u-)/2h: a random
-        # direction is nearly M-orthogonal to the gradient, and subtracting
-        # the two O(1e2) losses would cancel most significant digits
-        fd = 0.5 * float(torch.dot(up - um, h.mass_apply(up + um))) / (2 * hh)
-        ad = float(torch.dot(lam0, d))
-        errs.append(abs(fd - ad) / abs(fd))
-        nerrs.append(abs(fd - ad) / (gnorm * nrm0))
-    errs, nerrs = np.array(errs), np.array(nerrs)
-    print(f"adjoint FD over {cfg['fd_dirs']} directions: |fd-ad|/(|grad L| |delta|) max {nerrs.max():.2e}; "
-          f"|fd-ad|/|fd| max {errs.max():.2e} median {np.median(errs):.2e}")
-    # random directions are nearly M-orthogonal to the gradient (cos ~ 1e-4),
-    # so the per-direction ratio magnifies the O(eps/h) FD noise; the
-    # gradient-normalised error is the sharp test
+
+    def fd_errors(hh):
+        errs, nerrs = [], []
+        for i in range(cfg["fd_dirs"]):
+            d = dev(dirs[i])
+            d *= nrm0 / float(torch.sqrt(torch.dot(d, h.mass_apply(d))))
+            up, um = final(u0 + hh * d), final(u0 - hh * d)
+            # (L+ - L-)/2h written as 1/2 (u+ - u-)^T M (u+ + u-)/2h: a random
+            # direction is nearly M-orthogonal to the gradient, and subtracting
+            # the two O(1e2) losses would cancel most significant digits
+            fd = 0.5 * float(torch.dot(up - um, h.mass_apply(up + um))) / (2 * hh)
+            ad = float(torch.dot(lam0, d))
+            errs.append(abs(fd - ad) / abs(fd))
+            nerrs.append(abs(fd - ad) / (gnorm * nrm0))
+        return np.array(errs), np.array(nerrs)
+
+    # h = 1e-6 (the workload's step): the per-direction ratio |fd-ad|/|fd|
+    # is rounding noise magnified by the direction's near-orthogonality to
+    # the gradient (cos 3e-4 .. 1e-2); the oracle's own h-sweep on this
+    # recipe (4^3 x 6 tets, exact solves) shows the noise growing as 1/h
+    # below h = 1e-5 (2e-8 at 1e-6, 1e-7 at 1e-7, 4e-6 at 1e-8) and the
+    # truncation error growing as h^2 above it, with the minimum (1e-9 ..
+    # 1e-10) at h = 1e-5.  So: every direction at h = 1e-5 within 1e-7;
+    # at h = 1e-6 the gradient-normalised error and the median.
+    errs, nerrs = fd_errors(cfg["fd_h"])
+    errs5, nerrs5 = fd_errors(1e-5)
+    print(f"adjoint FD, {cfg['fd_dirs']} directions, h = 1e-6: |fd-ad|/|fd| " +
+          " ".join(f"{e:.1e}" for e in errs))
+    print(f"adjoint FD, h = 1e-6: max {errs.max():.2e} median {np.median(errs):.2e}; "
+          f"|fd-ad|/(|grad L| |delta|) max {nerrs.max():.2e}")
+    print(f"adjoint FD, h = 1e-5: |fd-ad|/|fd| max {errs5.max():.2e} median {np.median(errs5):.2e}")
+    assert errs5.max() <= 1e-7
     assert nerrs.max() <= 1e-10
     assert np.median(errs) <= 1e-7

@@ -132,7 +132,8 @@ def _bf16_terms_to_f32(bits):
 
 @pytest.mark.parametrize("dim,k", [(2, 2), (3, 3), (3, 5)])
 def test_host_bf16_split_tables(dim, k):
-    """The split-BF16 copies of the FP32-layout fragment tables: four steps of
+    """The split-BF16 copies of the FP32-layout fragment tables (of the
+    convection kernel and of the transpose-Jacobian kernel): four steps of
     a lane per fragment, terms that are successive 8-bit truncations of the
     FP32 value (hi + mid + lo equal to it, hi + lo within 2^-15), zero past
     the last step."""
@@ -141,7 +142,9 @@ def test_host_bf16_split_tables(dim, k):
     nqf = L.lib().hopu_host_sizes(dim, k, 5)
     NQVT, NAT, NQFT = -(-nqv // 16), -(-nP // 16), -(-nqf // 16)
     NPK = -(-nP // 4)
-    cases = [(8, 10, 3, NQVT, 4, dim * NAT), (8, 9, 2, NQVT, 4, dim * NAT), (11, 12, 3, (dim + 1) * NQFT, NPK, 1)]
+    cases = [(8, 10, 3, NQVT, 4, dim * NAT), (8, 9, 2, NQVT, 4, dim * NAT), (11, 12, 3, (dim + 1) * NQFT, NPK, 1),
+             # the transpose-Jacobian kernel's volume tables
+             (13, 15, 3, NQVT * dim, NPK, 1), (14, 16, 3, NQVT, 4, NAT)]
     for w32, wbf, ns, outer, steps, inner in cases:
         t32 = _table(dim, k, w32).astype(np.float32).reshape(outer, steps, inner, 64)
         ng = -(-steps // 4)

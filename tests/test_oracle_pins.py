@@ -285,7 +285,7 @@ def walled_parabola_case(dim, k, jitter=0.05):
         return np.stack(comps, -1)
 
     area = lengths[0] * (lengths[2] if dim == 3 else 1.0)
-    return sp, sp.interpolate(f), math.sqrt(area / 3.0)
+    return sp, sp.interpolate(f), math.sqrt(area / 3.0), mesh
 
 
 @pytest.mark.parametrize("dim,k", [(2, 2), (2, 3), (3, 2), (3, 3)])
@@ -293,6 +293,21 @@ def test_divergence_l2_closed_form(dim, k):
     """||div u_h||_L2 (the substep diagnostic, with div u|_T = div^ u^/det J)
     equals the closed form for a parabola in V_h on a graded, jittered,
     walled mesh; the same field scaled by 3 gives 3 times the value."""
-    sp, x, want = walled_parabola_case(dim, k)
+    sp, x, want, _ = walled_parabola_case(dim, k)
     assert O.divergence_l2(sp, x) == pytest.approx(want, rel=1e-13)
     assert O.divergence_l2(sp, 3.0 * x) == pytest.approx(3.0 * want, rel=1e-13)
+
+
+def test_interpolation_restricted_to_elements():
+    """Space.interpolate(..., elems=E') gives the full interpolant's DoFs on
+    the elements E' (their facets and interiors) and zero elsewhere (the
+    full-size tests use it to build inputs on a patch)."""
+    m, f, c = synth.make_config(3, n_override=(3, 4, 3))
+    sp = S.Space(m.elem_vid, m.elem_xyz, 3)
+    x = sp.interpolate(f, nq1d=5)
+    el = np.array([3, 17, 40, 41])
+    xr = sp.interpolate(f, nq1d=5, elems=el)
+    g = np.unique(sp.gdof[el][sp.gdof[el] >= 0])
+    assert np.abs(xr[g] - x[g]).max() <= 1e-14 * np.abs(x).max()
+    rest = np.setdiff1d(np.arange(sp.n_dof), g)
+    assert not xr[rest].any()
