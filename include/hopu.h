@@ -181,7 +181,12 @@ hopu_status hopu_mfma_f64_rate(int blocks_per_cu, double* tflops);
 hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_steps,
                           hopu_precision prec, double* diag_dev);
 
-/* out = J_r(u)^T mu (dev [n_dof] each).  Asynchronous. */
+/* out = J_r(u)^T mu (dev [n_dof] each), the derivative of the residual of
+ * eq. (hopudefinition) with respect to the state, transposed.  |u.n| is not
+ * differentiable at 0: its derivative is taken as sgn(u.n) with sgn(0) = 0,
+ * u.n within 1e-8 |<u>| of zero (rounding noise of a field tangential to
+ * the facet) counting as zero.  The reduced forms evaluate u.n for that
+ * decision in FP64 from the state's facet DoFs.  Asynchronous. */
 hopu_status hopu_convection_vjp(hopu_ctx ctx, const double* u, const double* mu,
                                 double* out, hopu_precision prec);
 

@@ -9,12 +9,15 @@
 // Batches, tables and fragment layouts are those of the forward kernel;
 // NS > 0 (T = float) runs the contractions in split BF16 as the forward
 // kernel does (see mma_bf), with two more split tables (vol_dV, vol_VT).
-// u.n at the facet points is computed in FP64 in every form, from the
-// facet DoFs of the FP64 state (u.n_F = sum_j x_Fj psi_j on the facet, by
-// one f64 MFMA per group of four DoFs): sgn(u.n) is a discontinuous
+// In the reduced forms u.n at the facet points is computed in FP64 from
+// the facet DoFs of the FP64 state (u.n_F = sum_j x_Fj psi_j on the facet,
+// by one f64 MFMA per group of four DoFs): sgn(u.n) is a discontinuous
 // function of the state, and where |u.n| is below the reduced forms'
 // rounding the traces' u.n would flip it against the FP64 result, an O(1)
-// change of the facet rows there.
+// change of the facet rows there.  The FP64 form takes u.n from its traces,
+// as the residual does.
+#include <type_traits>
+
 #include "bf16split.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -363,11 +366,15 @@ __global__ __launch_bounds__(64) void k_vjp(const T* __restrict__ mu_m, const T*
           }
         }
       }
-      // u.n at this tile's points (register i: the point of this lane's row i)
+      // reduced forms: u.n at this tile's points from the facet DoFs
+      // (register i: the point of this lane's row i)
+      constexpr bool UN_DOF = !std::is_same_v<T, double>;
       d4 un4 = vz<d4>();
+      if constexpr (UN_DOF) {
 #pragma unroll
-      for (int jk = 0; jk < C::NFK; ++jk)
-        un4 = VM<double>::mma(psi_n[(qt * C::NFK + jk) * 64 + lane], xF[jk], un4);
+        for (int jk = 0; jk < C::NFK; ++jk)
+          un4 = VM<double>::mma(psi_n[(qt * C::NFK + jk) * 64 + lane], xF[jk], un4);
+      }
       T h[D][4], aw[D][4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -386,7 +393,13 @@ __global__ __launch_bounds__(64) void k_vjp(const T* __restrict__ mu_m, const T*
           }
           uo[a] = s1 * idet; un[a] = s2 * idetn; mo2[a] = s3 * idet; mn2[a] = s4 * idetn;
         }
-        const double unn = un4[i];
+        double unn = 0;
+        if constexpr (UN_DOF) {
+          unn = un4[i];
+        } else {
+#pragma unroll
+          for (int a = 0; a < D; ++a) unn += 0.5 * (uo[a] + un[a]) * nrm[a];
+        }
         double s_avg = 0, s_up = 0, jm[D], jmp[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -396,7 +409,13 @@ __global__ __launch_bounds__(64) void k_vjp(const T* __restrict__ mu_m, const T*
           s_avg += 0.5 * (uo[a] + un[a]) * jm[a];
           s_up += jup * jmp[a];
         }
-        const double sg = unn > 0 ? 1.0 : (unn < 0 ? -1.0 : 0.0);
+        // sgn(0) := 0, u.n within 1e-8 |<u>| of zero counting as zero (a
+        // field tangential to the facet gives u.n as rounding noise; two
+        // FP64 evaluations of u.n differ by up to about 1e-11 |<u>|)
+        double aa = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) aa += 0.25 * (uo[a] + un[a]) * (uo[a] + un[a]);
+        const double sg = fabs(unn) <= 1e-8 * sqrt(aa) ? 0.0 : (unn > 0 ? 1.0 : -1.0);
         const double s = s_avg + 0.5 * sg * s_up;
         const double hu = 0.5 * fabs(unn);
         double gg[D];
