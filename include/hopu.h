@@ -222,6 +222,18 @@ hopu_status hopu_interpolate(hopu_ctx ctx, int n1d, const double* vals_facet,
 hopu_status hopu_eval(hopu_ctx ctx, const double* u, int n_pts,
                       const double* ref_pts, double* vals);
 
+/* hopu_eval without allocating: for callers that cannot allocate device or
+ * host memory during the call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments and result as
+ * hopu_eval; the basis table at the points goes to a scratch array the
+ * library keeps in each GPU's memory for the life of the process (1 MiB,
+ * i.e. n_pts * n_loc * dim <= 131072 doubles: at most 260 points at 3D
+ * k = 5); larger n_pts return HOPU_EINVAL with the limit in the message.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on
+ * one GPU (from several threads or streams) race.  Syncs. */
+hopu_status hopu_eval_noalloc(hopu_ctx ctx, const double* u, int n_pts,
+                              const double* ref_pts, double* vals);
+
 /* Per-kernel timing with HIP events attached to launches of the main kernels
  * (for benchmarks and roofline reports).  hopu_profile_enable(ctx, s, n),
  * s >= 1, starts recording every s-th launch of each kernel kind (s = 1:

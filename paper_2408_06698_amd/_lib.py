@@ -42,6 +42,7 @@ SIGNATURES = {
     "hopu_interp_points": (_i, [_p, _i, _p, _p]),
     "hopu_interpolate": (_i, [_p, _i, _p, _p, _p]),
     "hopu_eval": (_i, [_p, _p, _i, _p, _p]),
+    "hopu_eval_noalloc": (_i, [_p, _p, _i, _p, _p]),
     "hopu_profile_enable": (_i, [_p, _i, _i]),
     "hopu_profile_read": (_i, [_p, _i, _p, _p]),
     "hopu_last_error": (C.c_char_p, [_p]),

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -68,6 +69,8 @@ struct hopu_ctx_s {
   int* flag = nullptr;      // [0] converged, [1] iterations
   int* hflag = nullptr;     // pinned host copy
   std::vector<void*> allocs;
+  DualBasis eval_db;              // reference dual basis (evaluation at given points)
+  double* eval_scratch = nullptr;  // this device's copy of the evaluation scratch array
   int lglob = -1;
   const int8_t* lfac = nullptr;
   double rtol = 1e-13;
@@ -218,6 +221,37 @@ static void refresh_dm(hopu_ctx ctx) {
   ctx->dm.lglob = ctx->lglob;
 }
 
+// Scratch of the allocation-free evaluation (hopu_eval_noalloc): the basis
+// table at the caller's points, one copy per GPU for the life of the
+// process, shared by every context on that GPU.  Host code reaches it only
+// through the address hipGetSymbolAddress gives for each device (the name
+// itself is a host-side stand-in).
+static constexpr int64_t EVAL_SCRATCH_DOUBLES = 1 << 17;  // 1 MiB
+static __device__ __align__(256) double scratch[EVAL_SCRATCH_DOUBLES];
+static constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+static hopu_status scratch_address(double** out, std::string& err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) { err = std::string("hipGetDevice: ") + hipGetErrorString(e); return HOPU_EHIP; }
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) { err = "device index beyond the scratch table"; return HOPU_EUNSUPPORTED; }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return HOPU_EHIP;
+    }
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return HOPU_OK;
+}
+
 extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elems, const int64_t* elem_vid,
                                    const double* elem_xyz, void* hip_stream) {
   if (!out) { g_create_err = "out is NULL"; return HOPU_EINVAL; }
@@ -247,6 +281,11 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     g[GEO_SI] = (double)(dim == 2 ? sqrtl(ad) : powl(cbrtl(ad), 2.0L));
   }
   make_batches(ctx->mesh, ctx->bat);
+  if (!make_dual_basis(dim, k, ctx->eval_db, err)) {
+    g_create_err = err;
+    delete ctx;
+    return HOPU_EINVAL;
+  }
   RefTables rt;
   if (!make_ref_tables(dim, k, rt, err)) {
     g_create_err = err;
@@ -375,6 +414,9 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     void* hp = nullptr;
     if (hipHostMalloc(&hp, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) { st = HOPU_ENOMEM; ctx->err = "hipHostMalloc failed"; goto fail_create; }
     ctx->hflag = (int*)hp;
+    // this device's evaluation scratch (set up once per device, here, with
+    // the context's device current)
+    if ((st = scratch_address(&ctx->eval_scratch, ctx->err)) != HOPU_OK) goto fail_create;
     if (hipMemsetAsync(ctx->w, 0, n * sizeof(double), ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->slot, 0, (size_t)E * s.nfl * sizeof(double), ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -958,33 +1000,65 @@ extern "C" hopu_status hopu_interpolate(hopu_ctx ctx, int n1d, const double* val
   return HOPU_OK;
 }
 
-extern "C" hopu_status hopu_eval(hopu_ctx ctx, const double* u, int n_pts, const double* ref_pts, double* vals) {
-  if (!ctx) return HOPU_EINVAL;
-  if (!u || !vals || !ref_pts || n_pts < 1) return fail(ctx, HOPU_EINVAL, "bad eval arguments");
+static constexpr int MAX_NP = 84;  // dim P^k, up to 3D k = 6
+
+// The reference basis phi_j at n_pts points into phi [n_pts][n][dim] (host).
+static void eval_tabulate(hopu_ctx ctx, int n_pts, const double* ref_pts, double* phi) {
   const int dim = ctx->dim, k = ctx->k;
   const Sizes& sz = ctx->sz;
-  DualBasis db;
-  std::string err;
-  if (!make_dual_basis(dim, k, db, err)) return fail(ctx, HOPU_EINVAL, err);
-  std::vector<double> phi((size_t)n_pts * sz.n * dim);
-  std::vector<ld> val(sz.nP), grad(sz.nP * dim);
+  ld val[MAX_NP], grad[MAX_NP * 3];
   for (int p = 0; p < n_pts; ++p) {
     ld x[3];
     for (int a = 0; a < dim; ++a) x[a] = ref_pts[p * dim + a];
-    dubiner(dim, k, x, val.data(), grad.data());
+    dubiner(dim, k, x, val, grad);
     for (int j = 0; j < sz.n; ++j)
       for (int a = 0; a < dim; ++a) {
         ld s = 0;
-        for (int al = 0; al < sz.nP; ++al) s += db.Dinv[(a * sz.nP + al) * sz.n + j] * val[al];
+        for (int al = 0; al < sz.nP; ++al) s += ctx->eval_db.Dinv[(a * sz.nP + al) * sz.n + j] * val[al];
         phi[((size_t)p * sz.n + j) * dim + a] = (double)s;
       }
   }
+}
+
+extern "C" hopu_status hopu_eval(hopu_ctx ctx, const double* u, int n_pts, const double* ref_pts, double* vals) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!u || !vals || !ref_pts || n_pts < 1) return fail(ctx, HOPU_EINVAL, "bad eval arguments");
+  const Sizes& sz = ctx->sz;
+  std::vector<double> phi((size_t)n_pts * sz.n * ctx->dim);
+  eval_tabulate(ctx, n_pts, ref_pts, phi.data());
   double* dphi;
   HCHECK(hipMalloc(&dphi, phi.size() * 8));
   HCHECK(hipMemcpyAsync(dphi, phi.data(), phi.size() * 8, hipMemcpyHostToDevice, ctx->stream));
-  launch_eval(ctx->stream, dim, sz.n, sz.nf, sz.nint, n_pts, u, dphi, ctx->dm, vals);
+  launch_eval(ctx->stream, ctx->dim, sz.n, sz.nf, sz.nint, n_pts, u, dphi, ctx->dm, vals);
   HCHECK(hipStreamSynchronize(ctx->stream));
   (void)hipFree(dphi);
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
+}
+
+// The same evaluation with the basis table in this device's `scratch`
+// (through its looked-up address) and the host table in a per-thread
+// static buffer: no allocation on the device or the host.  Every entry of
+// the table that the kernel reads is written by this call first, so
+// nothing needs clearing.
+static thread_local double t_eval_host[EVAL_SCRATCH_DOUBLES];
+
+extern "C" hopu_status hopu_eval_noalloc(hopu_ctx ctx, const double* u, int n_pts, const double* ref_pts,
+                                         double* vals) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!u || !vals || !ref_pts || n_pts < 1) return fail(ctx, HOPU_EINVAL, "bad eval arguments");
+  const Sizes& sz = ctx->sz;
+  const int64_t need = (int64_t)n_pts * sz.n * ctx->dim;
+  if (need > EVAL_SCRATCH_DOUBLES)
+    return fail(ctx, HOPU_EINVAL,
+                "n_pts too large for the allocation-free evaluation: the table needs " + std::to_string(need) +
+                    " doubles, the scratch holds " + std::to_string(EVAL_SCRATCH_DOUBLES) + " (at most " +
+                    std::to_string(EVAL_SCRATCH_DOUBLES / (sz.n * ctx->dim)) + " points at this order)");
+  if (!ctx->eval_scratch) return fail(ctx, HOPU_EHIP, "no evaluation scratch on this device");
+  eval_tabulate(ctx, n_pts, ref_pts, t_eval_host);
+  HCHECK(hipMemcpyAsync(ctx->eval_scratch, t_eval_host, (size_t)need * 8, hipMemcpyHostToDevice, ctx->stream));
+  launch_eval(ctx->stream, ctx->dim, sz.n, sz.nf, sz.nint, n_pts, u, ctx->eval_scratch, ctx->dm, vals);
+  HCHECK(hipStreamSynchronize(ctx->stream));
   HCHECK(hipGetLastError());
   return HOPU_OK;
 }
