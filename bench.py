@@ -8,15 +8,21 @@ seeded turbulent-like field (random Fourier modes with a -5/3 spectrum, unit
 RMS) interpolated by the library, HOPU projection degree l = 4, dt = 1e-4.
 One step = one explicit substep u <- u - dt M^-1 r(u): the convection apply
 (dual->modal transform, fused element kernel, facet-row assembly), the PCG
-mass solve (warm-started, preconditioned residual 1e-13) and the update,
-all on the GPU, inputs resident in HBM.
+mass solve (preconditioned residual 1e-13, initial guess extrapolated from
+the previous substeps' solutions) and the update, all on the GPU, inputs
+resident in HBM.  The W warm-up substeps and the K timed ones are one
+trajectory: the timed substeps continue the warm-up's (hopu_set_warm_start),
+as in a long run; the first, cold substep's PCG count is reported apart.
 
-Also reported: the same substeps with FP32-MFMA and split-BF16 contractions
-(rate, speed-up and the state's error against the FP64 path), the
-checkpointed mixed-precision adjoint chain, apply-only rates, the roofline of
-the dominant kernel, the 3D periodic Taylor-Green workload (32^3 x 6 tets,
-k = 3) as a secondary line, the projection step on it, and the FP64 oracle
-on the host cores as the CPU baseline.
+Also reported: the PCG iteration counts (cold and warm), one substep from
+u0 with FP32-MFMA and split-BF16 contractions (rate, speed-up, the state's
+error against the FP64 substep and the apply's error against the FP64
+apply), the checkpointed FP64 and hi/mid/lo adjoint of one substep,
+apply-only rates, the roofline of the dominant kernel, the 3D periodic
+Taylor-Green workload (32^3 x 6 tets, k = 3) as a secondary line with the
+projection step, and the FP64 oracle on the host cores as the CPU
+baseline.  The sections after the timed substeps and the CPU baseline run
+only while they fit in --budget-s; a skipped one is named under "skipped".
 
 Prints one JSON line (metric in DoF-updates/s: n_dof x steps / time).
 """
@@ -47,12 +53,16 @@ WORKLOADS = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", type=int, default=5, choices=(2, 5),
                     help="main line: 5 (channel, k=5) or 2 (periodic Taylor-Green, k=3)")
-    ap.add_argument("--adjoint-steps", type=int, default=10,
-                    help="substeps of the timed mixed-precision adjoint chain (checkpoint every 5)")
+    ap.add_argument("--adjoint-steps", type=int, default=1,
+                    help="substeps of the timed adjoint chain (FP64 and hi/mid/lo)")
+    ap.add_argument("--adjoint-ckpt", type=int, default=1, help="checkpoint interval of the adjoint chain")
+    ap.add_argument("--budget-s", type=float, default=480.0,
+                    help="wall-clock budget of the whole run: the sections after the timed substeps and the "
+                         "CPU baseline (mixed forms, adjoint, secondary workload) run only while they fit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -82,23 +92,25 @@ def mass_flops(n, d, E):
 
 
 def traffic_from_profiles(kernel_key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summaries (profiles/*traffic*.txt), if one was taken on the current
+    kernel source; else None."""
     src = os.path.join(ROOT, "paper_2408_06698_amd", "csrc", "kernels.hip")
-    if not os.path.exists(path):
-        return None
     text = open(src).read()
     body = text[text.index("namespace hopu {"):text.index("// " + "-" * 66 + " launchers")]
     sha = hashlib.sha256(body.encode()).hexdigest()[:16]
-    vals = {}
-    for line in open(path):
-        if "=" in line and not line.startswith("#"):
-            a, b = line.split("=", 1)
-            vals[a.strip()] = b.strip()
-    if vals.get("kernels_sha") != sha or kernel_key + "_bytes_per_launch" not in vals:
-        return None
-    return float(vals[kernel_key + "_bytes_per_launch"])
+    pdir = os.path.join(ROOT, "profiles")
+    for fn in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
+        if "traffic" not in fn or not fn.endswith(".txt"):
+            continue
+        vals = {}
+        for line in open(os.path.join(pdir, fn)):
+            if "=" in line and not line.startswith("#"):
+                a, b = line.split("=", 1)
+                vals[a.strip()] = b.strip()
+        if vals.get("kernels_sha") == sha and kernel_key + "_bytes_per_launch" in vals:
+            return float(vals[kernel_key + "_bytes_per_launch"])
+    return None
 
 
 def _cpu_model():
@@ -113,11 +125,11 @@ def _cpu_model():
 
 def cpu_baseline(workload):
     """The FP64 oracle as it stands on the host cores, on a bounded sample:
-    the same recipe on a 4 x 4 x 4 x 6 = 384-tet mesh (k and l of the
-    workload); one substep = residual + mass solve (the oracle's CG) +
-    update, timed once with every BLAS/OpenMP pool at its default (all host
-    cores) and once with one thread.  Set-up (space, interpolation, mass
-    matrix) is not timed."""
+    the same recipe on a 3 x 3 x 3 x 6 = 162-tet mesh (k and l of the
+    workload).  One substep = the oracle's residual + mass solve + update,
+    timed once with every BLAS/OpenMP pool at its default (all host cores)
+    and once with one thread.  Set-up (space, interpolation, mass matrix and
+    its sparse LU factorisation) is not timed, as the GPU's is not."""
     import numpy as np
     import synth
     from oracle import space as S, operator as O
@@ -125,17 +137,19 @@ def cpu_baseline(workload):
         from threadpoolctl import threadpool_limits, threadpool_info
     except Exception:  # pragma: no cover
         threadpool_limits, threadpool_info = None, lambda: []
-    mesh, field, cfg = synth.make_config(workload, n_override=(4, 4, 4))
+    mesh, field, cfg = synth.make_config(workload, n_override=(3, 3, 3))
     k, l, dt = cfg["k"], cfg["l"], cfg["dt"]
+    t_set = time.perf_counter()
     sp = S.Space(mesh.elem_vid, mesh.elem_xyz, k)
     x = sp.interpolate(field, nq1d=k + 1)
     if cfg["noise"]:
         x = x + cfg["noise"] * np.random.default_rng(6698 + workload).standard_normal(sp.n_dof)
-    O.mass_matrix(sp)
+    O.mass_solve(sp, np.zeros(sp.n_dof))   # assembles M and factors it
+    t_set = time.perf_counter() - t_set
 
     def substep(x):
         t0 = time.perf_counter()
-        w = O.mass_solve(sp, O.residual(sp, x, l), method="cg")
+        w = O.mass_solve(sp, O.residual(sp, x, l))
         x = x - dt * w
         return x, time.perf_counter() - t0
 
@@ -148,9 +162,10 @@ def cpu_baseline(workload):
         t_one = None
     threads = max([p[1] for p in pools if p[1]] or [1])
     return {"value": sp.n_dof / t_all, "unit": "DoF-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"workload recipe on 4x4x4x6=384 tets, k={k}, {sp.n_dof} DoFs; one substep (numpy einsum "
-                      f"residual + CG mass solve + update) = {t_all:.2f} s with the BLAS/OpenMP pools at their "
-                      f"defaults {pools}" + (f", {t_one:.2f} s with one thread" if t_one else ""),
+            "sample": f"workload recipe on 3x3x3x6=162 tets, k={k}, {sp.n_dof} DoFs; one substep (numpy einsum "
+                      f"residual + sparse-LU mass solve + update) = {t_all:.2f} s with the BLAS/OpenMP pools at "
+                      f"their defaults {pools}" + (f", {t_one:.2f} s with one thread" if t_one else "") +
+                      f"; untimed set-up (space, interpolation, mass matrix, LU) {t_set:.1f} s",
             "value_1_thread": sp.n_dof / t_one if t_one else None,
             "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
 
@@ -169,7 +184,9 @@ class Ctx:
         self.k, self.l, self.dt = cfg["k"], cfg["l"], cfg["dt"]
         h = Hopu(3, self.k, mesh.elem_vid, mesh.elem_xyz)
         h.set_upwind(self.l)
-        h.set_solver(rtol=1e-13, max_it=2000, check_every=2)
+        # convergence checked every 16 iterations (a C5 solve takes
+        # hundreds; iterations queued past convergence return at once)
+        h.set_solver(rtol=1e-13, max_it=3000, check_every=16)
         self.h = h
         # the field is sampled on the GPU in chunks of points (the random
         # Fourier fields evaluate every mode at every point)
@@ -193,52 +210,41 @@ class Ctx:
     def ev(self):
         return self.torch.cuda.Event(enable_timing=True)
 
-    def substeps(self, prec, steps, warm, profile=0):
-        torch, h = self.torch, self.h
-        if warm:
-            u = self.u0.clone()
-            h.substeps(u, self.dt, warm, prec)
-        u = self.u0.clone()
+    def timed(self, fn):
+        """fn() between two events on the stream; (result, ms)."""
+        torch = self.torch
         torch.cuda.synchronize()
-        h.profile(profile)
         a, b = self.ev(), self.ev()
         a.record(self.stream)
-        h.substeps(u, self.dt, steps, prec, diag=False)
+        out = fn()
         b.record(self.stream)
         torch.cuda.synchronize()
-        prof = {kk: h.profile_read(kk) for kk in ("elem", "mass", "prec", "modal", "plain")} if profile else None
-        h.profile(False)
-        return u, a.elapsed_time(b), prof
+        return out, a.elapsed_time(b)
 
     def apply_ms(self, prec, reps=5):
         h, r = self.h, self.h.zeros()
         h.apply(self.u0, r, prec=prec)
-        self.torch.cuda.synchronize()
-        a, b = self.ev(), self.ev()
-        a.record(self.stream)
-        for _ in range(reps):
-            h.apply(self.u0, r, prec=prec)
-        b.record(self.stream)
-        self.torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
+
+        def run():
+            for _ in range(reps):
+                h.apply(self.u0, r, prec=prec)
+        return self.timed(run)[1] / reps
 
     def mnorm_rel(self, v, ref):
         torch, h = self.torch, self.h
         d = v - ref
         return float(torch.sqrt(torch.dot(d, h.mass_apply(d)) / torch.dot(ref, h.mass_apply(ref))))
 
-    def apply_err(self, prec):
-        """Residual error of a reduced-precision apply against the FP64 one
-        in the M^-1 norm (the dual norm of a residual)."""
-        torch, h = self.torch, self.h
-        r64, rp = h.apply(self.u0), h.apply(self.u0, prec=prec)
-        d = rp - r64
-        wd, _ = h.mass_solve(d, rtol=1e-12)
-        w64, _ = h.mass_solve(r64, rtol=1e-12)
-        return float(torch.sqrt(torch.dot(d, wd) / torch.dot(r64, w64)))
+    def minv_norm2(self, d):
+        """d.M^-1 d (a residual's squared dual norm).  CG's d.w_i approaches
+        d.M^-1 d from below with error ||w - w_i||_M^2, so a solve to a
+        relative residual of 1e-4 gives it to far better than the digits
+        reported."""
+        w, _ = self.h.mass_solve(d, rtol=1e-4, max_it=3000)
+        return float(self.torch.dot(d, w))
 
 
-def roofline(c, prof, pcg_its_per_step, steps):
+def roofline(c, prof):
     """Roofline of the kernel with the largest summed time in the timed
     region: algorithmic flops per launch / average launch duration (the
     library's HIP events on the launches themselves)."""
@@ -254,18 +260,20 @@ def roofline(c, prof, pcg_its_per_step, steps):
         name = f"k_elem<double,3,{c.k},0> (volume + HOPU facets + dual transform)"
     elif dom in ("mass", "prec"):
         algo = mass_flops(n, 3, E)
-        name = f"mass kernel, k={c.k} ({'M p' if dom == 'mass' else 'preconditioner P r'} sandwich)"
+        kern = "k_mass_tiled" if c.k >= 4 else "k_mass_lds"
+        name = f"{kern}, k={c.k} ({'M p' if dom == 'mass' else 'preconditioner P r'} sandwich)"
     else:
         algo = 2.0 * n * n * E
         name = f"{dom} kernel"
-    key = {"elem": "elem", "mass": "mass", "prec": "prec"}.get(dom, dom) + f"_k{c.k}"
+    key = f"{dom}_k{c.k}"
     roof = {"kernel": name, "bound": "mfma", "achieved": algo / avg / 1e12, "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s", "frac": algo / avg / PEAK_FP64, "traffic": traffic_from_profiles(key),
-            "avg_launch_us": avg * 1e6, "launches_timed": launches, "flops_per_launch": algo}
+            "traffic_key": key, "avg_launch_us": avg * 1e6, "launches_timed": launches, "flops_per_launch": algo}
     return roof, dom
 
 
 def main():
+    t_start = time.time()
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
@@ -275,31 +283,56 @@ def main():
     from paper_2408_06698_amd import FP64, FP32_MFMA, BF16X2, BF16X3
     from paper_2408_06698_amd.hopu import mfma_f64_rate
 
+    def log(msg):
+        print(f"# [{time.time() - t_start:6.1f} s] {msg}", file=sys.stderr, flush=True)
+
     # the library's per-launch timing events go on every PROF_STRIDE-th
     # launch of each kernel kind (a dispatch with events starts a few
     # microseconds later)
     PROF_STRIDE = 4
     c = Ctx(args.workload, torch)
     h, ndof = c.h, c.h.n_dof
-    print(f"# workload {args.workload}: {c.mesh.n_elems} elements, {ndof} DoFs, set-up {c.setup_s:.1f} s",
-          file=sys.stderr, flush=True)
-    u64, ms64, prof64 = c.substeps(FP64, args.steps, args.warmup, profile=PROF_STRIDE)
+    log(f"workload {args.workload}: {c.mesh.n_elems} elements, {ndof} DoFs, set-up {c.setup_s:.1f} s")
+
+    # warm-up: the first substep from u0 cold (its state and time are also
+    # the FP64 reference of the mixed forms), then the rest continuing it
+    W = max(args.warmup, 1)
+    u = c.u0.clone()
+    h.set_warm_start(False)
+    diag1, ms_first = c.timed(lambda: h.substeps(u, c.dt, 1, FP64, diag=True))
+    diag1 = diag1.cpu()
+    u1 = u.clone()
+    h.set_warm_start(True)
+    diagw = h.substeps(u, c.dt, W - 1, FP64, diag=True).cpu() if W > 1 else None
+    log(f"warm-up: {W} substeps, first (cold) {ms_first:.0f} ms, {int(diag1[1, 3])} PCG iterations")
+    # timed: K substeps continuing the warm-up's trajectory and extrapolation
+    h.profile(PROF_STRIDE)
+    _, ms64 = c.timed(lambda: h.substeps(u, c.dt, args.steps, FP64, diag=False))
+    prof64 = {kk: h.profile_read(kk) for kk in ("elem", "mass", "prec", "modal", "plain")}
+    h.profile(False)
+    t_sub = ms64 / args.steps * 1e-3
     value = ndof * args.steps / (ms64 * 1e-3)
-    print(f"# fp64 substeps: {ms64 / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
-    diag = h.substeps(c.u0.clone(), c.dt, 2, FP64, diag=True).cpu()
-    pcg_its = float(diag[1:, 3].mean())
-    roof, dom = roofline(c, prof64, pcg_its, args.steps)
+    log(f"fp64 substeps: {ms64 / args.steps:.1f} ms/step")
+    roof, dom = roofline(c, prof64)
     apply64 = c.apply_ms(FP64)
     F_apply, _, _ = flops_model(c.sz, c.mesh.n_elems, h.n_facets)
+    pcg = {"cold_first_substep": float(diag1[1, 3]), "rtol": 1e-13,
+           "preconditioner": "element-wise BDDC without primal constraints (local mass inverses, plain average)"}
+    if diagw is not None:
+        pcg["warm_mean_warmup_substeps"] = float(diagw[1:, 3].mean())
+    # launches of the preconditioner kernel in the timed region (every
+    # PROF_STRIDE-th is timed; each solve adds two set-up launches)
+    pcg["timed_mean_estimate"] = prof64["prec"][0] * PROF_STRIDE / args.steps - 2
     out = {
         "metric": METRIC, "value": value, "unit": "DoF-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms64 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded, see config.workload)",
         "config": {"workload": WORKLOADS[args.workload], "n_dof": ndof, "elements": c.mesh.n_elems,
-                   "facets": h.n_facets, "wall_facets": h.n_wall, "k": c.k, "l": c.l, "dt": c.dt},
+                   "facets": h.n_facets, "wall_facets": h.n_wall, "k": c.k, "l": c.l, "dt": c.dt,
+                   "warmup_substeps_run": W},
         "roofline": roof,
-        "pcg_iters_per_step": pcg_its,
+        "pcg_iterations_per_substep": pcg,
         "apply_ms_fp64": apply64, "apply_rate_fp64": ndof / (apply64 * 1e-3),
         "apply_frac_fp64_flops": F_apply / (apply64 * 1e-3) / PEAK_FP64,
         "apply_flops": F_apply,
@@ -308,50 +341,79 @@ def main():
         "kernel_launches_sampled": {kk: v[0] for kk, v in prof64.items()},
         "mfma_f64_sustained_tflops_by_waves_per_simd": {str(w): mfma_f64_rate(w) for w in (1, 2, 8)},
         "setup_s": c.setup_s,
+        "skipped": {},
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+        log("cpu baseline done")
+
+    def fits(name, est_s):
+        """Whether a further section of about est_s seconds keeps the whole
+        run inside --budget-s; records the skip otherwise."""
+        left = args.budget_s - (time.time() - t_start)
+        if est_s <= left - 30:
+            return True
+        out["skipped"][name] = f"time budget: needs about {est_s:.0f} s, {left:.0f} s of {args.budget_s:.0f} s left"
+        log(f"skipping {name}: {out['skipped'][name]}")
+        return False
+
+    # the mixed forms: each one cold substep from u0, against the FP64
+    # state after the same substep (the warm-up's first); apply error in the
+    # M^-1 norm against the FP64 apply
     if not args.no_mixed:
-        mixed = {}
+        mixed = {"protocol": "one cold substep from u0 per form (timed), state error against the FP64 "
+                             "substep from u0 in the M norm; apply error against the FP64 apply in the "
+                             "M^-1 norm", "fp64_ms_per_step": ms_first}
+        r64 = None
         for prec, name, dtype in ((FP32_MFMA, "fp32_mfma", "fp32-mfma"), (BF16X3, "bf16x3", "split-bf16 hi/mid/lo"),
                                   (BF16X2, "bf16x2", "split-bf16 hi/lo")):
-            up, msp, _ = c.substeps(prec, args.steps, 1)
+            if not fits(f"mixed_{name}", 1.5 * ms_first * 1e-3 + (0.7 if r64 is None else 0.35) * t_sub):
+                continue
+            if r64 is None:
+                r64 = h.apply(c.u0)
+                r64_n2 = c.minv_norm2(r64)
+            up = c.u0.clone()
+            h.set_warm_start(False)
+            dp, msp = c.timed(lambda: h.substeps(up, c.dt, 1, prec, diag=True))
             ap = c.apply_ms(prec)
-            mixed[name] = {"value": ndof * args.steps / (msp * 1e-3), "ms_per_step": msp / args.steps,
-                           "speedup_substep": ms64 / msp, "apply_ms": ap, "speedup_apply": apply64 / ap,
-                           "state_rel_err_vs_fp64_M_norm": c.mnorm_rel(up, u64),
-                           "apply_rel_err_vs_fp64_Minv_norm": c.apply_err(prec),
+            d = h.apply(c.u0, prec=prec) - r64
+            mixed[name] = {"ms_per_step": msp, "value": ndof / (msp * 1e-3), "speedup_substep": ms_first / msp,
+                           "pcg_iterations": float(dp.cpu()[1, 3]), "apply_ms": ap, "speedup_apply": apply64 / ap,
+                           "state_rel_err_vs_fp64_M_norm": c.mnorm_rel(up, u1),
+                           "apply_rel_err_vs_fp64_Minv_norm": math.sqrt(c.minv_norm2(d) / r64_n2),
                            "dtype": dtype + " contractions, FP32 accumulation in a tile, FP64 across tiles; "
                                             "FP64 state, transforms, mass solve and diagnostics"}
-            del up
-            print(f"# {name}: {msp / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
+            del up, d
+            log(f"{name}: {msp:.0f} ms/step")
         out["mixed"] = mixed
+        del r64
+    # the checkpointed reverse chain of L = 1/2 u_1.M u_1 after one
+    # substep, FP64 and hi/mid/lo: the forward recomputation, then the
+    # reverse step (a mass solve and a transpose Jacobian)
     if not args.no_adjoint:
-        # checkpointed reverse chain of L = 1/2 u_N.M u_N in the reduced
-        # forms (and FP64), checkpoint every 5 substeps: forward with
-        # checkpoints, then the segments' recomputation and the reverse steps
-        n_adj = args.adjoint_steps
-        uN = c.u0.clone()
-        h.substeps(uN, c.dt, n_adj, FP64)
-        lamN = h.mass_apply(uN)
-        del uN
-        adj = {"substeps": n_adj, "ckpt_every": 5}
+        n_adj, ck = args.adjoint_steps, args.adjoint_ckpt
+        adj = {"substeps": n_adj, "ckpt_every": ck, "loss": "1/2 u_N.M u_N"}
+        lamN = None
         lam_ref = None
-        for prec, name in ((FP64, "fp64"), (FP32_MFMA, "fp32_mfma"), (BF16X3, "bf16x3")):
-            torch.cuda.synchronize()
-            a, b = c.ev(), c.ev()
-            a.record(c.stream)
-            lam0 = h.substeps_vjp(c.u0, c.dt, n_adj, lamN, ckpt_every=5, prec=prec)
-            b.record(c.stream)
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b)
+        for prec, name in ((FP64, "fp64"), (BF16X3, "bf16x3")):
+            if not fits(f"adjoint_{name}", (2.5 * n_adj + 0.4) * t_sub):
+                continue
+            if lamN is None:
+                uN = u1.clone() if n_adj == 1 else c.u0.clone()
+                if n_adj != 1:
+                    h.set_warm_start(False)
+                    h.substeps(uN, c.dt, n_adj, FP64)
+                lamN = h.mass_apply(uN)
+                del uN
+            h.set_warm_start(False)
+            lam0, ms = c.timed(lambda: h.substeps_vjp(c.u0, c.dt, n_adj, lamN, ckpt_every=ck, prec=prec))
             adj[name] = {"ms": ms, "dof_updates_per_s": ndof * n_adj / (ms * 1e-3)}
             if lam_ref is None:
                 lam_ref = lam0
             else:
-                d = lam0 - lam_ref
-                wd, _ = h.mass_solve(d, rtol=1e-12)
-                wr, _ = h.mass_solve(lam_ref.clone(), rtol=1e-12)
-                adj[name]["rel_err_vs_fp64_Minv_norm"] = float(torch.sqrt(torch.dot(d, wd) / torch.dot(lam_ref, wr)))
-            print(f"# adjoint {name}: {ms:.0f} ms", file=sys.stderr, flush=True)
+                adj[name]["rel_err_vs_fp64_Minv_norm"] = math.sqrt(c.minv_norm2(lam0 - lam_ref) /
+                                                                   c.minv_norm2(lam_ref))
+            log(f"adjoint {name}: {ms:.0f} ms")
         del lam_ref, lamN
         out["adjoint_chain"] = adj
     if args.copy_calib:
@@ -361,40 +423,55 @@ def main():
         torch.cuda.synchronize()
         out["copy_calib_bytes"] = src.numel() * 8
         del src, dst
-    del u64
+    del u, u1
     h.close()
     del c
     torch.cuda.empty_cache()
-    if not args.no_secondary and args.workload != 2:
+    if not args.no_secondary and args.workload != 2 and fits("secondary", 40):
         # the 3D periodic Taylor-Green workload, FP64 and FP32-MFMA substeps
         c2 = Ctx(2, torch)
         steps2 = 50
-        u2, ms2, prof2 = c2.substeps(FP64, steps2, 3, profile=PROF_STRIDE)
-        roof2, _ = roofline(c2, prof2, None, steps2)
-        sec = {"workload": WORKLOADS[2], "value": c2.h.n_dof * steps2 / (ms2 * 1e-3),
+        h2 = c2.h
+        u2 = c2.u0.clone()
+        h2.set_warm_start(False)
+        h2.substeps(u2, c2.dt, 3, FP64)
+        h2.set_warm_start(True)
+        h2.profile(PROF_STRIDE)
+        _, ms2 = c2.timed(lambda: h2.substeps(u2, c2.dt, steps2, FP64))
+        prof2 = {kk: h2.profile_read(kk) for kk in ("elem", "mass", "prec", "modal", "plain")}
+        h2.profile(False)
+        roof2, _ = roofline(c2, prof2)
+        sec = {"workload": WORKLOADS[2], "value": h2.n_dof * steps2 / (ms2 * 1e-3),
                "ms_per_step": ms2 / steps2, "steps": steps2, "roofline": roof2,
                "apply_ms_fp64": c2.apply_ms(FP64, 20)}
         if not args.no_mixed:
-            u32, ms32, _ = c2.substeps(FP32_MFMA, steps2, 1)
-            sec["fp32_mfma"] = {"ms_per_step": ms32 / steps2, "speedup_substep": ms2 / ms32,
-                                "state_rel_err_vs_fp64_M_norm": c2.mnorm_rel(u32, u2)}
+            u2r = c2.u0.clone()
+            h2.set_warm_start(False)
+            h2.substeps(u2r, c2.dt, 1, FP64)
+            h2.set_warm_start(True)
+            _, ms2r = c2.timed(lambda: h2.substeps(u2r, c2.dt, steps2, FP64))
+            u32 = c2.u0.clone()
+            h2.set_warm_start(False)
+            h2.substeps(u32, c2.dt, 1, FP32_MFMA)
+            h2.set_warm_start(True)
+            _, ms32 = c2.timed(lambda: h2.substeps(u32, c2.dt, steps2, FP32_MFMA))
+            sec["fp32_mfma"] = {"ms_per_step": ms32 / steps2, "speedup_substep": ms2r / ms32,
+                                "apply_ms": c2.apply_ms(FP32_MFMA, 20),
+                                "state_rel_err_vs_fp64_M_norm": c2.mnorm_rel(u32, u2r),
+                                "protocol": f"1 untimed + {steps2} timed substeps from u0, FP64 on the same"}
+            del u2r, u32
         if not args.no_projection:
             # projection step (section 2.3, eq. (MCS_step2)) of the state
             # after the substeps, whose divergence the convection broke
-            un = c2.h.zeros()
-            c2.h.project(u2, un, rtol=1e-13)        # set-up (A^-1) and warm-up
-            torch.cuda.synchronize()
-            a, b = c2.ev(), c2.ev()
-            a.record(c2.stream)
-            _, its = c2.h.project(u2, un, rtol=1e-13)
-            b.record(c2.stream)
-            torch.cuda.synchronize()
-            sec["projection"] = {"ms": a.elapsed_time(b), "cg_iters": its, "rtol": 1e-13,
-                                 "div_l2_before": c2.h.diagnostics(u2)[1], "div_l2_after": c2.h.diagnostics(un)[1]}
+            un = h2.zeros()
+            h2.project(u2, un, rtol=1e-13)        # set-up (A^-1) and warm-up
+            (_, its), ms = c2.timed(lambda: h2.project(u2, un, rtol=1e-13))
+            sec["projection"] = {"ms": ms, "cg_iters": its, "rtol": 1e-13,
+                                 "div_l2_before": h2.diagnostics(u2)[1], "div_l2_after": h2.diagnostics(un)[1]}
         out["secondary"] = sec
-        c2.h.close()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload)
+        h2.close()
+        log("secondary done")
+    out["wall_s"] = time.time() - t_start
     print(json.dumps(out))
 
 

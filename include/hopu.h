@@ -91,7 +91,7 @@ enum { HOPU_TERM_VOLUME = 1, HOPU_TERM_CENTRAL = 2, HOPU_TERM_UPWIND = 4, HOPU_T
  * coordinates of each element; hip_stream a hipStream_t (NULL = default).
  * Host work: topology, geometry, tables; then device allocation and copies.
  * Device memory: about 15 vectors of n_dof doubles, the element workspaces
- * and the PCG search-direction ring (min(64, 8 GB / (8 n_dof)) vectors, at
+ * and the PCG search-direction ring (min(64, 32 GB / (8 n_dof)) vectors, at
  * least 4; the environment variable HOPU_TEST_RING = h, 2 <= h <= 64, read
  * here, sets h vectors instead, for tests of the ring's wrap-around).
  * Syncs. */
@@ -181,6 +181,13 @@ hopu_status hopu_mfma_f64_rate(int blocks_per_cu, double* tflops);
 hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_steps,
                           hopu_precision prec, double* diag_dev);
 
+/* carry = 1: hopu_substeps starts the PCG initial-guess extrapolation from
+ * the solutions of the previous hopu_substeps call on this context (for a
+ * caller that advances one trajectory with one dt in several calls);
+ * carry = 0 (default): every call starts from a zero guess.  Either way the
+ * solves meet the tolerance; only the iteration counts differ. */
+hopu_status hopu_set_warm_start(hopu_ctx ctx, int carry);
+
 /* out = J_r(u)^T mu (dev [n_dof] each), the derivative of the residual of
  * eq. (hopudefinition) with respect to the state, transposed.  |u.n| is not
  * differentiable at 0: its derivative is taken as sgn(u.n) with sgn(0) = 0,
@@ -198,6 +205,11 @@ int64_t hopu_substeps_vjp_workspace(hopu_ctx ctx, int n_steps, int ckpt_every);
 hopu_status hopu_substeps_vjp(hopu_ctx ctx, const double* u0, double dt, int n_steps,
                               int ckpt_every, const double* lam_N, double* lam_0,
                               hopu_precision prec, void* ws, int64_t ws_bytes);
+
+/* Number of NaN or infinite entries of v (dev [n_dof]) into *count (host):
+ * the check for a state or residual that has blown up (every other call
+ * propagates non-finite values without a status).  Syncs. */
+hopu_status hopu_count_nonfinite(hopu_ctx ctx, const double* v, int64_t* count);
 
 /* Kinetic energy 1/2 u.Mu of u (dev [n_dof]) into energy_dev (dev, one
  * double), FP64.  Asynchronous (the loss of the adjoint workload). */

@@ -34,11 +34,13 @@ SIGNATURES = {
     "hopu_project": (_i, [_p, _p, _p, _d, _i, _p]),
     "hopu_mfma_f64_rate": (_i, [_i, _p]),
     "hopu_substeps": (_i, [_p, _p, _d, _i, _i, _p]),
+    "hopu_set_warm_start": (_i, [_p, _i]),
     "hopu_convection_vjp": (_i, [_p, _p, _p, _p, _i]),
     "hopu_substeps_vjp_workspace": (_i64, [_p, _i, _i]),
     "hopu_substeps_vjp": (_i, [_p, _p, _d, _i, _i, _p, _p, _i, _p, _i64]),
     "hopu_diagnostics": (_i, [_p, _p, _p, _p, _p]),
     "hopu_energy": (_i, [_p, _p, _p]),
+    "hopu_count_nonfinite": (_i, [_p, _p, _p]),
     "hopu_interp_points": (_i, [_p, _i, _p, _p]),
     "hopu_interpolate": (_i, [_p, _i, _p, _p, _p]),
     "hopu_eval": (_i, [_p, _p, _i, _p, _p]),

@@ -19,6 +19,8 @@ void launch_eval(hipStream_t s, int D, int n, int nf, int nint, int np, const do
                  const DevMesh& mesh, double* out);
 void launch_adapt(hipStream_t s, const double* eta_nd, int64_t F, const double* thr, int k, int8_t* lfac,
                   double* eta_out);
+// count[0] = number of NaN / infinite entries of v[0, n)
+void launch_count_nonfinite(hipStream_t s, const double* v, int64_t n, unsigned long long* count);
 // measurement: register-only FP64 MFMA chains, blocks x 256 threads, out
 // [blocks * 256]
 void launch_mfma_f64_rate(hipStream_t s, double* out, int blocks, int iters);

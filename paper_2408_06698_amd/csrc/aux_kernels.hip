@@ -1,4 +1,6 @@
 // Diagnostics (energy, divergence), interpolation and evaluation kernels.
+#include <algorithm>
+
 #include "aux.hpp"
 #include "kernels.hpp"
 
@@ -258,6 +260,24 @@ void launch_interpolate(hipStream_t s, int D, int nqs, int nf, const double* vf,
     hipLaunchKernelGGL(k_interp_int, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, D, nqv, nint, vv, wv, qm,
                        mesh, x + mesh.F * nf);
 }
+// Number of NaN / infinite entries of v (an integer count: the atomic adds
+// commute, so the result is exact and order-independent).
+__global__ void k_zero_count(unsigned long long* count) { *count = 0ull; }
+__global__ __launch_bounds__(256) void k_count_nonfinite(const double* __restrict__ v, int64_t n,
+                                                         unsigned long long* count) {
+  unsigned int c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    c += isfinite(v[i]) ? 0u : 1u;
+#pragma unroll
+  for (int sh = 32; sh >= 1; sh >>= 1) c += __shfl_xor(c, sh, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, (unsigned long long)c);
+}
+void launch_count_nonfinite(hipStream_t s, const double* v, int64_t n, unsigned long long* count) {
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, count);
+  const int64_t b = std::min<int64_t>((n + 255) / 256, 2048);
+  if (n > 0) hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)b), dim3(256), 0, s, v, n, count);
+}
+
 void launch_eval(hipStream_t s, int D, int n, int nf, int nint, int np, const double* x, const double* phi,
                  const DevMesh& mesh, double* out) {
   int64_t nt = mesh.E * np;

@@ -65,8 +65,11 @@ struct hopu_ctx_s {
   bool proj_ready = false;
   double* stage = nullptr;  // 16-byte aligned copy of a mass-kernel input that is not
   double* wh[3] = {nullptr, nullptr, nullptr};  // previous substep solutions (newest first)
+  int nwh = 0;              // how many of them a continuing hopu_substeps may use
+  bool carry_warm = false;  // hopu_set_warm_start
   double* sc = nullptr;
   int* flag = nullptr;      // [0] converged, [1] iterations
+  unsigned long long* nbad = nullptr;  // hopu_count_nonfinite's counter
   int* hflag = nullptr;     // pinned host copy
   std::vector<void*> allocs;
   DualBasis eval_db;              // reference dual basis (evaluation at given points)
@@ -393,9 +396,12 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(dev_alloc(ctx, &ctx->r, (size_t)n));
     TRY(dev_alloc(ctx, &ctx->z, (size_t)n));
     {
-      // direction history: up to 64 vectors within 8 GB, at least 4
-      // (HOPU_TEST_RING=h sets h, for tests of the ring's wrap-around)
-      const int64_t fit = (int64_t)(8.0e9 / (8.0 * (double)std::max<int64_t>(n, 1)));
+      // direction history: up to 64 vectors within 32 GB (an eighth of the
+      // GPU's memory), at least 4 (HOPU_TEST_RING=h sets h, for tests of the
+      // ring's wrap-around).  A solve checks convergence at most every
+      // nph - 1 iterations, and each check adds the directions since the
+      // last one to x in one pass (x read and written once per chunk).
+      const int64_t fit = (int64_t)(32.0e9 / (8.0 * (double)std::max<int64_t>(n, 1)));
       ctx->nph = (int)std::max<int64_t>(4, std::min<int64_t>(64, fit));
       const char* ring = std::getenv("HOPU_TEST_RING");
       if (ring && std::atoi(ring) >= 2 && std::atoi(ring) <= 64) ctx->nph = std::atoi(ring);
@@ -411,6 +417,7 @@ extern "C" hopu_status hopu_create(hopu_ctx* out, int dim, int k, int64_t n_elem
     TRY(dev_alloc(ctx, &ctx->own_lfac, (size_t)ctx->mesh.F));
     TRY(dev_alloc(ctx, &ctx->eta_nd, (size_t)(2 * ctx->mesh.F)));
     TRY(dev_alloc(ctx, &ctx->flag, 4));
+    TRY(dev_alloc(ctx, &ctx->nbad, 1));
     void* hp = nullptr;
     if (hipHostMalloc(&hp, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) { st = HOPU_ENOMEM; ctx->err = "hipHostMalloc failed"; goto fail_create; }
     ctx->hflag = (int*)hp;
@@ -785,6 +792,17 @@ static hopu_status diag_into(hopu_ctx ctx, const double* u, double* dst /*dev [3
   return HOPU_OK;
 }
 
+extern "C" hopu_status hopu_count_nonfinite(hopu_ctx ctx, const double* v, int64_t* count) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!v || !count) return fail(ctx, HOPU_EINVAL, "NULL pointer");
+  launch_count_nonfinite(ctx->stream, v, ctx->n_dof, ctx->nbad);
+  unsigned long long h = 0;
+  HCHECK(hipMemcpyAsync(&h, ctx->nbad, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  HCHECK(hipStreamSynchronize(ctx->stream));
+  *count = (int64_t)h;
+  return HOPU_OK;
+}
+
 extern "C" hopu_status hopu_energy(hopu_ctx ctx, const double* u, double* energy_dev) {
   if (!ctx) return HOPU_EINVAL;
   if (!u || !energy_dev) return fail(ctx, HOPU_EINVAL, "NULL pointer");
@@ -896,9 +914,11 @@ extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_s
   refresh_dm(ctx);
   hipStream_t s = ctx->stream;
   // PCG initial guess: polynomial extrapolation of the previous solutions
-  // (w_{n-1}; 2w_{n-1} - w_{n-2}; 3w_{n-1} - 3w_{n-2} + w_{n-3})
+  // (w_{n-1}; 2w_{n-1} - w_{n-2}; 3w_{n-1} - 3w_{n-2} + w_{n-3}), from this
+  // call's earlier substeps, or also the previous call's (hopu_set_warm_start)
   double* wh[3] = {ctx->wh[0], ctx->wh[1], ctx->wh[2]};
-  int nh = 0;
+  int nh = ctx->carry_warm ? ctx->nwh : 0;
+  ctx->nwh = 0;  // until this call has left its history consistent
   for (int st_i = 0; st_i <= n_steps; ++st_i) {
     const bool last = st_i == n_steps;
     if (diag_dev) {
@@ -934,8 +954,17 @@ extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_s
     wh[0] = w;
     nh = std::min(nh + 1, 3);
   }
+  for (int i = 0; i < 3; ++i) ctx->wh[i] = wh[i];
+  ctx->nwh = nh;
   HCHECK(hipGetLastError());
   HCHECK(hipStreamSynchronize(s));
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_set_warm_start(hopu_ctx ctx, int carry) {
+  if (!ctx) return HOPU_EINVAL;
+  if (carry != 0 && carry != 1) return fail(ctx, HOPU_EINVAL, "carry must be 0 or 1");
+  ctx->carry_warm = carry == 1;
   return HOPU_OK;
 }
 

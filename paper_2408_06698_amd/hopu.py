@@ -103,6 +103,11 @@ class Hopu:
         check(L.lib().hopu_get_facet_orders(self.h, _ptr(out)), self.h)
         return out
 
+    def set_warm_start(self, carry):
+        """carry: continue the PCG initial-guess extrapolation across
+        substeps() calls (one trajectory advanced in several calls)."""
+        check(L.lib().hopu_set_warm_start(self.h, int(bool(carry))), self.h)
+
     def set_solver(self, rtol=1e-13, max_it=500, check_every=4):
         check(L.lib().hopu_set_solver(self.h, float(rtol), int(max_it), int(check_every)), self.h)
 
@@ -157,6 +162,12 @@ class Hopu:
         out = torch.zeros((), dtype=torch.float64, device=self.device) if out is None else out
         check(L.lib().hopu_energy(self.h, _ptr(_dev(u, self.n_dof)), _ptr(_dev(out, 1, what="energy"))), self.h)
         return out
+
+    def count_nonfinite(self, v):
+        """Number of NaN / infinite entries of v."""
+        n = C.c_int64()
+        check(L.lib().hopu_count_nonfinite(self.h, _ptr(_dev(v, self.n_dof)), C.byref(n)), self.h)
+        return n.value
 
     def diagnostics(self, u):
         e, dv, ds = C.c_double(), C.c_double(), C.c_double()

@@ -13,14 +13,19 @@ import sys
 
 # kernel keys of the traffic summary: substring of the demangled name
 TRAFFIC_KERNELS = [
-    ("mass", "k_mass_lds<double, 3, 3, 0>"),
-    ("prec", "k_mass_lds<double, 3, 3, 1>"),
-    ("elem", "k_elem<double, 3, 3, 0>"),
-    ("elem_fp32", "k_elem<float, 3, 3, 0>"),
-    ("modal", "k_mass_lds<double, 3, 3, 2>"),
+    ("mass_k3", "k_mass_lds<double, 3, 3, 0>"),
+    ("prec_k3", "k_mass_lds<double, 3, 3, 1>"),
+    ("elem_k3", "k_elem<double, 3, 3, 0>"),
+    ("elem_fp32_k3", "k_elem<float, 3, 3, 0>"),
+    ("modal_k3", "k_mass_lds<double, 3, 3, 2>"),
+    ("mass_k5", "k_mass_tiled<3, 5, 0>"),
+    ("prec_k5", "k_mass_tiled<3, 5, 1>"),
+    ("elem_k5", "k_elem<double, 3, 5, 0>"),
+    ("elem_fp32_k5", "k_elem<float, 3, 5, 0>"),
+    ("modal_k5", "k_modal<double, 3, 5>"),
     ("rupdate", "k_rupdate<2>("),
     ("xpay", "k_xpay<2>("),
-    ("proj", "k_proj<3, 3, 0>"),
+    ("proj_k3", "k_proj<3, 3, 0>"),
 ]
 
 
@@ -86,8 +91,11 @@ def traffic(fetch_db, write_db, src):
         print(f"{key}_bytes_per_launch = {f * 1024 * fs + w * 1024 * ws:.0f}")
 
 
-BUSY_KERNELS = TRAFFIC_KERNELS + [("elem_bf16x2", "k_elem<float, 3, 3, 2>"), ("elem_bf16x3", "k_elem<float, 3, 3, 3>"),
-                                  ("prec_fp32", "k_mass_lds<float, 3, 3, 1>")]
+BUSY_KERNELS = TRAFFIC_KERNELS + [("elem_bf16x2_k3", "k_elem<float, 3, 3, 2>"),
+                                  ("elem_bf16x3_k3", "k_elem<float, 3, 3, 3>"),
+                                  ("prec_fp32_k3", "k_mass_lds<float, 3, 3, 1>"),
+                                  ("elem_bf16x2_k5", "k_elem<float, 3, 5, 2>"),
+                                  ("elem_bf16x3_k5", "k_elem<float, 3, 5, 3>")]
 N_SIMD = 256 * 4  # MI355X: 256 CUs, 4 SIMDs each
 N_XCD = 8
 

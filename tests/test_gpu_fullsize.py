@@ -63,6 +63,32 @@ def _check_vjps(h, sp, x, xs, l, patch, rows_f, rows_i, what):
     _check(host(h.vjp(u, m, prec=2)), gref, rows_f, rows_i, 3e-3, f"vjp bf16x2 {what} (smooth state)")
 
 
+def _check_smooth_applies(h, sp, xs, l, patch, rows_f, rows_i, what):
+    """The applies at the workload's own smooth field, where the residual is
+    a sum that cancels: the volume part of the conservative form is many
+    times the residual (printed as |vol part|/|r|; up to 4e3 on the interior
+    rows, whose test fields are nearly orthogonal to the convective term of
+    a resolved field).  Errors are printed relative to the residual and held
+    relative to the volume part (a backward error: the reduced forms round
+    relative to the integrands they sum).  The reduced forms' bound: an FP32
+    tile accumulates 64 products per output (16 points x 4 in a step
+    group), each rounded to 2^-24, so up to 64 * 2^-24 = 3.8e-6 of the
+    tile's integrands in the worst case and about 8 * 2^-24 = 4.8e-7 for
+    random rounding; held at 2e-6."""
+    ref = O.residual(sp, xs, l, elems=patch)
+    vol = O.residual(sp, xs, l, terms=O.TERM_VOLUME, elems=patch)
+    u = dev(xs)
+    for prec, name, tol in ((0, "fp64", 1e-12), (1, "fp32", 2e-6), (3, "bf16x3", 2e-6), (2, "bf16x2", 3e-3)):
+        r = host(h.apply(u, prec=prec))
+        for blk, rows in (("facet", rows_f), ("interior", rows_i)):
+            kap = np.linalg.norm(vol[rows]) / np.linalg.norm(ref[rows])
+            d = np.linalg.norm(r[rows] - ref[rows])
+            e, eb = d / np.linalg.norm(ref[rows]), d / np.linalg.norm(vol[rows])
+            print(f"apply {name} {what} (smooth state) {blk} rows: |vol part|/|r| {kap:.1f}, rel l2 {e:.2e}, "
+                  f"error / |vol part| {eb:.2e}")
+            assert eb <= tol, (what, name, blk, eb)
+
+
 @pytest.mark.parametrize("cfg", [2, 3])
 def test_fullsize_apply_vjp_mass(cfg):
     mesh, sp, x, c, patch, rows_f, rows_i, xs = _setup(cfg)
@@ -75,6 +101,7 @@ def test_fullsize_apply_vjp_mass(cfg):
     _check(host(h.apply(u, prec=1)), ref, rows_f, rows_i, 1e-6, "apply fp32")
     _check(host(h.apply(u, prec=2)), ref, rows_f, rows_i, 3e-3, "apply bf16x2")
     _check(host(h.apply(u, prec=3)), ref, rows_f, rows_i, 1e-6, "apply bf16x3")
+    _check_smooth_applies(h, sp, xs, l, patch, rows_f, rows_i, f"cfg {cfg}")
     _check_vjps(h, sp, x, xs, l, patch, rows_f, rows_i, f"cfg {cfg}")
     # mass rows of the sample: M restricted to the patch elements
     t = sp.topo
@@ -113,6 +140,7 @@ def test_fullsize_channel_k5():
     _check(host(h.apply(u)), ref, rows_f, rows_i, 1e-12, "apply fp64 k5")
     _check(host(h.apply(u, prec=1)), ref, rows_f, rows_i, 1e-6, "apply fp32 k5")
     _check(host(h.apply(u, prec=3)), ref, rows_f, rows_i, 1e-6, "apply bf16x3 k5")
+    _check_smooth_applies(h, sp, xs, c["l"], patch, rows_f, rows_i, "k5")
     _check_vjps(h, sp, x, xs, c["l"], patch, rows_f, rows_i, "k5")
     _check(host(h.mass_apply(u)), _patch_mass(sp, x, patch), rows_f, rows_i, 1e-13, "mass k5")
     del sp

@@ -198,3 +198,48 @@ def test_divergence_closed_form(dim, k):
     assert abs(dv - want) <= 1e-12 * want
     d = host(h.substeps(dev(x), 1e-3, 0, diag=True))
     assert abs(d[0, 1] - want) <= 1e-12 * want
+
+
+def test_warm_start_carry_across_calls():
+    """hopu_set_warm_start(1): a trajectory advanced in two calls equals the
+    one-call chain bit for bit (the extrapolation history continues), and
+    the second call's first solve starts from the extrapolated guess
+    (fewer iterations than from zero).  carry = 0: each call starts cold,
+    and the states agree to the solve tolerance."""
+    mesh, sp, x, c = case(2, (4, 3, 3), 3, noise=1e-3)
+    h = gpu_space(mesh, 3)
+    h.set_upwind(2)
+    h.set_solver(rtol=1e-13, max_it=2000)
+    dt = 5e-4
+    one = dev(x)
+    d1 = host(h.substeps(one, dt, 5, diag=True))
+    two = dev(x)
+    h.substeps(two, dt, 2)           # history starts here (this call cold)
+    h.set_warm_start(True)
+    d2 = host(h.substeps(two, dt, 3, diag=True))
+    assert torch.equal(one, two)
+    its_one, its_two = d1[1:, 3], d2[1:, 3]
+    print("PCG iterations, one call", its_one, "second call", its_two)
+    assert np.array_equal(its_one[2:], its_two)
+    h.set_warm_start(False)
+    cold = dev(x)
+    h.substeps(cold, dt, 2)
+    d3 = host(h.substeps(cold, dt, 3, diag=True))
+    assert d3[1, 3] > d2[1, 3]
+    check_primal(sp, host(cold), host(one), 1e-12, "cold restart vs one call")
+    from paper_2408_06698_amd import _lib as L
+    assert L.lib().hopu_set_warm_start(h.h, 2) == L.HOPU_EINVAL
+
+
+def test_count_nonfinite():
+    mesh, sp, x, c = case(2, (4, 3, 3), 3, noise=1e-3)
+    h = gpu_space(mesh, 3)
+    assert h.count_nonfinite(dev(x)) == 0
+    v = x.copy()
+    rng = np.random.default_rng(5)
+    idx = rng.choice(sp.n_dof, 37, replace=False)
+    v[idx[:20]] = np.nan
+    v[idx[20:30]] = np.inf
+    v[idx[30:]] = -np.inf
+    assert h.count_nonfinite(dev(v)) == 37
+    assert h.count_nonfinite(dev(x)) == 0     # the counter is cleared per call

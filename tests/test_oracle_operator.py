@@ -106,6 +106,31 @@ def test_advective_equals_conservative_on_divfree(which, nq, request):
         assert minv_norm(sp, a - c) <= 1e-11 * minv_norm(sp, c)
 
 
+@pytest.mark.parametrize("which", ["periodic3d", "wall3d"])
+def test_conservative_equals_advective_plus_divergence_term(which, request):
+    """Integration by parts on each element, for any u with continuous
+    normal component (divergence-free or not): the conservative form equals
+    the advective form of eq. (hopudefinition) plus int (div u)(u . phi);
+    the rules integrate both exactly, so the two agree to rounding."""
+    sp = request.getfixturevalue(which)[0]
+    x = np.random.default_rng(11).standard_normal(sp.n_dof)
+    t = sp.topo
+    dterm = np.zeros(sp.n_dof)
+    for eb in sp.batches(t.n_elems, sp.elem_batch_size()):
+        xl = sp.local(x, eb)
+        phi = sp.phys_vals(eb, sp.ref_vals)
+        gphi = sp.phys_grads(eb, sp.ref_grads)
+        u = np.einsum("bqid,bi->bqd", phi, xl)
+        div = np.einsum("bqiaa,bi->bq", gphi, xl)
+        wdx = sp.wq[None, :] * np.abs(t.detJ[eb])[:, None]
+        sp.scatter(dterm, eb, np.einsum("bq,bq,bqa,bqia->bi", wdx, div, u, phi))
+    assert minv_norm(sp, dterm) > 1e-2 * minv_norm(sp, O.residual(sp, x, 1))   # not divergence-free
+    for l in (-1, 1, sp.k):
+        c = O.residual(sp, x, l)
+        a = O.residual_advective(sp, x, l)
+        assert minv_norm(sp, c - (a + dterm)) <= 1e-12 * minv_norm(sp, c)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_central_part_skew_symmetric(dim):
     m = two_element_mesh(dim)

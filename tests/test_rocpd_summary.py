@@ -65,9 +65,9 @@ def test_traffic_scales_by_the_copy_calibration(tmp_path, capsys):
             vals[a.strip()] = b.strip()
     assert float(vals["fetch_scale"]) == pytest.approx(2.0)
     assert float(vals["write_scale"]) == pytest.approx(1.0)
-    assert float(vals["mass_bytes_per_launch"]) == pytest.approx(1000 * 1024 * 2 + 300 * 1024)
+    assert float(vals["mass_k3_bytes_per_launch"]) == pytest.approx(1000 * 1024 * 2 + 300 * 1024)
     assert vals["kernels_sha"] == R.kernels_sha(str(src)) and len(vals["kernels_sha"]) == 16
-    assert "elem_bytes_per_launch" not in vals
+    assert "elem_k3_bytes_per_launch" not in vals
 
 
 def test_traffic_requires_the_copy_last(tmp_path):
@@ -91,7 +91,7 @@ def test_busy_utilisation_arithmetic(tmp_path, capsys):
             "SQ_WAVE_CYCLES": 2.0 * cyc * simd / 4}         # two resident waves per SIMD
     _counters_db(db, [(1, MASS, n, v) for n, v in vals.items()])
     R.busy(db)
-    row = [l for l in capsys.readouterr().out.splitlines() if l.startswith("mass ")][0].split()
+    row = [l for l in capsys.readouterr().out.splitlines() if l.startswith("mass_k3 ")][0].split()
     assert int(row[1]) == 1
     assert float(row[2]) == pytest.approx(cyc)
     assert float(row[3]) == pytest.approx(cyc / 2400, abs=0.05)
