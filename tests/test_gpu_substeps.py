@@ -154,13 +154,14 @@ def test_profile_counts_and_stride():
     assert 0.5 < (ms4 / n4) / (ms1 / n1) < 2.0
 
 
-def test_pcg_direction_ring_wraps(monkeypatch):
+@pytest.mark.parametrize("cfg,n,k", [(2, (4, 3, 3), 3), (3, (3, 4, 3), 4)])
+def test_pcg_direction_ring_wraps(monkeypatch, cfg, n, k):
     """The PCG keeps its search directions in a ring and adds them to the
-    solution at each host check; with a ring of 2 or 3 (as on the largest
-    workloads, where the ring holds only a few vectors) the chunks stop at
+    solution at each host check; with a ring of 2 or 3 the chunks stop at
     the ring's capacity and the solve is bitwise the one with the full ring
-    (the same updates in the same order)."""
-    mesh, sp, x, c = case(2, (4, 3, 3), 3)
+    (the same updates in the same order); k = 4 runs the streamed-table
+    mass kernels."""
+    mesh, sp, x, c = case(cfg, n, k)
     rng = np.random.default_rng(3)
     b = rng.standard_normal(sp.n_dof)
     ref = None
@@ -169,7 +170,7 @@ def test_pcg_direction_ring_wraps(monkeypatch):
             monkeypatch.delenv("HOPU_TEST_RING", raising=False)
         else:
             monkeypatch.setenv("HOPU_TEST_RING", str(ring))
-        h = gpu_space(mesh, 3)
+        h = gpu_space(mesh, k)
         h.set_solver(rtol=1e-13, max_it=2000, check_every=5)
         w, its = h.mass_solve(dev(b), rtol=1e-13)
         w = host(w)
