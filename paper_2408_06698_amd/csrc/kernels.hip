@@ -1091,11 +1091,11 @@ struct MassTile {
 // Chunk c of a round (c mod NCH): the first contraction's passes p = 0, 1
 // (chunks p N1 + j, steps j K1 ..), then the second's (2 N1 + p N2 + j).
 // Laid out [step - first step][tile - first tile][lane].
-template <int D, int KK>
+template <typename T, int D, int KK>
 struct TileChunk {
-  const double* src;
+  const T* src;
   int nk, k0, nks, t0, nts;  // table K size; first step and steps; first tile and tiles
-  __device__ __forceinline__ TileChunk(const double* fin, const double* fout, int c) {
+  __device__ __forceinline__ TileChunk(const T* fin, const T* fout, int c) {
     using C = Cfg<D, KK>;
     using TT = MassTile<D, KK>;
     c %= TT::NCH;
@@ -1113,15 +1113,15 @@ struct TileChunk {
   }
 };
 
-template <int D, int KK>
-__device__ __forceinline__ void tile_fetch(const double* __restrict__ fin, const double* __restrict__ fout, int c,
-                                           double (&st)[MassTile<D, KK>::PER]) {
+template <typename T, int D, int KK>
+__device__ __forceinline__ void tile_fetch(const T* __restrict__ fin, const T* __restrict__ fout, int c,
+                                           T (&st)[MassTile<D, KK>::PER]) {
   using TT = MassTile<D, KK>;
-  const TileChunk<D, KK> k(fin, fout, c);
+  const TileChunk<T, D, KK> k(fin, fout, c);
   // an opaque copy of the base: the chunk's addresses do not depend on the
   // round, and the compiler would otherwise hoist every round's loads out of
   // the loop and hold all chunks in registers
-  const double* src = k.src;
+  const T* src = k.src;
   asm volatile("" : "+s"(src));
   int tid = (int)threadIdx.x;  // (likewise the per-thread offsets)
   asm volatile("" : "+v"(tid));
@@ -1134,8 +1134,8 @@ __device__ __forceinline__ void tile_fetch(const double* __restrict__ fin, const
     st[p] = src[ok ? (((t * k.nk + k.k0 + s) << 6) + l) : 0];
   }
 }
-template <int D, int KK>
-__device__ __forceinline__ void tile_store(double* __restrict__ buf, const double (&st)[MassTile<D, KK>::PER]) {
+template <typename T, int D, int KK>
+__device__ __forceinline__ void tile_store(T* __restrict__ buf, const T (&st)[MassTile<D, KK>::PER]) {
 #pragma unroll
   for (int p = 0; p < MassTile<D, KK>::PER; ++p) {
     const int i = (int)threadIdx.x + p * 64 * TILE_WPB;
@@ -1146,19 +1146,19 @@ __device__ __forceinline__ void tile_store(double* __restrict__ buf, const doubl
 // One pass of a contraction over tiles [T0, T0 + NT) of its output, K steps
 // 0 .. NKT in chunks of KC from the LDS window: acc[t] += A(step, T0 + t) b[step].
 // c: the round's index of the pass's first chunk; cb: the buffer holding it.
-template <int D, int KK, int NT, int NKT, int KC, int NB>
-__device__ __forceinline__ void tile_pass(const double* __restrict__ fin, const double* __restrict__ fout,
-                                          double (*buf)[MassTile<D, KK>::CH], int c, int& cb,
-                                          double (&st)[MassTile<D, KK>::PER], const double (&b)[NB], d4 (&acc)[NT],
-                                          int lane) {
-  using M = MF<double>;
+template <typename T, int D, int KK, int NT, int NKT, int KC, int NB>
+__device__ __forceinline__ void tile_pass(const T* __restrict__ fin, const T* __restrict__ fout,
+                                          T (*buf)[MassTile<D, KK>::CH], int c, int& cb,
+                                          T (&st)[MassTile<D, KK>::PER], const T (&b)[NB],
+                                          typename MF<T>::V (&acc)[NT], int lane) {
+  using M = MF<T>;
   constexpr int NCHK = (NKT + KC - 1) / KC;
 #pragma unroll
   for (int ch = 0; ch < NCHK; ++ch) {
-    tile_fetch<D, KK>(fin, fout, c + ch + 1, st);  // the round's next chunk
-    const double* const a = buf[cb];
+    tile_fetch<T, D, KK>(fin, fout, c + ch + 1, st);  // the round's next chunk
+    const T* const a = buf[cb];
     const int nks = NKT - ch * KC < KC ? NKT - ch * KC : KC;
-    double fr[2][NT];
+    T fr[2][NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) fr[0][t] = a[t * 64 + lane];
 #pragma unroll
@@ -1174,23 +1174,27 @@ __device__ __forceinline__ void tile_pass(const double* __restrict__ fin, const 
         MASS_SCHED_FENCE();
       }
     }
-    tile_store<D, KK>(buf[cb ^ 1], st);
+    tile_store<T, D, KK>(buf[cb ^ 1], st);
     cb ^= 1;
     __syncthreads();
   }
 }
 
-template <int D, int KK, int MODE>
+// T: the MFMA precision of the two contractions (FP32 for the preconditioner
+// of the mixed-precision substeps, with the FP32 row-map tables; the
+// gather, the mixing and the stores stay FP64).
+template <typename T, int D, int KK, int MODE>
 __global__ __launch_bounds__(64 * TILE_WPB, 1) void k_mass_tiled(const double* __restrict__ x,
                                                                  double* __restrict__ out, double* __restrict__ fs,
-                                                                 DevMesh mesh, const double* __restrict__ fin,
-                                                                 const double* __restrict__ fout,
+                                                                 DevMesh mesh, const T* __restrict__ fin,
+                                                                 const T* __restrict__ fout,
                                                                  const int* __restrict__ flag,
                                                                  double* __restrict__ part) {
   using C = Cfg<D, KK>;
   using TT = MassTile<D, KK>;
+  using VT = typename MF<T>::V;
   static_assert(D == 3, "the streamed-table kernel serves the 3D orders only");
-  __shared__ double buf[2][TT::CH];
+  __shared__ T buf[2][TT::CH];
   if (flag && *flag) return;  // uniform over the launch
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int nx = gridDim.x % 8 == 0 ? 8 : 1;
@@ -1203,9 +1207,9 @@ __global__ __launch_bounds__(64 * TILE_WPB, 1) void k_mass_tiled(const double* _
   const int64_t off = mesh.F * C::NF;
   double* const trash = fs + 2 * mesh.F * C::NF;
   double dot = 0.0;
-  double st[TT::PER];
-  tile_fetch<D, KK>(fin, fout, 0, st);  // the round's first chunk
-  tile_store<D, KK>(buf[0], st);
+  T st[TT::PER];
+  tile_fetch<T, D, KK>(fin, fout, 0, st);  // the round's first chunk
+  tile_store<T, D, KK>(buf[0], st);
   __syncthreads();
   int cb = 0;  // the buffer holding the chunk about to be used
   for (int64_t r = 0; r < rounds; ++r) {
@@ -1220,34 +1224,34 @@ __global__ __launch_bounds__(64 * TILE_WPB, 1) void k_mass_tiled(const double* _
     const double sfac = MODE == 1 ? 0.5 / md.nf : md.nf;
     const double sint = MODE == 1 ? 1.0 / md.si : md.si;
     const bool fok = valid && g <= D && md.ix.fid >= 0;
-    double xh[C::NK];
+    T xh[C::NK];
 #pragma unroll
     for (int kk = 0; kk < C::NK; ++kk) {
       const bool ok = mass_is_facet<D, KK>(kk, g) ? fok : valid && mass_int_row<D, KK>(kk, g) < C::NINT;
-      xh[kk] = ok ? md.x[kk] * (mass_is_facet<D, KK>(kk, g) ? sfac : sint) : 0.0;
+      xh[kk] = (T)(ok ? md.x[kk] * (mass_is_facet<D, KK>(kk, g) ? sfac : sint) : 0.0);
     }
     // ---- first contraction y = fin . xh, in two passes over its tiles
     double y[C::NMT][4];
     {
-      d4 acc[TT::H1];
+      VT acc[TT::H1];
 #pragma unroll
-      for (int t = 0; t < TT::H1; ++t) acc[t] = vzero<d4>();
-      tile_pass<D, KK, TT::H1, C::NK, TT::K1, C::NK>(fin, fout, buf, 0, cb, st, xh, acc, lane);
+      for (int t = 0; t < TT::H1; ++t) acc[t] = vzero<VT>();
+      tile_pass<T, D, KK, TT::H1, C::NK, TT::K1, C::NK>(fin, fout, buf, 0, cb, st, xh, acc, lane);
 #pragma unroll
       for (int t = 0; t < TT::H1; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) y[t][i] = acc[t][i];
+        for (int i = 0; i < 4; ++i) y[t][i] = (double)acc[t][i];
     }
     {
       constexpr int NT = C::NMT - TT::H1;
-      d4 acc[NT];
+      VT acc[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = vzero<d4>();
-      tile_pass<D, KK, NT, C::NK, TT::K1, C::NK>(fin, fout, buf, TT::N1, cb, st, xh, acc, lane);
+      for (int t = 0; t < NT; ++t) acc[t] = vzero<VT>();
+      tile_pass<T, D, KK, NT, C::NK, TT::K1, C::NK>(fin, fout, buf, TT::N1, cb, st, xh, acc, lane);
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) y[TT::H1 + t][i] = acc[t][i];
+        for (int i = 0; i < 4; ++i) y[TT::H1 + t][i] = (double)acc[t][i];
     }
     // ---- component mixing (as in mass_compute) and the local x . y share;
     // the geometry is read again here rather than held through the MFMAs
@@ -1283,7 +1287,7 @@ __global__ __launch_bounds__(64 * TILE_WPB, 1) void k_mass_tiled(const double* _
           Gs[a][bb] = (Gm[a1][b1] * Gm[a2][b2] - Gm[a1][b2] * Gm[a2][b1]) * sd;
         }
     }
-    double yb[C::NMQ];  // the mixed rows, by step of the second contraction
+    T yb[C::NMQ];  // the mixed rows, by step of the second contraction
 #pragma unroll
     for (int blk = 0; blk < C::NPK; ++blk) {
       double t[D];
@@ -1300,37 +1304,37 @@ __global__ __launch_bounds__(64 * TILE_WPB, 1) void k_mass_tiled(const double* _
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         dot += y[(blk * D + a) / 4][(blk * D + a) % 4] * t[a];
-        yb[blk * D + a] = t[a];
+        yb[blk * D + a] = (T)t[a];
       }
     }
 #pragma unroll
-    for (int rq = D * C::NPK; rq < C::NMQ; ++rq) yb[rq] = 0.0;
+    for (int rq = D * C::NPK; rq < C::NMQ; ++rq) yb[rq] = (T)0;
     // ---- second contraction o = fout . yb, in two passes, stored per pass
     double* const fsrow = fs + ((int64_t)md.ix.side * mesh.F + (md.ix.fid >= 0 ? md.ix.fid : 0)) * C::NF;
     double* const irow = out + off + (valid ? e : 0) * C::NINT;
-    auto store = [&](const d4& ot, int jt) {
+    auto store = [&](const VT& ot, int jt) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int s = 4 * jt + i;  // register i of tile jt holds step s of this lane
         if (s < C::NK)
-          mass_store<D, KK>(s, g, ot[i], i % 2 == 0 && i < 3 ? ot[i + 1] : 0.0, sfac, sint, fok, fsrow, valid,
-                            irow, trash);
+          mass_store<D, KK>(s, g, (double)ot[i], i % 2 == 0 && i < 3 ? (double)ot[i + 1] : 0.0, sfac, sint, fok,
+                            fsrow, valid, irow, trash);
       }
     };
     {
-      d4 o[TT::H2];
+      VT o[TT::H2];
 #pragma unroll
-      for (int t = 0; t < TT::H2; ++t) o[t] = vzero<d4>();
-      tile_pass<D, KK, TT::H2, C::NMQ, TT::K2, C::NMQ>(fin, fout, buf, 2 * TT::N1, cb, st, yb, o, lane);
+      for (int t = 0; t < TT::H2; ++t) o[t] = vzero<VT>();
+      tile_pass<T, D, KK, TT::H2, C::NMQ, TT::K2, C::NMQ>(fin, fout, buf, 2 * TT::N1, cb, st, yb, o, lane);
 #pragma unroll
       for (int t = 0; t < TT::H2; ++t) store(o[t], t);
     }
     {
       constexpr int NT = C::NJT - TT::H2;
-      d4 o[NT];
+      VT o[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) o[t] = vzero<d4>();
-      tile_pass<D, KK, NT, C::NMQ, TT::K2, C::NMQ>(fin, fout, buf, 2 * TT::N1 + TT::N2, cb, st, yb, o, lane);
+      for (int t = 0; t < NT; ++t) o[t] = vzero<VT>();
+      tile_pass<T, D, KK, NT, C::NMQ, TT::K2, C::NMQ>(fin, fout, buf, 2 * TT::N1 + TT::N2, cb, st, yb, o, lane);
 #pragma unroll
       for (int t = 0; t < NT; ++t) store(o[t], TT::H2 + t);
     }
@@ -1423,18 +1427,19 @@ int launch_mass(hipStream_t s, int mode, const double* x, double* out, double* f
     return (int)blocks;
   } else if constexpr (D == 3) {
     // tables streamed through LDS by blocks of TILE_WPB waves (one block
-    // per CU); no FP32 form (the preconditioner runs in FP64)
+    // per CU)
     const int64_t blocks = std::min<int64_t>((waves + TILE_WPB - 1) / TILE_WPB, MASS_BLOCKS);
     const dim3 thr(64 * TILE_WPB);
     if (mode == 0)
-      HOPU_LAUNCH((k_mass_tiled<D, KK, 0>), dim3((unsigned)blocks), thr, 0, s, x, out, fs, mesh, fin, fout, flag,
-                  part);
+      HOPU_LAUNCH((k_mass_tiled<double, D, KK, 0>), dim3((unsigned)blocks), thr, 0, s, x, out, fs, mesh, fin, fout,
+                  flag, part);
+    else if (fin32 && fout32)
+      HOPU_LAUNCH((k_mass_tiled<float, D, KK, 1>), dim3((unsigned)blocks), thr, 0, s, x, out, fs, mesh, fin32,
+                  fout32, flag, part);
     else
-      HOPU_LAUNCH((k_mass_tiled<D, KK, 1>), dim3((unsigned)blocks), thr, 0, s, x, out, fs, mesh, fin, fout, flag,
-                  part);
+      HOPU_LAUNCH((k_mass_tiled<double, D, KK, 1>), dim3((unsigned)blocks), thr, 0, s, x, out, fs, mesh, fin, fout,
+                  flag, part);
     (void)sizeof(C);
-    (void)fin32;
-    (void)fout32;
     return (int)blocks;
   } else {
     const int64_t blocks = (waves + 3) / 4;
