@@ -244,6 +244,44 @@ class Ctx:
         return float(self.torch.dot(d, w))
 
 
+def small_latency(torch):
+    """Launch-bound latency on the 2D periodic Taylor-Green workload (16x16x2
+    = 512 triangles, k = 2, 3,840 DoFs): one convection apply (averaged over
+    200 back to back) and one substep (50 substeps in one call, so the PCG's
+    host checks are included)."""
+    import numpy as np
+    import synth
+    from synth.configs import coefficient_noise
+    from paper_2408_06698_amd.hopu import Hopu
+    mesh, field, cfg = synth.make_config(1)
+    h = Hopu(2, cfg["k"], mesh.elem_vid, mesh.elem_xyz)
+    h.set_upwind(cfg["l"])
+    h.set_solver(rtol=1e-13, max_it=500, check_every=4)
+    u = h.interpolate(field, n1d=cfg["k"] + 1)
+    u += torch.tensor(coefficient_noise(1, h.n_dof, cfg["noise"]), device=u.device)
+    r = h.zeros()
+    h.apply(u, r)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(200):
+        h.apply(u, r)
+    ev[1].record()
+    h.substeps(u, cfg["dt"], 5)
+    torch.cuda.synchronize()
+    ev[2].record()
+    h.substeps(u, cfg["dt"], 50)
+    ev[3].record()
+    torch.cuda.synchronize()
+    out = {"workload": "2d_periodic_tg_k2: [0,1]^2 periodic, 16x16x2=512 triangles, BDM k=2, "
+                       f"{h.n_dof} DoFs, l=1, dt=1e-3",
+           "apply_us": ev[0].elapsed_time(ev[1]) / 200 * 1e3,
+           "substep_us": ev[2].elapsed_time(ev[3]) / 50 * 1e3,
+           "note": "launch-bound: each apply is 3 launches, each PCG iteration 4 plus a host check every 4"}
+    h.close()
+    return out
+
+
 def roofline(c, prof):
     """Roofline of the kernel with the largest summed time in the timed
     region: algorithmic flops per launch / average launch duration (the
@@ -471,6 +509,9 @@ def main():
         out["secondary"] = sec
         h2.close()
         log("secondary done")
+    if not args.no_secondary and fits("small_latency", 15):
+        out["small_latency"] = small_latency(torch)
+        log("small-workload latency done")
     out["wall_s"] = time.time() - t_start
     print(json.dumps(out))
 

@@ -124,19 +124,44 @@ def _fourier_sum(kv, sin_coef, cos_coef):
     return f
 
 
+def _fourier_sum6(kv, sin_coef, cos_coef):
+    """Two three-component Fourier sums at once (coefficients [m][6]): one
+    evaluation of each phase serves both.  On the GPU the modes go in chunks
+    of 512 (a chunk's phase matrix is the traffic), on the host of 64."""
+    def f(x):
+        ns = _ns(x)
+        shp = x.shape[:-1]
+        xf = x.reshape(-1, x.shape[-1])
+        if ns is np:
+            out = np.zeros((xf.shape[0], 6))
+            K, S, C = kv, sin_coef, cos_coef
+            chunk = 64
+        else:
+            out = ns.zeros((xf.shape[0], 6), dtype=xf.dtype, device=xf.device)
+            K = ns.as_tensor(kv, dtype=xf.dtype, device=xf.device)
+            S = ns.as_tensor(sin_coef, dtype=xf.dtype, device=xf.device)
+            C = ns.as_tensor(cos_coef, dtype=xf.dtype, device=xf.device)
+            chunk = 512
+        for m0 in range(0, kv.shape[0], chunk):
+            ph = xf @ K[m0:m0 + chunk].T
+            out = out + ns.sin(ph) @ S[m0:m0 + chunk] + ns.cos(ph) @ C[m0:m0 + chunk]
+        return out.reshape(shp + (6,))
+    return f
+
+
 def _curl_f_times_fourier(kv, a, b, fy, dfy):
     """u = curl(f(y) A), A = sum a_m cos(k.x) + b_m sin(k.x):
     u = f curl A + grad f x A, grad f = (0, f'(y), 0)."""
     ca = np.cross(kv, a)
     cb = np.cross(kv, b)
-    inner = _fourier_sum(kv, -ca, cb)   # curl A
-    potA = _fourier_sum(kv, b, a)        # A itself
+    # columns 0..2: curl A (sin: -n x a, cos: n x b); 3..5: A (sin: b, cos: a)
+    both = _fourier_sum6(kv, np.concatenate([-ca, b], 1), np.concatenate([cb, a], 1))
 
     def f(x):
         ns = _ns(x)
         y = x[..., 1]
-        cA = inner(x)
-        A = potA(x)
+        cAA = both(x)
+        cA, A = cAA[..., 0:3], cAA[..., 3:6]
         fp = dfy(y)
         gx = fp * A[..., 2]        # (0, f', 0) x A = (f' A_z, 0, -f' A_x)
         gz = -fp * A[..., 0]
