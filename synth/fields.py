@@ -127,7 +127,8 @@ def _fourier_sum(kv, sin_coef, cos_coef):
 def _fourier_sum6(kv, sin_coef, cos_coef):
     """Two three-component Fourier sums at once (coefficients [m][6]): one
     evaluation of each phase serves both.  On the GPU the modes go in chunks
-    of 512 (a chunk's phase matrix is the traffic), on the host of 64."""
+    of up to 512 with the phase matrix held to 2^30 entries (it and its sine
+    and cosine are the memory and the traffic), on the host in chunks of 64."""
     def f(x):
         ns = _ns(x)
         shp = x.shape[:-1]
@@ -141,7 +142,7 @@ def _fourier_sum6(kv, sin_coef, cos_coef):
             K = ns.as_tensor(kv, dtype=xf.dtype, device=xf.device)
             S = ns.as_tensor(sin_coef, dtype=xf.dtype, device=xf.device)
             C = ns.as_tensor(cos_coef, dtype=xf.dtype, device=xf.device)
-            chunk = 512
+            chunk = max(16, min(512, (1 << 30) // max(xf.shape[0], 1)))
         for m0 in range(0, kv.shape[0], chunk):
             ph = xf @ K[m0:m0 + chunk].T
             out = out + ns.sin(ph) @ S[m0:m0 + chunk] + ns.cos(ph) @ C[m0:m0 + chunk]
