@@ -18,8 +18,8 @@ TRAFFIC_KERNELS = [
     ("elem_k3", "k_elem<double, 3, 3, 0>"),
     ("elem_fp32_k3", "k_elem<float, 3, 3, 0>"),
     ("modal_k3", "k_mass_lds<double, 3, 3, 2>"),
-    ("mass_k5", "k_mass_tiled<3, 5, 0>"),
-    ("prec_k5", "k_mass_tiled<3, 5, 1>"),
+    ("mass_k5", "k_mass_tiled<double, 3, 5, 0>"),
+    ("prec_k5", "k_mass_tiled<double, 3, 5, 1>"),
     ("elem_k5", "k_elem<double, 3, 5, 0>"),
     ("elem_fp32_k5", "k_elem<float, 3, 5, 0>"),
     ("modal_k5", "k_modal<double, 3, 5>"),
@@ -95,7 +95,8 @@ BUSY_KERNELS = TRAFFIC_KERNELS + [("elem_bf16x2_k3", "k_elem<float, 3, 3, 2>"),
                                   ("elem_bf16x3_k3", "k_elem<float, 3, 3, 3>"),
                                   ("prec_fp32_k3", "k_mass_lds<float, 3, 3, 1>"),
                                   ("elem_bf16x2_k5", "k_elem<float, 3, 5, 2>"),
-                                  ("elem_bf16x3_k5", "k_elem<float, 3, 5, 3>")]
+                                  ("elem_bf16x3_k5", "k_elem<float, 3, 5, 3>"),
+                                  ("prec_fp32_k5", "k_mass_tiled<float, 3, 5, 1>")]
 N_SIMD = 256 * 4  # MI355X: 256 CUs, 4 SIMDs each
 N_XCD = 8
 
