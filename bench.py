@@ -54,7 +54,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", type=int, default=5, choices=(2, 5),
                     help="main line: 5 (channel, k=5) or 2 (periodic Taylor-Green, k=3)")
     ap.add_argument("--adjoint-steps", type=int, default=1,
