@@ -254,30 +254,47 @@ def small_latency(torch):
     from synth.configs import coefficient_noise
     from paper_2408_06698_amd.hopu import Hopu
     mesh, field, cfg = synth.make_config(1)
-    h = Hopu(2, cfg["k"], mesh.elem_vid, mesh.elem_xyz)
-    h.set_upwind(cfg["l"])
-    h.set_solver(rtol=1e-13, max_it=500, check_every=4)
-    u = h.interpolate(field, n1d=cfg["k"] + 1)
-    u += torch.tensor(coefficient_noise(1, h.n_dof, cfg["noise"]), device=u.device)
-    r = h.zeros()
-    h.apply(u, r)
-    torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    ev[0].record()
-    for _ in range(200):
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        h = Hopu(2, cfg["k"], mesh.elem_vid, mesh.elem_xyz, stream=st)
+        h.set_upwind(cfg["l"])
+        h.set_solver(rtol=1e-13, max_it=500, check_every=4)
+        u = h.interpolate(field, n1d=cfg["k"] + 1)
+        u += torch.tensor(coefficient_noise(1, h.n_dof, cfg["noise"]), device=u.device)
+        r = h.zeros()
         h.apply(u, r)
-    ev[1].record()
-    h.substeps(u, cfg["dt"], 5)
     torch.cuda.synchronize()
-    ev[2].record()
-    h.substeps(u, cfg["dt"], 50)
-    ev[3].record()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    with torch.cuda.stream(st):
+        ev[0].record(st)
+        for _ in range(200):
+            h.apply(u, r)
+        ev[1].record(st)
+        h.substeps(u, cfg["dt"], 5)
+        torch.cuda.synchronize()
+        ev[2].record(st)
+        h.substeps(u, cfg["dt"], 50)
+        ev[3].record(st)
+    torch.cuda.synchronize()
+    # the apply captured into a HIP graph (10 applies per graph, 20 replays)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        for _ in range(10):
+            h.apply(u, r)
+    torch.cuda.synchronize()
+    ev[4].record()
+    for _ in range(20):
+        g.replay()
+    ev[5].record()
     torch.cuda.synchronize()
     out = {"workload": "2d_periodic_tg_k2: [0,1]^2 periodic, 16x16x2=512 triangles, BDM k=2, "
                        f"{h.n_dof} DoFs, l=1, dt=1e-3",
            "apply_us": ev[0].elapsed_time(ev[1]) / 200 * 1e3,
+           "apply_us_hip_graph": ev[4].elapsed_time(ev[5]) / 200 * 1e3,
            "substep_us": ev[2].elapsed_time(ev[3]) / 50 * 1e3,
-           "note": "launch-bound: each apply is 3 launches, each PCG iteration 4 plus a host check every 4"}
+           "note": "launch-bound: each apply is 3 launches, each PCG iteration 4 plus a host check every 4; "
+                   "the graph replays 10 captured applies per launch"}
+    del g
     h.close()
     return out
 

@@ -135,7 +135,10 @@ hopu_status hopu_get_facet_orders(hopu_ctx ctx, int8_t* l_dev);
 hopu_status hopu_set_solver(hopu_ctx ctx, double rtol, int max_it, int check_every);
 
 /* r = C(u) u: the convection residual (dual vector).  u, r dev [n_dof].
- * terms: bitmask of HOPU_TERM_*.  Asynchronous. */
+ * terms: bitmask of HOPU_TERM_*.  Asynchronous: only kernel launches on the
+ * context's stream (no allocation, copy, memset or synchronisation while
+ * per-kernel timing is off), so the call may be captured into a HIP graph
+ * on that stream. */
 hopu_status hopu_convection_apply(hopu_ctx ctx, const double* u, double* r,
                                   int terms, hopu_precision prec);
 
