@@ -3,6 +3,7 @@
 #include "../../include/hopu.h"
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cmath>
 #include <cstdint>
@@ -19,6 +20,15 @@
 #include "launch.hpp"
 #include "launch_events.hpp"
 #include "vec.hpp"
+
+// A named range around an entry point's host work and launches, for
+// rocprofv3's marker trace (roctx; a host call, no stream operation).
+struct RocRange {
+  explicit RocRange(const char* name) { roctxRangePushA(name); }
+  ~RocRange() { roctxRangePop(); }
+  RocRange(const RocRange&) = delete;
+  RocRange& operator=(const RocRange&) = delete;
+};
 
 using namespace hopu;
 
@@ -559,6 +569,7 @@ static hopu_status check_prec(hopu_ctx ctx, hopu_precision prec) {
 }
 
 extern "C" hopu_status hopu_convection_apply(hopu_ctx ctx, const double* u, double* r, int terms, hopu_precision prec) {
+  RocRange range("hopu_convection_apply");
   if (!ctx) return HOPU_EINVAL;
   if (!u || !r) return fail(ctx, HOPU_EINVAL, "NULL vector");
   if (terms < 0 || terms > 7) return fail(ctx, HOPU_EINVAL, "terms must be a HOPU_TERM_* mask");
@@ -655,6 +666,7 @@ static hopu_status pcg(hopu_ctx ctx, const double* b, double* x, double rtol, in
 // the element-wise recovery of u~.
 extern "C" hopu_status hopu_project(hopu_ctx ctx, const double* ustar, double* unew, double rtol, int max_it,
                                     int* iters) {
+  RocRange range("hopu_project");
   if (!ctx) return HOPU_EINVAL;
   if (!ustar || !unew) return fail(ctx, HOPU_EINVAL, "NULL vector");
   if (ustar == unew) return fail(ctx, HOPU_EINVAL, "u* and u_new must be different vectors");
@@ -766,6 +778,7 @@ done:
 }
 
 extern "C" hopu_status hopu_mass_solve(hopu_ctx ctx, const double* r, double* w, double rtol, int max_it, int* iters) {
+  RocRange range("hopu_mass_solve");
   if (!ctx) return HOPU_EINVAL;
   if (!r || !w) return fail(ctx, HOPU_EINVAL, "NULL vector");
   if (max_it < 1) return fail(ctx, HOPU_EINVAL, "max_it must be >= 1");
@@ -906,6 +919,7 @@ extern "C" hopu_status hopu_adapt_upwind(hopu_ctx ctx, const double* u) {
 
 extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_steps, hopu_precision prec,
                                      double* diag_dev) {
+  RocRange range("hopu_substeps");
   if (!ctx) return HOPU_EINVAL;
   if (!u) return fail(ctx, HOPU_EINVAL, "NULL vector");
   if (n_steps < 0) return fail(ctx, HOPU_EINVAL, "n_steps must be >= 0");
@@ -937,6 +951,7 @@ extern "C" hopu_status hopu_substeps(hopu_ctx ctx, double* u, double dt, int n_s
       hopu_status sa = adapt_now(ctx, u);
       if (sa) return sa;
     }
+    RocRange step_range("substep");
     hopu_status st = do_apply(ctx, u, ctx->rc, HOPU_TERM_ALL, prec, nullptr);
     if (st) return st;
     double* w = wh[2];
@@ -1229,6 +1244,7 @@ static hopu_status substep(hopu_ctx ctx, double* u, double* w, double dt, hopu_p
 extern "C" hopu_status hopu_substeps_vjp(hopu_ctx ctx, const double* u0, double dt, int n_steps, int ckpt_every,
                                          const double* lam_N, double* lam_0, hopu_precision prec, void* ws,
                                          int64_t ws_bytes) {
+  RocRange range("hopu_substeps_vjp");
   if (!ctx) return HOPU_EINVAL;
   if (!u0 || !lam_N || !lam_0 || !ws) return fail(ctx, HOPU_EINVAL, "NULL pointer");
   if (n_steps < 0 || ckpt_every < 1 || !std::isfinite(dt)) return fail(ctx, HOPU_EINVAL, "bad step arguments");

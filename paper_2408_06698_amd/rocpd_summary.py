@@ -2,6 +2,8 @@
 
     python -m paper_2408_06698_amd.rocpd_summary trace <db> [top]
         per kernel name: launches, average / busy-average / max / total duration
+    python -m paper_2408_06698_amd.rocpd_summary ranges <db>
+        the library's roctx ranges (marker trace): calls, average / total time
     python -m paper_2408_06698_amd.rocpd_summary traffic <fetch_db> <write_db> <kernels.hip>
         HBM bytes per launch from a FETCH_SIZE and a WRITE_SIZE run, scaled by
         what the counters read for the largest plain device copy in the runs
@@ -42,6 +44,20 @@ def trace(db, top=20):
                          (r[0], r[5])).fetchone()
         print(f"{r[1]:8d} {r[2]/1e3:10.2f} {busy[0]:7d} {busy[1]/1e3:11.2f} {r[5]/1e3:9.2f} {r[3]/1e6:9.3f} "
               f"{100*r[3]/tot:6.2f}  {r[0][:110]}")
+
+
+def ranges(db):
+    """The library's roctx ranges (one per entry point call, and one per
+    substep inside hopu_substeps): count, average and total host duration
+    per range name, from a --marker-trace run."""
+    c = sqlite3.connect(db)
+    rows = c.execute("select json_extract(extdata, '$.message') as msg, count(*), avg(duration), sum(duration) "
+                     "from regions where category like 'MARKER%' group by msg order by sum(duration) desc").fetchall()
+    print("host time between the range's push and pop (the entry point's launches, its host work and, for")
+    print("calls that synchronise, the wait for the GPU)")
+    print(f"{'calls':>6} {'avg_ms':>10} {'total_ms':>10}  range")
+    for msg, n, avg, tot in rows:
+        print(f"{n:6d} {avg / 1e6:10.3f} {tot / 1e6:10.3f}  {msg}")
 
 
 def _counter(db, name):
@@ -138,5 +154,7 @@ if __name__ == "__main__":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "busy":
         busy(sys.argv[2])
+    elif sys.argv[1] == "ranges":
+        ranges(sys.argv[2])
     else:
         trace(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 20)

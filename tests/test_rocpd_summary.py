@@ -98,3 +98,22 @@ def test_busy_utilisation_arithmetic(tmp_path, capsys):
     assert float(row[4]) == pytest.approx(0.5)
     assert float(row[5]) == pytest.approx(0.25)
     assert float(row[6]) == pytest.approx(2.0)
+
+
+def test_ranges_grouped_by_message(tmp_path, capsys):
+    db = str(tmp_path / "r.db")
+    c = sqlite3.connect(db)
+    c.execute("create table regions (category text, extdata text, duration integer)")
+    rows = [("MARKER_CORE_RANGE_API", '{"message":"substep"}', 10_000_000)] * 3 + \
+           [("MARKER_CORE_RANGE_API", '{"message":"hopu_substeps"}', 31_000_000),
+            ("HIP_RUNTIME_API", '{"message":"ignored"}', 5)]
+    c.executemany("insert into regions values (?, ?, ?)", rows)
+    c.commit()
+    c.close()
+    R.ranges(db)
+    out = capsys.readouterr().out.splitlines()
+    sub = [l for l in out if l.endswith(" substep")][0].split()
+    assert int(sub[0]) == 3 and float(sub[1]) == pytest.approx(10.0) and float(sub[2]) == pytest.approx(30.0)
+    assert not any("ignored" in l for l in out)
+    # ordered by total time: hopu_substeps (31 ms) before substep (30 ms)
+    assert out.index([l for l in out if l.endswith("hopu_substeps")][0]) < out.index([l for l in out if l.endswith(" substep")][0])
