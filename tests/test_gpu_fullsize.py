@@ -130,8 +130,8 @@ def _mnorm(h, v):
 def test_fullsize_channel_k5():
     """Workload 5 (1,769,472 tets, k = 5, 222.8M DoFs) at full size: apply
     (FP64, FP32-MFMA, hi/mid/lo), transpose Jacobian and mass rows of the
-    sample against the oracle; the PCG mass solve checked by what holds at
-    any size (w = M^-1 (M x) returns x)."""
+    sample against the oracle; the PCG mass solve and one substep of the
+    bench's configuration checked by what holds at any size."""
     mesh, sp, x, c, patch, rows_f, rows_i, xs = _setup(5)
     h = gpu_space(mesh, c["k"])
     h.set_upwind(c["l"])
@@ -150,6 +150,35 @@ def test_fullsize_channel_k5():
     e = _mnorm(h, w - u) / _mnorm(h, u)
     print(f"k5 PCG: {its} iterations, ||w - x||_M / ||x||_M = {e:.2e}")
     assert e <= 1e-12
+    del w, b
+    # one substep of the bench's configuration from the workload's own field
+    # (sampled on the GPU), held by what holds at any size: the update w =
+    # (u - u_1)/dt solves M w = r(u), i.e. ||M w - r||_{M^-1} / ||r||_{M^-1}
+    # at the PCG tolerance (the M^-1 norms by a CG solve to 1e-4, which
+    # approaches them from below)
+    h.set_solver(rtol=1e-13, max_it=3000, check_every=16)
+    from synth import fields
+    field = fields.spectral_wall_field(c["seed"], lengths=c["lengths"])
+
+    def chunked(p):  # the field sampled in chunks of 2M points, as the bench does
+        flat = p.reshape(-1, 3)
+        out = torch.empty_like(flat)
+        for s0 in range(0, flat.shape[0], 1 << 21):
+            out[s0:s0 + (1 << 21)] = field(flat[s0:s0 + (1 << 21)])
+        return out.reshape(p.shape)
+    u0 = h.interpolate(chunked, n1d=c["k"] + 1)
+    r0 = h.apply(u0)
+    u1 = u0.clone()
+    diag = host(h.substeps(u1, c["dt"], 1, diag=True))
+    wst = (u0 - u1) / c["dt"]
+    d = h.mass_apply(wst) - r0
+
+    def minv2(v):
+        z, _ = h.mass_solve(v, rtol=1e-4, max_it=3000)
+        return float(torch.dot(v, z))
+    e = (minv2(d) / minv2(r0)) ** 0.5
+    print(f"k5 substep: {diag[1, 3]:.0f} PCG iterations, ||M w - r||_M^-1 / ||r||_M^-1 = {e:.2e}")
+    assert e <= 1e-11
 
 
 def test_fullsize_graded_k4_mixed_chain():
