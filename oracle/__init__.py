@@ -22,11 +22,15 @@ transitional turbulent flows"):
   * the explicit convection substep u <- u - dt M^{-1} r(u) (the explicit part
     of step 1, eq. (MCS_step1));
   * energy, divergence and upwind-dissipation diagnostics;
-  * the transpose Jacobian of r and of the substep chain.
+  * the transpose Jacobian of r and of the substep chain;
+  * the projection step (section 2.3, eq. (MCS_step2));
+  * the implicit Stokes step (section 2.2 spaces Sigma_h, W_h, V^_h and forms
+    a_h, b_2h; section 2.3 eq. (MCS_step1), its static condensation and the
+    element-wise BDDC preconditioner).
 
 Everything is evaluated in physical coordinates with element and facet loops
 (vectorised over batches).  Parity status of each function is stated in its
 docstring, and so is each reading taken where the paper does not fix an
 item (the quadrature rule, the basis, the adaptive thresholds' ties).
 """
-from . import quadrature, basis, mesh, space, operator  # noqa: F401
+from . import quadrature, basis, mesh, space, operator, projection, stokes  # noqa: F401
