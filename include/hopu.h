@@ -271,6 +271,52 @@ const char* hopu_last_error(hopu_ctx ctx);
 /* Frees everything the context owns.  NULL-safe. */
 void hopu_destroy(hopu_ctx ctx);
 
+/* ---- implicit Stokes step (paper section 2.2: the stress space Sigma_h of
+ * trace-free P^{k+1} matrices with nt-traces of degree k on interior facets,
+ * the skew space W_h = P^k, the tangential facet space V^_h = P^k with u^ = 0
+ * on walls, the forms a_h and b_2h; section 2.3: eq. (MCS_step1), its matrix
+ * form, the static condensation S = A - B M^-1 B^t of sigma and gamma, and
+ * PCG with the element-wise BDDC preconditioner C^-1 = R S_BDDC^-1 R^t,
+ * without primal constraints).  Built for 2D k <= 4 and 3D k <= 3
+ * (HOPU_EUNSUPPORTED otherwise).
+ *
+ * Unknown vector X (device, FP64, n_total = n_dof + n_uhat entries): the
+ * velocity DoFs in the layout of the other calls, then u^ per interior facet
+ * (facet ascending, tangent c = 0..d-2, mode j = 0..n_f-1 fastest) with
+ * u^|_F(x(s)) = sum_c sum_j u^_{F,c,j} psi_j(s) t_{F,c}: psi_j the facet
+ * polynomials of the velocity DoFs on the facet's sorted-vertex
+ * parametrisation, t_{F,1} = (x_b - x_a)/|x_b - x_a| from its first two
+ * sorted vertices, t_{F,2} = n_F x t_{F,1} (3D).  div of a matrix field is
+ * row-wise; sigma_nt = sigma n - (n . sigma n) n.
+ *
+ * hopu_stokes_sizes: n_total, n_uhat and the unknowns per element of S_T
+ *   (any pointer may be NULL).
+ * hopu_stokes_setup: nu > 0, dt > 0.  Builds on the GPU, per element, S_T on
+ *   its velocity and u^ unknowns and S_T^-1, and keeps both in device memory
+ *   (2 E nx^2 doubles, nx from hopu_stokes_sizes).  Allocates on its first
+ *   call (HOPU_ENOMEM if that fails) and a set-up scratch for each call;
+ *   HOPU_EINVAL if an element matrix is not positive definite.  Re-call it
+ *   when nu or dt changes.
+ * hopu_stokes_apply: y = S x (assembled; x and y distinct, n_total each).
+ * hopu_stokes_precond: y = C^-1 x = R S_BDDC^-1 R^t x (R averages the two
+ *   copies of every facet unknown).
+ * hopu_stokes_step: one step of eq. (MCS_step1) from u^n (n_dof entries):
+ *   PCG on S X = [M u^n/dt - r(u^n); 0] with C^-1 from X = 0, where r is the
+ *   FP64 convection residual of hopu_convection_apply with the context's
+ *   upwind setting when with_convection != 0 and zero otherwise.  Writes X
+ *   = [u*; u^] to x (n_total entries) and the iteration count to *iters
+ *   (may be NULL).  Stops when the C^-1 norm of the residual falls below rtol
+ *   times its initial value; HOPU_ENOCONV after max_it iterations (x then
+ *   holds the last iterate).  Synchronises the context's stream.
+ * Every Stokes call except hopu_stokes_sizes needs hopu_stokes_setup first
+ * (HOPU_EINVAL otherwise). */
+hopu_status hopu_stokes_sizes(hopu_ctx ctx, int64_t* n_total, int64_t* n_uhat, int* n_elem_unknowns);
+hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt);
+hopu_status hopu_stokes_apply(hopu_ctx ctx, const double* x, double* y);
+hopu_status hopu_stokes_precond(hopu_ctx ctx, const double* x, double* y);
+hopu_status hopu_stokes_step(hopu_ctx ctx, const double* un, int with_convection, double* x, double rtol,
+                             int max_it, int* iters);
+
 /* ---- host-only inspection (no HIP calls; used by CPU tests) ------------
  * hopu_host_tables: reference tables for (dim, k): which = 0 volume points
  * [nqv][d], 1 volume weights, 2 V [nqv][nP] (internal modal basis), 3 facet
@@ -281,12 +327,20 @@ void hopu_destroy(hopu_ctx ctx);
  * are the transpose-Jacobian kernel's volume tables), and split-BF16 copies
  * as raw bfloat16 bit patterns (one per double): 9 vol_dVT hi/lo, 10 vol_dVT
  * hi/mid/lo, 12 fac_Tr hi/mid/lo, 15 vol_dV hi/mid/lo, 16 vol_VT
- * hi/mid/lo, laid out [outer][ceil(steps/4)][inner][64][terms][4].  Writes at most cap
+ * hi/mid/lo, laid out [outer][ceil(steps/4)][inner][64][terms][4]; the
+ * Stokes step's reference tables: 20 Ea [d*d-1][d][d] (orthonormal
+ * trace-free basis), 21 Gc [d(d-1)/2][d][d] (orthonormal skew basis), 22 MpG
+ * [dim P^k][dim P^{k+1}], 23 TV [dim P^{k+1}][n][d][d], 24 Phi
+ * [d+1][dim P^{k+1}][dim P^{k+1}(F)], 25 Mref [n][n][d][d] (the last four
+ * with the P^{k+1} basis scaled to unit norm).  Writes at most cap
  * doubles; returns the count or < 0.
  * hopu_host_mesh: topology/geometry of a mesh: which = 0 fid int32
  * [E][d+1], 1 nbr int32, 2 nbr_face (as int32), 3 geometry double
  * [E][32], 4 facet_elem int32 [F][2] (free facets only; a wall side has
- * nbr -1), 5 batches int32 [nb][16].  Writes at most cap entries; returns
+ * nbr -1), 5 batches int32 [nb][16], 6 the Stokes step's element frames
+ * double [E][64] (J, J^-1 with row stride 3, det J at 18, then per local
+ * facet f at 20 + 11 f: outward unit normal, tangents t_1, t_2, |N_F|,
+ * 1 interior / 0 wall).  Writes at most cap entries; returns
  * the array's full length (which may exceed cap), -1 for bad arguments, -2
  * for a mesh the builder rejects.
  * hopu_host_sizes: sizes of the space for (dim, k): which = 0 n_loc, 1 n_f

@@ -52,6 +52,11 @@ SIGNATURES = {
     "hopu_host_tables": (_i64, [_i, _i, _i, _p, _i64]),
     "hopu_host_mesh": (_i64, [_i, _i64, _p, _p, _i, _p, _i64]),
     "hopu_host_sizes": (_i64, [_i, _i, _i]),
+    "hopu_stokes_sizes": (_i, [_p, _p, _p, _p]),
+    "hopu_stokes_setup": (_i, [_p, _d, _d]),
+    "hopu_stokes_apply": (_i, [_p, _p, _p]),
+    "hopu_stokes_precond": (_i, [_p, _p, _p]),
+    "hopu_stokes_step": (_i, [_p, _p, _i, _p, _d, _i, _p]),
 }
 
 _lib = None

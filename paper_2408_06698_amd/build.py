@@ -17,7 +17,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
 SOURCES = ["host_tables.cpp", "hopu_api.cpp", "kernels.hip", "vec_kernels.hip",
-           "aux_kernels.hip", "vjp_kernels.hip", "proj_kernels.hip"]
+           "aux_kernels.hip", "vjp_kernels.hip", "proj_kernels.hip",
+           "stokes_host.cpp", "stokes_kernels.hip"]
 
 
 def _compile(src):

@@ -17,6 +17,7 @@
 #include "host_tables.hpp"
 #include "kernels.hpp"
 #include "proj.hpp"
+#include "stokes.hpp"
 #include "launch.hpp"
 #include "launch_events.hpp"
 #include "vec.hpp"
@@ -103,6 +104,15 @@ struct hopu_ctx_s {
   std::vector<hipEvent_t> events;       // pool, pairs
   std::vector<int> ev_kind;             // kernel id per used pair
   size_t ev_used = 0;
+  // implicit Stokes step (tables and workspaces on the first hopu_stokes_setup)
+  StokesDims st_sd;
+  StokesDev st_dv{};
+  bool st_alloc = false, st_ready = false;
+  double st_nu = 0.0, st_dt = 0.0;
+  double *st_S = nullptr, *st_Sinv = nullptr, *st_slot = nullptr;
+  double *st_r = nullptr, *st_z = nullptr, *st_p = nullptr, *st_q = nullptr, *st_b = nullptr;
+  double *st_mu = nullptr, *st_conv = nullptr, *st_part = nullptr;
+  int* st_bad = nullptr;
 };
 
 enum { PROF_ELEM = 0, PROF_MASS = 1, PROF_PREC = 2, PROF_MODAL = 3, PROF_VJP = 4, PROF_PLAIN = 5, PROF_N = 6 };
@@ -1124,6 +1134,16 @@ extern "C" int64_t hopu_host_sizes(int dim, int k, int which) {
 
 extern "C" int64_t hopu_host_tables(int dim, int k, int which, double* out, int64_t cap) {
   if ((dim != 2 && dim != 3) || k < 1 || k > 6 || (!out && cap > 0)) return -1;
+  if (which >= 20 && which <= 25) {  // the Stokes step's reference tables
+    StokesTables st;
+    std::string serr;
+    if (!make_stokes_tables(dim, k, st, serr)) return -2;
+    const std::vector<double>* sv[6] = {&st.Ea, &st.Gc, &st.MpG, &st.TV, &st.Phi, &st.Mref};
+    const std::vector<double>& v = *sv[which - 20];
+    const int64_t nwr = std::min<int64_t>(cap, (int64_t)v.size());
+    if (out && nwr > 0) std::memcpy(out, v.data(), nwr * sizeof(double));
+    return (int64_t)v.size();
+  }
   RefTables t;
   std::string err;
   if (!make_ref_tables(dim, k, t, err)) return -2;
@@ -1187,6 +1207,12 @@ extern "C" int64_t hopu_host_mesh(int dim, int64_t n_elems, const int64_t* elem_
       Batches b;
       make_batches(m, b);
       return put_i32(b.elem);
+    }
+    case 6: {  // the Stokes step's per-element frames [E][64]
+      std::vector<double> sg;
+      make_stokes_geometry(dim, m.E, m.xyz, m.geo, m.fid, sg);
+      if (out) std::memcpy(out, sg.data(), std::min<int64_t>(cap, sg.size()) * 8);
+      return (int64_t)sg.size();
     }
     default: return -1;
   }
@@ -1339,5 +1365,173 @@ extern "C" hopu_status hopu_profile_read(hopu_ctx ctx, int kind, int64_t* launch
   }
   if (launches) *launches = n;
   if (total_ms) *total_ms = tot;
+  return HOPU_OK;
+}
+
+// ---------------------------------------------------------------- Stokes
+// Implicit Stokes step (paper section 2.2, spaces and forms; section 2.3,
+// eq. (MCS_step1), static condensation, element-wise BDDC).
+static bool stokes_supported(int dim, int k) { return (dim == 2 && k >= 1 && k <= 4) || (dim == 3 && k >= 1 && k <= 3); }
+
+static int64_t stokes_n_uhat(hopu_ctx ctx) { return ctx->mesh.F * (ctx->dim - 1) * ctx->sz.nf; }
+
+extern "C" hopu_status hopu_stokes_sizes(hopu_ctx ctx, int64_t* n_total, int64_t* n_uhat, int* n_elem_unknowns) {
+  if (!ctx) return HOPU_EINVAL;
+  const StokesDims sd = stokes_dims(ctx->dim, ctx->k);
+  if (n_total) *n_total = ctx->n_dof + stokes_n_uhat(ctx);
+  if (n_uhat) *n_uhat = stokes_n_uhat(ctx);
+  if (n_elem_unknowns) *n_elem_unknowns = sd.nx;
+  return HOPU_OK;
+}
+
+static hopu_status stokes_alloc(hopu_ctx ctx) {
+  std::string err;
+  StokesTables tb;
+  if (!make_stokes_tables(ctx->dim, ctx->k, tb, err)) return fail(ctx, HOPU_EINVAL, err);
+  const StokesDims& sd = tb.sd;
+  if (sd.nx > 512 || sd.nx > sd.nsf || sd.nE * 9 > 256)
+    return fail(ctx, HOPU_EUNSUPPORTED, "Stokes element sizes outside the kernels' limits");
+  std::vector<double> sgeo;
+  make_stokes_geometry(ctx->dim, ctx->mesh.E, ctx->mesh.xyz, ctx->mesh.geo, ctx->mesh.fid, sgeo);
+  const int64_t E = ctx->mesh.E, nX = ctx->n_dof + stokes_n_uhat(ctx);
+  hopu_status st;
+  const double *Ea, *Gc, *MpG, *TV, *Phi, *Mref, *g;
+  if ((st = upload(ctx, &Ea, tb.Ea)) || (st = upload(ctx, &Gc, tb.Gc)) || (st = upload(ctx, &MpG, tb.MpG)) ||
+      (st = upload(ctx, &TV, tb.TV)) || (st = upload(ctx, &Phi, tb.Phi)) || (st = upload(ctx, &Mref, tb.Mref)) ||
+      (st = upload(ctx, &g, sgeo)))
+    return st;
+  const size_t nn = (size_t)E * sd.nx * sd.nx;
+  if ((st = dev_alloc(ctx, &ctx->st_S, nn)) || (st = dev_alloc(ctx, &ctx->st_Sinv, nn)) ||
+      (st = dev_alloc(ctx, &ctx->st_slot, (size_t)E * (ctx->dim + 1) * sd.nsd)) ||
+      (st = dev_alloc(ctx, &ctx->st_r, (size_t)nX)) || (st = dev_alloc(ctx, &ctx->st_z, (size_t)nX)) ||
+      (st = dev_alloc(ctx, &ctx->st_p, (size_t)nX)) || (st = dev_alloc(ctx, &ctx->st_q, (size_t)nX)) ||
+      (st = dev_alloc(ctx, &ctx->st_b, (size_t)nX)) || (st = dev_alloc(ctx, &ctx->st_mu, (size_t)ctx->n_dof)) ||
+      (st = dev_alloc(ctx, &ctx->st_conv, (size_t)ctx->n_dof)) || (st = dev_alloc(ctx, &ctx->st_part, 1024)) ||
+      (st = dev_alloc(ctx, &ctx->st_bad, 4)))
+    return st;
+  ctx->st_sd = sd;
+  ctx->st_dv = StokesDev{Ea, Gc, MpG, TV, Phi, Mref, g, ctx->dm.fid, ctx->dm.facet_elem, ctx->dm.facet_local,
+                         E, ctx->mesh.F, ctx->n_dof};
+  ctx->st_alloc = true;
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt) {
+  RocRange range("hopu_stokes_setup");
+  if (!ctx) return HOPU_EINVAL;
+  if (!(nu > 0.0) || !(dt > 0.0) || !std::isfinite(nu) || !std::isfinite(dt))
+    return fail(ctx, HOPU_EINVAL, "nu and dt must be positive and finite");
+  if (!stokes_supported(ctx->dim, ctx->k))
+    return fail(ctx, HOPU_EUNSUPPORTED, "the Stokes step is built for 2D k <= 4 and 3D k <= 3");
+  hopu_status st;
+  if (!ctx->st_alloc && (st = stokes_alloc(ctx))) return st;
+  ctx->st_ready = false;
+  hipStream_t s = ctx->stream;
+  // the set-up's per-block scratch lives only for this call
+  double* scratch = nullptr;
+  const size_t nscr = stokes_setup_scratch(ctx->st_sd);
+  if (const char* f = std::getenv("HOPU_TEST_FAIL_ALLOC"); f && std::atoi(f) == 1)
+    return fail(ctx, HOPU_ENOMEM, "device allocation refused (HOPU_TEST_FAIL_ALLOC)");
+  if (hipMalloc(&scratch, nscr * sizeof(double)) != hipSuccess)
+    return fail(ctx, HOPU_ENOMEM, "hipMalloc of the Stokes set-up scratch failed");
+  HCHECK(hipMemsetAsync(ctx->st_bad, 0, sizeof(int), s));
+  launch_stokes_setup(s, ctx->st_sd, ctx->st_dv, nu, dt, ctx->st_S, ctx->st_Sinv, scratch, ctx->st_bad);
+  int bad = 0;
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipMemcpyAsync(&bad, ctx->st_bad, sizeof(int), hipMemcpyDeviceToHost, s);
+  hipError_t e3 = hipStreamSynchronize(s);
+  hipFree(scratch);
+  HCHECK(e1);
+  HCHECK(e2);
+  HCHECK(e3);
+  if (bad) return fail(ctx, HOPU_EINVAL, "an element matrix of the Stokes step is not positive definite");
+  ctx->st_nu = nu;
+  ctx->st_dt = dt;
+  ctx->st_ready = true;
+  return HOPU_OK;
+}
+
+static hopu_status stokes_check(hopu_ctx ctx) {
+  if (!ctx->st_ready) return fail(ctx, HOPU_EINVAL, "hopu_stokes_setup has not been called");
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_stokes_apply(hopu_ctx ctx, const double* x, double* y) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!x || !y) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  if (x == y) return fail(ctx, HOPU_EINVAL, "x and y must be different vectors");
+  if (hopu_status st = stokes_check(ctx)) return st;
+  launch_stokes_gemv(ctx->stream, ctx->st_sd, ctx->st_dv, ctx->st_S, 0, x, y, ctx->st_slot);
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_stokes_precond(hopu_ctx ctx, const double* x, double* y) {
+  if (!ctx) return HOPU_EINVAL;
+  if (!x || !y) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  if (x == y) return fail(ctx, HOPU_EINVAL, "x and y must be different vectors");
+  if (hopu_status st = stokes_check(ctx)) return st;
+  launch_stokes_gemv(ctx->stream, ctx->st_sd, ctx->st_dv, ctx->st_Sinv, 1, x, y, ctx->st_slot);
+  HCHECK(hipGetLastError());
+  return HOPU_OK;
+}
+
+static hopu_status stokes_dot(hopu_ctx ctx, const double* a, const double* b, int64_t n, double* out) {
+  const int np = launch_stokes_dot(ctx->stream, a, b, n, ctx->st_part);
+  double h[1024];
+  HCHECK(hipMemcpyAsync(h, ctx->st_part, np * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HCHECK(hipStreamSynchronize(ctx->stream));
+  double v = 0.0;
+  for (int i = 0; i < np; ++i) v += h[i];
+  *out = v;
+  return HOPU_OK;
+}
+
+extern "C" hopu_status hopu_stokes_step(hopu_ctx ctx, const double* un, int with_convection, double* x, double rtol,
+                                        int max_it, int* iters) {
+  RocRange range("hopu_stokes_step");
+  if (!ctx) return HOPU_EINVAL;
+  if (!un || !x) return fail(ctx, HOPU_EINVAL, "NULL vector");
+  if (!(rtol > 0.0) || max_it < 1) return fail(ctx, HOPU_EINVAL, "rtol must be > 0 and max_it >= 1");
+  if (hopu_status st = stokes_check(ctx)) return st;
+  hipStream_t s = ctx->stream;
+  const int64_t nX = ctx->n_dof + stokes_n_uhat(ctx);
+  // b = [M u^n / dt - r(u^n); 0]
+  do_mass(ctx, 0, un, ctx->st_mu, nullptr);
+  if (with_convection) {
+    refresh_dm(ctx);
+    if (hopu_status st = do_apply(ctx, un, ctx->st_conv, 7, HOPU_FP64, nullptr)) return st;
+  }
+  launch_stokes_rhs(s, ctx->st_b, ctx->st_mu, with_convection ? ctx->st_conv : nullptr, ctx->st_dt, ctx->n_dof, nX);
+  // PCG on S with C^-1 = R S_BDDC^-1 R^t from x = 0
+  HCHECK(hipMemsetAsync(x, 0, (size_t)nX * sizeof(double), s));
+  vec_copy(s, ctx->st_r, ctx->st_b, nX);
+  launch_stokes_gemv(s, ctx->st_sd, ctx->st_dv, ctx->st_Sinv, 1, ctx->st_r, ctx->st_z, ctx->st_slot);
+  vec_copy(s, ctx->st_p, ctx->st_z, nX);
+  double rz = 0.0;
+  if (hopu_status st = stokes_dot(ctx, ctx->st_r, ctx->st_z, nX, &rz)) return st;
+  const double stop = rtol * std::sqrt(std::fabs(rz));
+  int it = 0;
+  bool conv = !(std::sqrt(std::fabs(rz)) > stop);
+  while (!conv && it < max_it) {
+    launch_stokes_gemv(s, ctx->st_sd, ctx->st_dv, ctx->st_S, 0, ctx->st_p, ctx->st_q, ctx->st_slot);
+    double pq = 0.0;
+    if (hopu_status st = stokes_dot(ctx, ctx->st_p, ctx->st_q, nX, &pq)) return st;
+    const double alpha = rz / pq;
+    launch_stokes_axpy(s, x, ctx->st_p, alpha, nX);
+    launch_stokes_axpy(s, ctx->st_r, ctx->st_q, -alpha, nX);
+    launch_stokes_gemv(s, ctx->st_sd, ctx->st_dv, ctx->st_Sinv, 1, ctx->st_r, ctx->st_z, ctx->st_slot);
+    double rz1 = 0.0;
+    if (hopu_status st = stokes_dot(ctx, ctx->st_r, ctx->st_z, nX, &rz1)) return st;
+    ++it;
+    if (!std::isfinite(rz1)) break;
+    if (std::sqrt(std::fabs(rz1)) <= stop) conv = true;
+    launch_stokes_xpby(s, ctx->st_p, ctx->st_z, rz1 / rz, nX);
+    rz = rz1;
+  }
+  HCHECK(hipGetLastError());
+  HCHECK(hipStreamSynchronize(s));
+  if (iters) *iters = it;
+  if (!conv) return fail(ctx, HOPU_ENOCONV, "Stokes PCG did not reach rtol within max_it iterations");
   return HOPU_OK;
 }

@@ -194,6 +194,38 @@ class Hopu:
         check(L.lib().hopu_interpolate(self.h, int(n1d), _ptr(vf), _ptr(vv), _ptr(u)), self.h)
         return u
 
+    # ---- implicit Stokes step (hopu_stokes_*)
+    def stokes_sizes(self):
+        """(n_total, n_uhat, unknowns per element of S_T)."""
+        nt, nh, nx = C.c_int64(), C.c_int64(), C.c_int()
+        check(L.lib().hopu_stokes_sizes(self.h, C.byref(nt), C.byref(nh), C.byref(nx)), self.h)
+        return nt.value, nh.value, nx.value
+
+    def stokes_setup(self, nu, dt):
+        check(L.lib().hopu_stokes_setup(self.h, float(nu), float(dt)), self.h)
+
+    def _stokes_vec(self, out):
+        n = self.stokes_sizes()[0]
+        return torch.zeros(n, dtype=torch.float64, device=self.device) if out is None else _dev(out, n)
+
+    def stokes_apply(self, x, y=None):
+        y = self._stokes_vec(y)
+        check(L.lib().hopu_stokes_apply(self.h, _ptr(_dev(x, y.numel())), _ptr(y)), self.h)
+        return y
+
+    def stokes_precond(self, x, y=None):
+        y = self._stokes_vec(y)
+        check(L.lib().hopu_stokes_precond(self.h, _ptr(_dev(x, y.numel())), _ptr(y)), self.h)
+        return y
+
+    def stokes_step(self, un, with_convection=True, out=None, rtol=1e-12, max_it=2000):
+        """[u*; u^] of one implicit Stokes step from u^n; returns (x, iterations)."""
+        x = self._stokes_vec(out)
+        its = C.c_int()
+        check(L.lib().hopu_stokes_step(self.h, _ptr(_dev(un, self.n_dof)), int(bool(with_convection)), _ptr(x),
+                                       float(rtol), int(max_it), C.byref(its)), self.h)
+        return x, its.value
+
     PROF_KINDS = {"elem": 0, "mass": 1, "prec": 2, "modal": 3, "vjp": 4, "plain": 5}
 
     def profile(self, enable, max_launches=200000):

@@ -1,0 +1,179 @@
+"""GPU parity of the implicit Stokes step (paper section 2.2, spaces and
+forms; section 2.3, eq. (MCS_step1), static condensation, element-wise BDDC)
+against the oracle, through the C ABI: the condensed operator S x, the
+preconditioner C^-1 x, and the step's (u*, u^) with and without the
+convection term.  FP64 throughout; entry-wise comparison, relative to the
+largest entry of each block (velocity, u^)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import operator as O
+from oracle import stokes as OST
+from oracle.space import Space
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(d, k, n, walls, jitter=0.1):
+    per = tuple(a != 1 for a in range(d)) if walls else (True,) * d
+    m = synth.kuhn_mesh(d, (n,) * d, periodic=per, jitter=jitter, jitter_seed=9 if jitter else None)
+    return m, Space(m.elem_vid, m.elem_xyz, k)
+
+
+def _gpu(m, k):
+    from paper_2408_06698_amd.hopu import Hopu
+    return Hopu(m.dim, k, m.elem_vid, m.elem_xyz)
+
+
+def _blockerr(sp, v, ref):
+    nd = sp.n_dof
+    out = []
+    for sl in (slice(0, nd), slice(nd, len(ref))):
+        den = np.abs(ref[sl]).max()
+        out.append(float(np.abs(v[sl] - ref[sl]).max() / den))
+    return max(out)
+
+
+# The two sides condense sigma and gamma through different bases (the
+# oracle: monomials and a null-space reduction; the library: an orthonormal
+# basis with multipliers), so their rounding differs by the conditioning of
+# the element blocks, which grows with k: the bounds below (entry-wise,
+# relative to each block's largest entry) follow the CPU emulation of the
+# set-up against the oracle (3D k = 3: 2.40e-9 in the u^ block, which holds
+# only the viscous part; the GPU gives the same figure); C^-1 adds the
+# conditioning of S_T.  Against that emulation (same formulas, LAPACK in
+# numpy) the GPU's S x agrees to rounding (EMU_TOL): the kernel's own
+# arithmetic is pinned tighter than the two condensation routes agree.
+TOL_S = {1: 1e-11, 2: 1e-11, 3: 5e-9, 4: 1e-8}
+TOL_C = {1: 1e-10, 2: 1e-10, 3: 5e-9, 4: 1e-7}
+EMU_TOL = 1e-12
+TOL_STEP = {1: 1e-10, 2: 1e-10, 3: 1e-9}
+
+def _emulated_S(m, sp, k, nu, dt, schur):
+    """S assembled from the CPU emulation of the set-up kernel."""
+    import scipy.sparse as sps
+    from tests.test_stokes_setup_math import emulate_ST, _table, _frames
+    loc = schur[2]
+    tabs = [_table(m.dim, k, w) for w in range(20, 26)]
+    geo = _frames(m)
+    rows, cols, vals = [], [], []
+    for T in range(sp.topo.n_elems):
+        Se = emulate_ST(m.dim, k, geo[T], nu, dt, tabs)
+        g = loc[T]
+        rr = np.broadcast_to(g[:, None], Se.shape)
+        cc = np.broadcast_to(g[None, :], Se.shape)
+        keep = (rr >= 0) & (cc >= 0)
+        rows.append(rr[keep]); cols.append(cc[keep]); vals.append(Se[keep])
+    return sps.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=schur[0].shape).tocsr()
+
+
+CASES = [(2, 1, 4, False), (2, 2, 4, True), (2, 3, 3, False), (2, 4, 3, True),
+         (3, 1, 3, False), (3, 2, 3, True), (3, 3, 3, False)]
+
+
+@pytest.mark.parametrize("d,k,n,walls", CASES)
+def test_stokes_operator_and_preconditioner(d, k, n, walls):
+    print(f"stokes S/C^-1 d={d} k={k} n={n} walls={walls}", flush=True)
+    m, sp = _case(d, k, n, walls)
+    nu, dt = 0.03, 0.01
+    schur = OST.schur_system(sp, nu, dt)
+    g = _gpu(m, k)
+    nt, nh, nx = g.stokes_sizes()
+    assert nt == schur[0].shape[0] and nh == OST.n_uhat(sp)
+    g.stokes_setup(nu, dt)
+    rng = np.random.default_rng(100 + 10 * d + k)
+    x = rng.standard_normal(nt)
+    y = host(g.stokes_apply(dev(x)))
+    ref = schur[0] @ x
+    print(f"  S x: {_blockerr(sp, y, ref):.2e}", flush=True)
+    assert _blockerr(sp, y, ref) <= TOL_S[k]
+    yemu = _emulated_S(m, sp, k, nu, dt, schur) @ x
+    print(f"  S x against the set-up emulation: {_blockerr(sp, y, yemu):.2e}", flush=True)
+    assert _blockerr(sp, y, yemu) <= EMU_TOL
+    z = host(g.stokes_precond(dev(x)))
+    zref = OST.bddc_apply(sp, schur, x)
+    print(f"  C^-1 x: {_blockerr(sp, z, zref):.2e}", flush=True)
+    assert _blockerr(sp, z, zref) <= TOL_C[k]
+    # S is symmetric: x . S y = y . S x for the GPU operator too
+    y2 = rng.standard_normal(nt)
+    a = x @ host(g.stokes_apply(dev(y2)))
+    b = y2 @ y
+    assert abs(a - b) <= 1e-12 * abs(a) * 10
+
+
+@pytest.mark.parametrize("d,k,n,walls,conv", [(2, 2, 4, True, True), (2, 3, 3, False, True),
+                                             (3, 1, 3, False, True), (3, 2, 3, True, True),
+                                             (3, 2, 3, False, False)])
+def test_stokes_step_matches_direct_solve(d, k, n, walls, conv):
+    print(f"stokes step d={d} k={k} n={n} walls={walls} conv={conv}", flush=True)
+    m, sp = _case(d, k, n, walls)
+    f = (lambda x: np.stack([np.sin(np.pi * x[..., 1])] + [0.0 * x[..., 0]] * (d - 1), -1)) if walls else \
+        (synth.taylor_green_2d() if d == 2 else synth.taylor_green_3d())
+    un = sp.interpolate(f) + 1e-2 * np.random.default_rng(7).standard_normal(sp.n_dof)
+    nu, dt = 0.05, 0.02
+    r = O.residual(sp, un, -1) if conv else None
+    us, uh, _, _, _ = OST.step1(sp, un, nu, dt, r)
+    g = _gpu(m, k)
+    g.set_upwind(-1)
+    g.stokes_setup(nu, dt)
+    x, its = g.stokes_step(dev(un), with_convection=conv, rtol=1e-13)
+    xh = host(x)
+    ref = np.concatenate([us, uh])
+    print(f"  step: {_blockerr(sp, xh, ref):.2e} after {its} iterations", flush=True)
+    assert _blockerr(sp, xh, ref) <= TOL_STEP[k], its
+    assert its < 300
+
+
+def test_stokes_errors_and_setup_reuse():
+    print("stokes errors", flush=True)
+    from paper_2408_06698_amd._lib import HopuError, HOPU_EINVAL, HOPU_EUNSUPPORTED
+    m, sp = _case(2, 2, 3, False)
+    g = _gpu(m, 2)
+    nt = g.stokes_sizes()[0]
+    x = torch.zeros(nt, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(HopuError) as e:
+        g.stokes_apply(x)
+    assert e.value.status == HOPU_EINVAL
+    with pytest.raises(HopuError) as e:
+        g.stokes_setup(-1.0, 0.1)
+    assert e.value.status == HOPU_EINVAL
+    # a second set-up with other nu, dt replaces the element matrices
+    rng = np.random.default_rng(3)
+    xv = rng.standard_normal(nt)
+    for nu, dt in ((0.1, 0.05), (0.01, 0.2)):
+        g.stokes_setup(nu, dt)
+        y = host(g.stokes_apply(dev(xv)))
+        ref = OST.schur_system(sp, nu, dt)[0] @ xv
+        assert _blockerr(sp, y, ref) <= 1e-11
+    m3 = synth.kuhn_mesh(3, (3, 3, 3), periodic=(True,) * 3)
+    g4 = _gpu(m3, 4)
+    with pytest.raises(HopuError) as e:
+        g4.stokes_setup(0.1, 0.1)
+    assert e.value.status == HOPU_EUNSUPPORTED
+
+
+def test_stokes_step_decay_factor_at_size():
+    """The 32^3 x 6 Taylor-Green mesh (k = 3) at the bench's nu and dt: the
+    Stokes part alone maps the interpolated mode to (1 + 3 nu dt)^-1 times
+    itself up to the discretisation error (a property that holds at any
+    size; the oracle cannot run this mesh)."""
+    print("stokes step 32^3 k=3", flush=True)
+    L = (2 * np.pi,) * 3
+    m = synth.kuhn_mesh(3, (32, 32, 32), periodic=(True,) * 3, lengths=L)
+    g = _gpu(m, 3)
+    nu, dt = 0.05, 0.05
+    g.stokes_setup(nu, dt)
+    tg = synth.taylor_green_3d()
+    un = g.interpolate(tg)
+    x, its = g.stokes_step(un, with_convection=False, rtol=1e-10)
+    u = x[:g.n_dof]
+    e = u - un / (1 + 3 * nu * dt)
+    Me = g.mass_apply(e.contiguous())
+    Mu = g.mass_apply(un)
+    rel = float(torch.sqrt((e * Me).sum() / (un * Mu).sum()))
+    print(f"  iterations {its}, relative M-norm error {rel:.3e}", flush=True)
+    assert rel <= 1e-4
