@@ -20,8 +20,9 @@ error against the FP64 substep and the apply's error against the FP64
 apply), the checkpointed FP64 and hi/mid/lo adjoint of one substep,
 apply-only rates, the roofline of the dominant kernel, the 3D periodic
 Taylor-Green workload (32^3 x 6 tets, k = 3) as a secondary line with the
-projection step, and the FP64 oracle on the host cores as the CPU
-baseline.  The sections after the timed substeps and the CPU baseline run
+projection step and the implicit Stokes step (element Schur complements,
+PCG with the element-wise BDDC; --only-stokes runs that section alone), and
+the FP64 oracle on the host cores as the CPU baseline.  The sections after the timed substeps and the CPU baseline run
 only while they fit in --budget-s; a skipped one is named under "skipped".
 
 Prints one JSON line (metric in DoF-updates/s: n_dof x steps / time).
@@ -68,6 +69,9 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the Taylor-Green line")
     ap.add_argument("--no-projection", action="store_true")
+    ap.add_argument("--no-stokes", action="store_true", help="skip the implicit Stokes step section")
+    ap.add_argument("--only-stokes", action="store_true",
+                    help="run only the implicit Stokes step section and print it as the JSON line")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after the run, copy a 1 GiB device buffer (reference for HBM counters)")
     return ap.parse_args()
@@ -91,14 +95,16 @@ def mass_flops(n, d, E):
     return 4.0 * n * n * E + 2.0 * d * d * (n // d) * E
 
 
-def traffic_from_profiles(kernel_key):
+def traffic_from_profiles(kernel_key, source="kernels.hip"):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     summaries (profiles/*traffic*.txt), if one was taken on the current
     kernel source; else None."""
-    src = os.path.join(ROOT, "paper_2408_06698_amd", "csrc", "kernels.hip")
+    src = os.path.join(ROOT, "paper_2408_06698_amd", "csrc", source)
     text = open(src).read()
-    body = text[text.index("namespace hopu {"):text.index("// " + "-" * 66 + " launchers")]
-    sha = hashlib.sha256(body.encode()).hexdigest()[:16]
+    marker = "// " + "-" * 66 + " launchers"
+    if marker in text:
+        text = text[text.index("namespace hopu {"):text.index(marker)]
+    sha = hashlib.sha256(text.encode()).hexdigest()[:16]
     pdir = os.path.join(ROOT, "profiles")
     for fn in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
         if "traffic" not in fn or not fn.endswith(".txt"):
@@ -244,6 +250,69 @@ class Ctx:
         return float(self.torch.dot(d, w))
 
 
+STOKES_NU = 1.0 / 1600.0   # Taylor-Green at Re = 1600 on [0, 2 pi]^3
+STOKES_STEPS = 3
+
+
+def stokes_section(torch, log):
+    """The implicit Stokes step (section 2.3, eq. (MCS_step1)) on the 3D
+    periodic Taylor-Green workload (32^3 x 6 tets, k = 3, dt = 5e-4,
+    nu = 1/1600): set-up of the element Schur complements and their inverses
+    (timed), one warm-up step, then STOKES_STEPS timed steps from the same
+    u^n (convection included, PCG to 1e-10 from zero).  The element products
+    read the packed upper triangle of S_T or S_T^-1 once per launch, so the
+    roofline is HBM: bytes = E nx (nx + 1)/2 8 per launch (the matrix;
+    vectors add < 1%) over the launch's average duration from the library's
+    events."""
+    import synth
+    from paper_2408_06698_amd.hopu import Hopu
+    mesh, field, cfg = synth.make_config(2)
+    h = Hopu(3, cfg["k"], mesh.elem_vid, mesh.elem_xyz)
+    h.set_upwind(cfg["l"])
+    un = h.interpolate(field, n1d=cfg["k"] + 1)
+    nt, nh, nx = h.stokes_sizes()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    h.stokes_setup(STOKES_NU, cfg["dt"])
+    setup_s = time.time() - t0
+    log(f"stokes set-up {setup_s:.1f} s ({mesh.n_elems} elements, {nx} unknowns each)")
+    x, its0 = h.stokes_step(un, with_convection=True, rtol=1e-10)
+    h.profile(1)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    its = []
+    for _ in range(STOKES_STEPS):
+        its.append(h.stokes_step(un, with_convection=True, out=x, rtol=1e-10)[1])
+    torch.cuda.synchronize()
+    ms = (time.time() - t1) * 1e3 / STOKES_STEPS
+    nS, msS = h.profile_read("stokes_S")
+    nC, msC = h.profile_read("stokes_C")
+    h.profile(False)
+    # the packed upper triangle of S_T^-1 (padded to 8 doubles per element)
+    mat_bytes = mesh.n_elems * ((nx * (nx + 1) // 2 + 7) // 8 * 8) * 8
+    avg_S, avg_C = msS / max(nS, 1), msC / max(nC, 1)
+    ach = mat_bytes / (avg_C * 1e-3)
+    out = {
+        "workload": WORKLOADS[2].replace("one substep per step", "one implicit Stokes step per step")
+        + f", nu={STOKES_NU}",
+        "n_unknowns": nt, "n_uhat": nh, "unknowns_per_element": nx,
+        "setup_s": setup_s, "pcg_iterations": its, "pcg_iterations_first": its0, "rtol": 1e-10,
+        "ms_per_step": ms, "ms_per_iteration": ms / max(1, sum(its) / len(its)),
+        "dof_updates_per_s": h.n_dof / (ms * 1e-3),
+        "kernel_avg_ms": {"stokes_S": avg_S, "stokes_C": avg_C},
+        "kernel_launches": {"stokes_S": nS, "stokes_C": nC},
+        "roofline": {"kernel": "k_stokes_gemv (S_T^-1, the preconditioner)", "bound": "hbm",
+                     "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": ach / PEAK_HBM, "traffic": traffic_from_profiles("stokes_gemv", "stokes_kernels.hip"),
+                     "algorithmic_bytes_per_launch": mat_bytes},
+        "timing": "host clock around STOKES_STEPS hopu_stokes_step calls (each synchronises); kernel "
+                  "averages from the library's HIP events on every launch",
+    }
+    log(f"stokes: {ms:.1f} ms per step, {its} PCG iterations, element product {avg_S:.2f} / {avg_C:.2f} ms")
+    h.close()
+    return out
+
+
 def small_latency(torch):
     """Launch-bound latency on the 2D periodic Taylor-Green workload (16x16x2
     = 512 triangles, k = 2, 3,840 DoFs): one convection apply (averaged over
@@ -340,6 +409,18 @@ def main():
 
     def log(msg):
         print(f"# [{time.time() - t_start:6.1f} s] {msg}", file=sys.stderr, flush=True)
+
+    if args.only_stokes:
+        line = {"stokes_step": stokes_section(torch, log)}
+        if args.copy_calib:
+            src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            line["copy_calib_bytes"] = src.numel() * 8
+        line["wall_s"] = time.time() - t_start
+        print(json.dumps(line))
+        return
 
     # the library's per-launch timing events go on every PROF_STRIDE-th
     # launch of each kernel kind (a dispatch with events starts a few
@@ -526,6 +607,9 @@ def main():
         out["secondary"] = sec
         h2.close()
         log("secondary done")
+    if not args.no_stokes and fits("stokes_step", 90):
+        out["stokes_step"] = stokes_section(torch, log)
+        torch.cuda.empty_cache()
     if not args.no_secondary and fits("small_latency", 15):
         out["small_latency"] = small_latency(torch)
         log("small-workload latency done")

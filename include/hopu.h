@@ -259,7 +259,8 @@ hopu_status hopu_eval_noalloc(hopu_ctx ctx, const double* u, int n_pts,
  * returns, for one kernel kind (0 element/convection kernel, 1 mass apply
  * inside PCG, 2 preconditioner inside PCG, 3 dual->modal transform,
  * 4 transpose-Jacobian kernel, 5 mass/preconditioner applies outside the
- * PCG loop), the number of recorded launches and their summed duration in
+ * PCG loop, 6 the Stokes step's element product with S_T, 7 the same with
+ * S_T^-1), the number of recorded launches and their summed duration in
  * ms.  Both sync. */
 hopu_status hopu_profile_enable(hopu_ctx ctx, int enable, int max_launches);
 hopu_status hopu_profile_read(hopu_ctx ctx, int kind, int64_t* launches, double* total_ms);
@@ -293,7 +294,7 @@ void hopu_destroy(hopu_ctx ctx);
  *   (any pointer may be NULL).
  * hopu_stokes_setup: nu > 0, dt > 0.  Builds on the GPU, per element, S_T on
  *   its velocity and u^ unknowns and S_T^-1, and keeps both in device memory
- *   (2 E nx^2 doubles, nx from hopu_stokes_sizes).  Allocates on its first
+ *   (their upper triangles: about E nx^2 doubles, nx from hopu_stokes_sizes).  Allocates on its first
  *   call (HOPU_ENOMEM if that fails) and a set-up scratch for each call;
  *   HOPU_EINVAL if an element matrix is not positive definite.  Re-call it
  *   when nu or dt changes.

@@ -115,7 +115,8 @@ struct hopu_ctx_s {
   int* st_bad = nullptr;
 };
 
-enum { PROF_ELEM = 0, PROF_MASS = 1, PROF_PREC = 2, PROF_MODAL = 3, PROF_VJP = 4, PROF_PLAIN = 5, PROF_N = 6 };
+enum { PROF_ELEM = 0, PROF_MASS = 1, PROF_PREC = 2, PROF_MODAL = 3, PROF_VJP = 4, PROF_PLAIN = 5, PROF_STOKES_S = 6,
+       PROF_STOKES_C = 7, PROF_N = 8 };
 static_assert(PROF_N <= 8, "prof_count holds 8 kinds");
 
 namespace hopu {
@@ -1389,7 +1390,7 @@ static hopu_status stokes_alloc(hopu_ctx ctx) {
   StokesTables tb;
   if (!make_stokes_tables(ctx->dim, ctx->k, tb, err)) return fail(ctx, HOPU_EINVAL, err);
   const StokesDims& sd = tb.sd;
-  if (sd.nx > 512 || sd.nx > sd.nsf || sd.nE * 9 > 256)
+  if (sd.nx > 256 || sd.nx * sd.nx > sd.ng * sd.nsf || sd.nE * 9 > 256)
     return fail(ctx, HOPU_EUNSUPPORTED, "Stokes element sizes outside the kernels' limits");
   std::vector<double> sgeo;
   make_stokes_geometry(ctx->dim, ctx->mesh.E, ctx->mesh.xyz, ctx->mesh.geo, ctx->mesh.fid, sgeo);
@@ -1400,7 +1401,7 @@ static hopu_status stokes_alloc(hopu_ctx ctx) {
       (st = upload(ctx, &TV, tb.TV)) || (st = upload(ctx, &Phi, tb.Phi)) || (st = upload(ctx, &Mref, tb.Mref)) ||
       (st = upload(ctx, &g, sgeo)))
     return st;
-  const size_t nn = (size_t)E * sd.nx * sd.nx;
+  const size_t nn = (size_t)E * stokes_packed_stride(sd.nx);
   if ((st = dev_alloc(ctx, &ctx->st_S, nn)) || (st = dev_alloc(ctx, &ctx->st_Sinv, nn)) ||
       (st = dev_alloc(ctx, &ctx->st_slot, (size_t)E * (ctx->dim + 1) * sd.nsd)) ||
       (st = dev_alloc(ctx, &ctx->st_r, (size_t)nX)) || (st = dev_alloc(ctx, &ctx->st_z, (size_t)nX)) ||
@@ -1451,6 +1452,13 @@ extern "C" hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt) {
   return HOPU_OK;
 }
 
+// the Stokes element product (S or C^-1), timed as its own kernel kind
+static void stokes_gemv(hopu_ctx ctx, int inv, const double* x, double* y) {
+  prof_begin(ctx, inv ? PROF_STOKES_C : PROF_STOKES_S);
+  launch_stokes_gemv(ctx->stream, ctx->st_sd, ctx->st_dv, inv ? ctx->st_Sinv : ctx->st_S, inv, x, y, ctx->st_slot);
+  prof_end(ctx);
+}
+
 static hopu_status stokes_check(hopu_ctx ctx) {
   if (!ctx->st_ready) return fail(ctx, HOPU_EINVAL, "hopu_stokes_setup has not been called");
   return HOPU_OK;
@@ -1461,7 +1469,7 @@ extern "C" hopu_status hopu_stokes_apply(hopu_ctx ctx, const double* x, double* 
   if (!x || !y) return fail(ctx, HOPU_EINVAL, "NULL vector");
   if (x == y) return fail(ctx, HOPU_EINVAL, "x and y must be different vectors");
   if (hopu_status st = stokes_check(ctx)) return st;
-  launch_stokes_gemv(ctx->stream, ctx->st_sd, ctx->st_dv, ctx->st_S, 0, x, y, ctx->st_slot);
+  stokes_gemv(ctx, 0, x, y);
   HCHECK(hipGetLastError());
   return HOPU_OK;
 }
@@ -1471,7 +1479,7 @@ extern "C" hopu_status hopu_stokes_precond(hopu_ctx ctx, const double* x, double
   if (!x || !y) return fail(ctx, HOPU_EINVAL, "NULL vector");
   if (x == y) return fail(ctx, HOPU_EINVAL, "x and y must be different vectors");
   if (hopu_status st = stokes_check(ctx)) return st;
-  launch_stokes_gemv(ctx->stream, ctx->st_sd, ctx->st_dv, ctx->st_Sinv, 1, x, y, ctx->st_slot);
+  stokes_gemv(ctx, 1, x, y);
   HCHECK(hipGetLastError());
   return HOPU_OK;
 }
@@ -1506,7 +1514,7 @@ extern "C" hopu_status hopu_stokes_step(hopu_ctx ctx, const double* un, int with
   // PCG on S with C^-1 = R S_BDDC^-1 R^t from x = 0
   HCHECK(hipMemsetAsync(x, 0, (size_t)nX * sizeof(double), s));
   vec_copy(s, ctx->st_r, ctx->st_b, nX);
-  launch_stokes_gemv(s, ctx->st_sd, ctx->st_dv, ctx->st_Sinv, 1, ctx->st_r, ctx->st_z, ctx->st_slot);
+  stokes_gemv(ctx, 1, ctx->st_r, ctx->st_z);
   vec_copy(s, ctx->st_p, ctx->st_z, nX);
   double rz = 0.0;
   if (hopu_status st = stokes_dot(ctx, ctx->st_r, ctx->st_z, nX, &rz)) return st;
@@ -1514,13 +1522,13 @@ extern "C" hopu_status hopu_stokes_step(hopu_ctx ctx, const double* un, int with
   int it = 0;
   bool conv = !(std::sqrt(std::fabs(rz)) > stop);
   while (!conv && it < max_it) {
-    launch_stokes_gemv(s, ctx->st_sd, ctx->st_dv, ctx->st_S, 0, ctx->st_p, ctx->st_q, ctx->st_slot);
+    stokes_gemv(ctx, 0, ctx->st_p, ctx->st_q);
     double pq = 0.0;
     if (hopu_status st = stokes_dot(ctx, ctx->st_p, ctx->st_q, nX, &pq)) return st;
     const double alpha = rz / pq;
     launch_stokes_axpy(s, x, ctx->st_p, alpha, nX);
     launch_stokes_axpy(s, ctx->st_r, ctx->st_q, -alpha, nX);
-    launch_stokes_gemv(s, ctx->st_sd, ctx->st_dv, ctx->st_Sinv, 1, ctx->st_r, ctx->st_z, ctx->st_slot);
+    stokes_gemv(ctx, 1, ctx->st_r, ctx->st_z);
     double rz1 = 0.0;
     if (hopu_status st = stokes_dot(ctx, ctx->st_r, ctx->st_z, nX, &rz1)) return st;
     ++it;

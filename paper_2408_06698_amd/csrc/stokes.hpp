@@ -68,8 +68,14 @@ struct StokesDev {
   int64_t E, F, n_dof;
 };
 
-// S_T and S_T^-1 ([E][nx][nx] each) for elements [e0, e1); scratch holds
-// nblocks * (ng * nsf + ng * ng) doubles.  Returns the number of blocks.
+// Per-element storage of S_T and S_T^-1: the upper triangle packed by rows
+// (row i holds entries j >= i at offset i nx - i (i - 1)/2), padded to a
+// multiple of 8 doubles.
+__host__ __device__ inline int64_t stokes_packed_stride(int nx) {
+  return ((int64_t)nx * (nx + 1) / 2 + 7) / 8 * 8;
+}
+// S_T and S_T^-1 ([E][stokes_packed_stride(nx)] each); scratch holds
+// nblocks * (ng * nsf + ng * ng) doubles.
 int stokes_setup_blocks(const StokesDims& sd);
 size_t stokes_setup_scratch(const StokesDims& sd);
 void launch_stokes_setup(hipStream_t s, const StokesDims& sd, const StokesDev& dv, double nu, double dt,

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "launch_events.hpp"
 #include "stokes.hpp"
 
 namespace hopu {
@@ -111,6 +112,16 @@ __device__ void block_cholesky(double* A, int lda, int n, int* bad) {
     }
     __syncthreads();
   }
+}
+
+// Upper triangle of the symmetric n x n matrix A (row stride n), packed by
+// rows: row i holds A[i][i..n-1] at offset i n - i (i - 1)/2.
+__device__ void pack_upper(const double* A, int n, double* out) {
+  for (int64_t v = threadIdx.x; v < (int64_t)n * n; v += ST_THREADS) {
+    const int i = (int)(v / n), j = (int)(v % n);
+    if (j >= i) out[(int64_t)i * n - (int64_t)i * (i - 1) / 2 + (j - i)] = A[v];
+  }
+  __syncthreads();
 }
 
 __device__ inline int64_t gidx(const StokesDims& sd, const StokesDev& dv, int64_t e, int t, int* fside, int* vslot) {
@@ -262,7 +273,8 @@ __global__ void __launch_bounds__(ST_THREADS)
     // ---- K22 += W^t W; S_T = A_T - K22 (into ST)
     double* K22 = K + (size_t)n1 * ng + n1;
     block_gram(K + (size_t)n1 * ng, ng, nx, n1, K22, ng, 1.0, true, As, Bs);
-    double* S = ST + (size_t)e * nx * nx;
+    // S_T in full (row stride nx) in G's storage, which is free once K is formed
+    double* S = G;
     for (int64_t v = t; v < (int64_t)nx * nx; v += ST_THREADS) {
       const int i = (int)(v / nx), j = (int)(v % nx);
       double s = -K22[(size_t)i * ng + j];
@@ -289,74 +301,103 @@ __global__ void __launch_bounds__(ST_THREADS)
       S[v] = s;
     }
     __syncthreads();
-    // ---- S_T^-1: L_S L_S^t = S_T (in K's first nx x nx block), X = L_S^-1
-    // stored transposed in G's first nx rows, S_T^-1 = X^t X
-    for (int64_t v = t; v < (int64_t)nx * nx; v += ST_THREADS) {
-      const int i = (int)(v / nx), j = (int)(v % nx);
-      K[(size_t)i * ng + j] = S[v];
-    }
-    __syncthreads();
-    block_cholesky(K, ng, nx, bad);
+    pack_upper(S, nx, ST + (size_t)e * stokes_packed_stride(nx));
+    // ---- S_T^-1: L_S L_S^t = S_T in place, X = L_S^-1 stored transposed in
+    // K's storage (row stride nx), S_T^-1 = X^t X into G's storage, packed
+    block_cholesky(S, nx, nx, bad);
+    double* XT = K;
     for (int i = t; i < nx; i += ST_THREADS) {
-      double* xt = G + (size_t)i * nsf;  // row i: X[m][i] for m = 0..nx-1
+      double* xt = XT + (size_t)i * nx;  // row i: X[m][i] for m = 0..nx-1
       for (int m = 0; m < i; ++m) xt[m] = 0.0;
-      xt[i] = 1.0 / K[(size_t)i * ng + i];
+      xt[i] = 1.0 / S[(size_t)i * nx + i];
       for (int m = i + 1; m < nx; ++m) {
         double v = 0.0;
-        for (int p = i; p < m; ++p) v += K[(size_t)m * ng + p] * xt[p];
-        xt[m] = -v / K[(size_t)m * ng + m];
+        for (int p = i; p < m; ++p) v += S[(size_t)m * nx + p] * xt[p];
+        xt[m] = -v / S[(size_t)m * nx + m];
       }
     }
     __syncthreads();
-    block_gram(G, nsf, nx, nx, STinv + (size_t)e * nx * nx, nx, 1.0, false, As, Bs);
+    block_gram(XT, nx, nx, nx, S, nx, 1.0, false, As, Bs);
+    pack_upper(S, nx, STinv + (size_t)e * stokes_packed_stride(nx));
   }
 }
 
 // y_T = A_T (w x_T) with w = 1/2 on facet unknowns for the preconditioner
-// (R^t) and the same weight on the way out (R).
+// (R^t) and the same weight on the way out (R).  A_T is read once, as its
+// packed upper triangle.  A quarter-wave (16 lanes) owns one row: wave w
+// takes the row groups 4g .. 4g+3 with g = w, w + 4, ...; a row's lanes load
+// A[i][j], j >= i, in chunks of 16 (all chunks of the row in flight at once)
+// and give both its dot product with x (row i of y, a 16-lane reduction)
+// and the symmetric part A[i][j] x_i for the rows j > i, added to the
+// quarter's own partial y in LDS.  Every sum has a fixed order, so results
+// are bitwise reproducible.
+// CH = ceil(nx / 16) chunks per row (nx <= 16 CH).  The first row group's
+// loads are issued before the gather of x, each later group's at the end of
+// the previous one (a second register set for a deeper prefetch halves the
+// resident waves and measured slower).
+template <int CH>
 __global__ void __launch_bounds__(ST_THREADS)
     k_stokes_gemv(StokesDims sd, StokesDev dv, const double* __restrict__ A, int inv, const double* __restrict__ x,
                   double* __restrict__ y, double* __restrict__ slot) {
-  __shared__ double xs[512];
-  __shared__ double part[ST_THREADS];
-  const int t = threadIdx.x;
+  extern __shared__ double lds[];
   const int nx = sd.nx;
+  double* xs = lds;            // [nx]
+  double* yr = lds + nx;       // [nx]  row dots
+  double* yp = lds + 2 * nx;   // [16][nx] partials of the symmetric part, per quarter-wave
+  const int t = threadIdx.x, lane = t % 64, w = t / 64;
+  const int q = lane / 16, s16 = lane % 16;
   const int64_t e = blockIdx.x;
   const double wf = inv ? 0.5 : 1.0;
+  const double* Ae = A + (size_t)e * stokes_packed_stride(nx);
+  auto load_group = [&](int g, double* v) {
+    const int i = 4 * g + q;
+    const double* row = Ae + ((int64_t)i * nx - (int64_t)i * (i - 1) / 2) - i;  // row[j] = A[i][j]
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int j = i + s16 + 16 * c;
+      v[c] = (i < nx && j < nx) ? __builtin_nontemporal_load(row + j) : 0.0;
+    }
+  };
+  double v[CH];
+  load_group(w, v);
   for (int i = t; i < nx; i += ST_THREADS) {
     int fs = -1, vs = 0;
     const int64_t g = gidx(sd, dv, e, i, &fs, &vs);
     xs[i] = g >= 0 ? (fs >= 0 ? wf : 1.0) * x[g] : 0.0;
   }
+  for (int k = t; k < 16 * nx; k += ST_THREADS) yp[k] = 0.0;
   __syncthreads();
-  const double* Ae = A + (size_t)e * nx * nx;
-  // P column groups of nx threads each split the sum over j
-  const int P = nx <= ST_THREADS ? ST_THREADS / nx : 1;
-  for (int i0 = 0; i0 < nx; i0 += (nx <= ST_THREADS ? nx : ST_THREADS)) {
-    const int grp = nx <= ST_THREADS ? t / nx : 0;
-    const int i = nx <= ST_THREADS ? t % nx : i0 + t;
-    double acc = 0.0;
-    if (grp < P && i < nx) {
-      const int j0 = (int)((int64_t)nx * grp / P), j1 = (int)((int64_t)nx * (grp + 1) / P);
-      for (int j = j0; j < j1; ++j) acc += Ae[(size_t)j * nx + i] * xs[j];
-    }
-    part[t] = acc;
-    __syncthreads();
-    if (t < nx && (nx <= ST_THREADS || i0 + t < nx)) {
-      double v = 0.0;
-      if (nx <= ST_THREADS)
-        for (int p = 0; p < P; ++p) v += part[p * nx + t];
-      else
-        v = part[t];
-      const int ii = nx <= ST_THREADS ? t : i0 + t;
-      int fs = -1, vs = 0;
-      const int64_t g = gidx(sd, dv, e, ii, &fs, &vs);
-      if (g >= 0) {
-        if (fs < 0) y[g] = v;
-        else slot[((size_t)e * (sd.dim + 1) + fs) * sd.nsd + vs] = wf * v;
+  double* ypq = yp + (size_t)(4 * w + q) * nx;
+  for (int g = w; 4 * g < nx; g += 4) {
+
+    const int i = 4 * g + q;
+    double dot = 0.0;
+    if (i < nx) {
+      const double xi = xs[i];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int j = i + s16 + 16 * c;
+        if (j < nx) {
+          dot += v[c] * xs[j];
+          if (j > i) ypq[j] += v[c] * xi;
+        }
       }
     }
-    __syncthreads();
+    for (int off = 8; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 16);
+    if (s16 == 0 && i < nx) yr[i] = dot;
+    if (4 * (g + 4) < nx) load_group(g + 4, v);
+  }
+  __syncthreads();
+  for (int i = t; i < nx; i += ST_THREADS) {
+    double sym = 0.0;
+    for (int p = 0; p < 16; ++p) sym += yp[(size_t)p * nx + i];
+    const double val = yr[i] + sym;
+    int fs = -1, vs = 0;
+    const int64_t g = gidx(sd, dv, e, i, &fs, &vs);
+    if (g >= 0) {
+      if (fs < 0) y[g] = val;
+      else slot[((size_t)e * (sd.dim + 1) + fs) * sd.nsd + vs] = wf * val;
+    }
   }
 }
 
@@ -424,7 +465,17 @@ void launch_stokes_setup(hipStream_t s, const StokesDims& sd, const StokesDev& d
 
 void launch_stokes_gemv(hipStream_t s, const StokesDims& sd, const StokesDev& dv, const double* A, int inv,
                         const double* x, double* y, double* slot) {
-  if (dv.E > 0) hipLaunchKernelGGL(k_stokes_gemv, dim3((unsigned)dv.E), dim3(ST_THREADS), 0, s, sd, dv, A, inv, x, y, slot);
+  const size_t lds = (size_t)18 * sd.nx * sizeof(double);
+  const int ch = (sd.nx + 15) / 16;
+  const dim3 grid((unsigned)dv.E), blk(ST_THREADS);
+  if (dv.E > 0) {
+    if (ch <= 1) HOPU_LAUNCH(k_stokes_gemv<1>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+    else if (ch <= 2) HOPU_LAUNCH(k_stokes_gemv<2>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+    else if (ch <= 3) HOPU_LAUNCH(k_stokes_gemv<3>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+    else if (ch <= 5) HOPU_LAUNCH(k_stokes_gemv<5>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+    else if (ch <= 9) HOPU_LAUNCH(k_stokes_gemv<9>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+    else HOPU_LAUNCH(k_stokes_gemv<16>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+  }
   const int64_t nv = dv.F * sd.nsd;
   if (nv > 0) hipLaunchKernelGGL(k_stokes_facets, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, sd, dv, slot, y);
 }

@@ -226,7 +226,8 @@ class Hopu:
                                        float(rtol), int(max_it), C.byref(its)), self.h)
         return x, its.value
 
-    PROF_KINDS = {"elem": 0, "mass": 1, "prec": 2, "modal": 3, "vjp": 4, "plain": 5}
+    PROF_KINDS = {"elem": 0, "mass": 1, "prec": 2, "modal": 3, "vjp": 4, "plain": 5,
+                  "stokes_S": 6, "stokes_C": 7}
 
     def profile(self, enable, max_launches=200000):
         """enable: False/0 stops; True/1 times every launch of the main

@@ -26,6 +26,7 @@ TRAFFIC_KERNELS = [
     ("elem_fp32_k5", "k_elem<float, 3, 5, 0>"),
     ("modal_k5", "k_modal<double, 3, 5>"),
     ("rupdate", "k_rupdate<2>("),
+    ("stokes_gemv", "k_stokes_gemv<"),
     ("xpay", "k_xpay<2>("),
     ("proj_k3", "k_proj<3, 3, 0>"),
 ]
@@ -74,9 +75,14 @@ def _counter(db, name):
 
 
 def kernels_sha(src):
+    """SHA-256 (16 hex) of a kernel source: for kernels.hip the part from
+    'namespace hopu {' to the launchers marker, for other sources the whole
+    file."""
     text = open(src).read()
-    body = text[text.index("namespace hopu {"):text.index("// " + "-" * 66 + " launchers")]
-    return hashlib.sha256(body.encode()).hexdigest()[:16]
+    marker = "// " + "-" * 66 + " launchers"
+    if marker in text:
+        text = text[text.index("namespace hopu {"):text.index(marker)]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def traffic(fetch_db, write_db, src):
@@ -90,7 +96,8 @@ def traffic(fetch_db, write_db, src):
     print(f"# calibration: 1 GiB device copy ({flast[0]}) reads back FETCH_SIZE {fmax:.1f} KiB, "
           f"WRITE_SIZE {wmax:.1f} KiB")
     print(f"#   -> fetch scale {fs:.4f}, write scale {ws:.4f} (bytes = KiB * 1024 * scale)")
-    print("# kernels_sha: SHA-256 (16 hex) of kernels.hip from 'namespace hopu {' to the launchers marker")
+    print(f"# kernels_sha: SHA-256 (16 hex) of {src.split('/')[-1]} (kernels.hip: from 'namespace hopu {{' "
+          "to the launchers marker; other sources whole)")
     print("# per-launch medians over the launches at full size (> 80% of the kernel's largest)")
     print(f"kernels_sha = {kernels_sha(src)}")
     print(f"fetch_scale = {fs:.6f}")
