@@ -255,60 +255,79 @@ STOKES_STEPS = 3
 
 
 def stokes_section(torch, log):
-    """The implicit Stokes step (section 2.3, eq. (MCS_step1)) on the 3D
-    periodic Taylor-Green workload (32^3 x 6 tets, k = 3, dt = 5e-4,
-    nu = 1/1600): set-up of the element Schur complements and their inverses
-    (timed), one warm-up step, then STOKES_STEPS timed steps from the same
-    u^n (convection included, PCG to 1e-10 from zero).  The element products
-    read the packed upper triangle of S_T or S_T^-1 once per launch, so the
-    roofline is HBM: bytes = E nx (nx + 1)/2 8 per launch (the matrix;
-    vectors add < 1%) over the launch's average duration from the library's
-    events."""
+    """The splitting step of section 2.3 on the 3D periodic Taylor-Green
+    workload (32^3 x 6 tets, k = 3, dt = 5e-4, nu = 1/1600): the implicit
+    Stokes step (eq. (MCS_step1), convection of u^n on the right-hand side)
+    and the projection (eq. (MCS_step2)) of its u*, which gives the next
+    state.  Set-up of the element Schur complements and their inverses
+    (timed), one warm-up step from u0 with a zero PCG guess, then
+    STOKES_STEPS timed steps of the trajectory, each Stokes PCG started from
+    [u^n; u^ of the previous step] and run to 1e-10 of the right-hand side's
+    C^-1 norm.  The element products read the packed upper triangle of S_T
+    or S_T^-1 once per launch, so their roofline is HBM: bytes =
+    E nx (nx + 1)/2 8 per launch (the matrix; vectors add < 1%) over the
+    launch's average duration from the library's events."""
     import synth
     from paper_2408_06698_amd.hopu import Hopu
     mesh, field, cfg = synth.make_config(2)
     h = Hopu(3, cfg["k"], mesh.elem_vid, mesh.elem_xyz)
     h.set_upwind(cfg["l"])
-    un = h.interpolate(field, n1d=cfg["k"] + 1)
+    u = h.interpolate(field, n1d=cfg["k"] + 1)
     nt, nh, nx = h.stokes_sizes()
     torch.cuda.synchronize()
     t0 = time.time()
     h.stokes_setup(STOKES_NU, cfg["dt"])
     setup_s = time.time() - t0
     log(f"stokes set-up {setup_s:.1f} s ({mesh.n_elems} elements, {nx} unknowns each)")
-    x, its0 = h.stokes_step(un, with_convection=True, rtol=1e-10)
+    x, its0 = h.stokes_step(u, with_convection=True, rtol=1e-10)
+    u = h.project(x[:h.n_dof], rtol=1e-13)[0]
     h.profile(1)
-    torch.cuda.synchronize()
-    t1 = time.time()
-    its = []
+    its, pits, ms_st, ms_pr, div = [], [], [], [], []
     for _ in range(STOKES_STEPS):
-        its.append(h.stokes_step(un, with_convection=True, out=x, rtol=1e-10)[1])
-    torch.cuda.synchronize()
-    ms = (time.time() - t1) * 1e3 / STOKES_STEPS
+        x[:h.n_dof].copy_(u)
+        torch.cuda.synchronize()
+        t1 = time.time()
+        its.append(h.stokes_step(u, with_convection=True, out=x, rtol=1e-10, guess=True)[1])
+        t2 = time.time()
+        div_star = h.diagnostics(x[:h.n_dof].contiguous())[1]
+        torch.cuda.synchronize()
+        t3 = time.time()
+        u, pit = h.project(x[:h.n_dof], rtol=1e-13)
+        torch.cuda.synchronize()
+        t4 = time.time()
+        pits.append(pit)
+        ms_st.append((t2 - t1) * 1e3)
+        ms_pr.append((t4 - t3) * 1e3)
+        div.append((div_star, h.diagnostics(u)[1]))
     nS, msS = h.profile_read("stokes_S")
     nC, msC = h.profile_read("stokes_C")
     h.profile(False)
+    ms = sum(ms_st) / len(ms_st)
     # the packed upper triangle of S_T^-1 (padded to 8 doubles per element)
     mat_bytes = mesh.n_elems * ((nx * (nx + 1) // 2 + 7) // 8 * 8) * 8
     avg_S, avg_C = msS / max(nS, 1), msC / max(nC, 1)
     ach = mat_bytes / (avg_C * 1e-3)
     out = {
-        "workload": WORKLOADS[2].replace("one substep per step", "one implicit Stokes step per step")
-        + f", nu={STOKES_NU}",
+        "workload": WORKLOADS[2].replace("one substep per step", "one splitting step (implicit Stokes step + "
+                                         "projection) per step") + f", nu={STOKES_NU}",
         "n_unknowns": nt, "n_uhat": nh, "unknowns_per_element": nx,
-        "setup_s": setup_s, "pcg_iterations": its, "pcg_iterations_first": its0, "rtol": 1e-10,
-        "ms_per_step": ms, "ms_per_iteration": ms / max(1, sum(its) / len(its)),
-        "dof_updates_per_s": h.n_dof / (ms * 1e-3),
+        "setup_s": setup_s, "pcg_iterations": its, "pcg_iterations_first_zero_guess": its0, "rtol": 1e-10,
+        "ms_per_stokes_step": ms, "ms_per_pcg_iteration": ms / max(1.0, sum(its) / len(its)),
+        "stokes_dof_updates_per_s": h.n_dof / (ms * 1e-3),
+        "projection_ms": sum(ms_pr) / len(ms_pr), "projection_cg_iterations": pits,
+        "ms_per_splitting_step": (sum(ms_st) + sum(ms_pr)) / len(ms_st),
+        "div_l2_before_after_projection": div,
         "kernel_avg_ms": {"stokes_S": avg_S, "stokes_C": avg_C},
         "kernel_launches": {"stokes_S": nS, "stokes_C": nC},
         "roofline": {"kernel": "k_stokes_gemv (S_T^-1, the preconditioner)", "bound": "hbm",
                      "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                      "frac": ach / PEAK_HBM, "traffic": traffic_from_profiles("stokes_gemv", "stokes_kernels.hip"),
                      "algorithmic_bytes_per_launch": mat_bytes},
-        "timing": "host clock around STOKES_STEPS hopu_stokes_step calls (each synchronises); kernel "
-                  "averages from the library's HIP events on every launch",
+        "timing": "host clock around each hopu_stokes_step and hopu_project call (both synchronise); kernel "
+                  "averages from the library's HIP events on every element-product launch",
     }
-    log(f"stokes: {ms:.1f} ms per step, {its} PCG iterations, element product {avg_S:.2f} / {avg_C:.2f} ms")
+    log(f"stokes: {ms:.1f} ms per step, {its} PCG iterations, element product {avg_S:.2f} / {avg_C:.2f} ms; "
+        f"projection {out['projection_ms']:.1f} ms")
     h.close()
     return out
 

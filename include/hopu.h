@@ -302,20 +302,25 @@ void hopu_destroy(hopu_ctx ctx);
  * hopu_stokes_precond: y = C^-1 x = R S_BDDC^-1 R^t x (R averages the two
  *   copies of every facet unknown).
  * hopu_stokes_step: one step of eq. (MCS_step1) from u^n (n_dof entries):
- *   PCG on S X = [M u^n/dt - r(u^n); 0] with C^-1 from X = 0, where r is the
- *   FP64 convection residual of hopu_convection_apply with the context's
- *   upwind setting when with_convection != 0 and zero otherwise.  Writes X
- *   = [u*; u^] to x (n_total entries) and the iteration count to *iters
- *   (may be NULL).  Stops when the C^-1 norm of the residual falls below rtol
- *   times its initial value; HOPU_ENOCONV after max_it iterations (x then
- *   holds the last iterate).  Synchronises the context's stream.
+ *   PCG on S X = [M u^n/dt - r(u^n); 0] with C^-1, where r is the FP64
+ *   convection residual of hopu_convection_apply with the context's upwind
+ *   setting when flags has HOPU_STOKES_CONVECTION and zero otherwise.  The
+ *   PCG starts from X = 0, or from the contents of x when flags has
+ *   HOPU_STOKES_GUESS (in a time loop [u^n; u^ of the previous step] is a
+ *   good guess).  Writes X = [u*; u^] to x (n_total entries) and the
+ *   iteration count to *iters (may be NULL).  Stops when the C^-1 norm of
+ *   the residual falls below rtol times the C^-1 norm of the right-hand
+ *   side; HOPU_ENOCONV after max_it iterations (x then holds the last
+ *   iterate); HOPU_EINVAL for other flag bits.  Synchronises the context's
+ *   stream.
  * Every Stokes call except hopu_stokes_sizes needs hopu_stokes_setup first
  * (HOPU_EINVAL otherwise). */
 hopu_status hopu_stokes_sizes(hopu_ctx ctx, int64_t* n_total, int64_t* n_uhat, int* n_elem_unknowns);
 hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt);
 hopu_status hopu_stokes_apply(hopu_ctx ctx, const double* x, double* y);
 hopu_status hopu_stokes_precond(hopu_ctx ctx, const double* x, double* y);
-hopu_status hopu_stokes_step(hopu_ctx ctx, const double* un, int with_convection, double* x, double rtol,
+enum { HOPU_STOKES_CONVECTION = 1, HOPU_STOKES_GUESS = 2 };
+hopu_status hopu_stokes_step(hopu_ctx ctx, const double* un, int flags, double* x, double rtol,
                              int max_it, int* iters);
 
 /* ---- host-only inspection (no HIP calls; used by CPU tests) ------------

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libhopu.so")
 HOPU_OK, HOPU_EINVAL, HOPU_EMESH, HOPU_ENOMEM, HOPU_EHIP, HOPU_ENOCONV, HOPU_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32_MFMA, BF16X2, BF16X3 = 0, 1, 2, 3
 TERM_VOLUME, TERM_CENTRAL, TERM_UPWIND, TERM_ALL = 1, 2, 4, 7
+HOPU_STOKES_CONVECTION, HOPU_STOKES_GUESS = 1, 2
 
 STATUS_NAMES = {0: "HOPU_OK", -1: "HOPU_EINVAL", -2: "HOPU_EMESH", -3: "HOPU_ENOMEM",
                 -4: "HOPU_EHIP", -5: "HOPU_ENOCONV", -6: "HOPU_EUNSUPPORTED"}

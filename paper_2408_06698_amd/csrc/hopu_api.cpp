@@ -1495,15 +1495,17 @@ static hopu_status stokes_dot(hopu_ctx ctx, const double* a, const double* b, in
   return HOPU_OK;
 }
 
-extern "C" hopu_status hopu_stokes_step(hopu_ctx ctx, const double* un, int with_convection, double* x, double rtol,
+extern "C" hopu_status hopu_stokes_step(hopu_ctx ctx, const double* un, int flags, double* x, double rtol,
                                         int max_it, int* iters) {
   RocRange range("hopu_stokes_step");
   if (!ctx) return HOPU_EINVAL;
   if (!un || !x) return fail(ctx, HOPU_EINVAL, "NULL vector");
   if (!(rtol > 0.0) || max_it < 1) return fail(ctx, HOPU_EINVAL, "rtol must be > 0 and max_it >= 1");
+  if (flags & ~(HOPU_STOKES_CONVECTION | HOPU_STOKES_GUESS)) return fail(ctx, HOPU_EINVAL, "unknown flags");
   if (hopu_status st = stokes_check(ctx)) return st;
   hipStream_t s = ctx->stream;
   const int64_t nX = ctx->n_dof + stokes_n_uhat(ctx);
+  const bool with_convection = (flags & HOPU_STOKES_CONVECTION) != 0;
   // b = [M u^n / dt - r(u^n); 0]
   do_mass(ctx, 0, un, ctx->st_mu, nullptr);
   if (with_convection) {
@@ -1511,14 +1513,24 @@ extern "C" hopu_status hopu_stokes_step(hopu_ctx ctx, const double* un, int with
     if (hopu_status st = do_apply(ctx, un, ctx->st_conv, 7, HOPU_FP64, nullptr)) return st;
   }
   launch_stokes_rhs(s, ctx->st_b, ctx->st_mu, with_convection ? ctx->st_conv : nullptr, ctx->st_dt, ctx->n_dof, nX);
-  // PCG on S with C^-1 = R S_BDDC^-1 R^t from x = 0
-  HCHECK(hipMemsetAsync(x, 0, (size_t)nX * sizeof(double), s));
+  // PCG on S with C^-1 = R S_BDDC^-1 R^t from x = 0 or the caller's guess;
+  // the stopping rule is relative to the C^-1 norm of b either way
   vec_copy(s, ctx->st_r, ctx->st_b, nX);
   stokes_gemv(ctx, 1, ctx->st_r, ctx->st_z);
+  double bz = 0.0;
+  if (hopu_status st = stokes_dot(ctx, ctx->st_r, ctx->st_z, nX, &bz)) return st;
+  const double stop = rtol * std::sqrt(std::fabs(bz));
+  double rz = bz;
+  if (flags & HOPU_STOKES_GUESS) {
+    // r = b - S x
+    stokes_gemv(ctx, 0, x, ctx->st_q);
+    launch_stokes_axpy(s, ctx->st_r, ctx->st_q, -1.0, nX);
+    stokes_gemv(ctx, 1, ctx->st_r, ctx->st_z);
+    if (hopu_status st = stokes_dot(ctx, ctx->st_r, ctx->st_z, nX, &rz)) return st;
+  } else {
+    HCHECK(hipMemsetAsync(x, 0, (size_t)nX * sizeof(double), s));
+  }
   vec_copy(s, ctx->st_p, ctx->st_z, nX);
-  double rz = 0.0;
-  if (hopu_status st = stokes_dot(ctx, ctx->st_r, ctx->st_z, nX, &rz)) return st;
-  const double stop = rtol * std::sqrt(std::fabs(rz));
   int it = 0;
   bool conv = !(std::sqrt(std::fabs(rz)) > stop);
   while (!conv && it < max_it) {

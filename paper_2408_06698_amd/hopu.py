@@ -218,11 +218,15 @@ class Hopu:
         check(L.lib().hopu_stokes_precond(self.h, _ptr(_dev(x, y.numel())), _ptr(y)), self.h)
         return y
 
-    def stokes_step(self, un, with_convection=True, out=None, rtol=1e-12, max_it=2000):
-        """[u*; u^] of one implicit Stokes step from u^n; returns (x, iterations)."""
+    def stokes_step(self, un, with_convection=True, out=None, rtol=1e-12, max_it=2000, guess=False):
+        """[u*; u^] of one implicit Stokes step from u^n; returns (x, iterations).
+        guess: start the PCG from the contents of `out` (else from zero)."""
+        if guess and out is None:
+            raise ValueError("guess=True needs the initial guess in `out`")
         x = self._stokes_vec(out)
+        flags = (L.HOPU_STOKES_CONVECTION if with_convection else 0) | (L.HOPU_STOKES_GUESS if guess else 0)
         its = C.c_int()
-        check(L.lib().hopu_stokes_step(self.h, _ptr(_dev(un, self.n_dof)), int(bool(with_convection)), _ptr(x),
+        check(L.lib().hopu_stokes_step(self.h, _ptr(_dev(un, self.n_dof)), flags, _ptr(x),
                                        float(rtol), int(max_it), C.byref(its)), self.h)
         return x, its.value
 

@@ -177,3 +177,27 @@ def test_stokes_step_decay_factor_at_size():
     rel = float(torch.sqrt((e * Me).sum() / (un * Mu).sum()))
     print(f"  iterations {its}, relative M-norm error {rel:.3e}", flush=True)
     assert rel <= 1e-4
+
+
+def test_stokes_step_initial_guess():
+    """HOPU_STOKES_GUESS: the PCG from a guess reaches the same solution as
+    from zero (to the stopping rule), in fewer iterations from a nearby
+    solution, and from the solution itself in at most one."""
+    print("stokes step with a guess", flush=True)
+    m, sp = _case(3, 2, 3, True)
+    f = lambda x: np.stack([np.sin(np.pi * x[..., 1]), 0.0 * x[..., 0], 0.0 * x[..., 0]], -1)
+    un = sp.interpolate(f)
+    g = _gpu(m, 2)
+    g.stokes_setup(0.05, 0.02)
+    u = dev(un)
+    x0, its0 = g.stokes_step(u, rtol=1e-12)
+    ref = host(x0)
+    # a good guess: the solution from a nearby state (the previous step of a
+    # time loop); [u^n; 0] is not one (u^ = 0 contradicts u's tangential trace)
+    near = u + dev(1e-3 * np.random.default_rng(1).standard_normal(g.n_dof))
+    xg, _ = g.stokes_step(near, rtol=1e-12)
+    x1, its1 = g.stokes_step(u, out=xg, rtol=1e-12, guess=True)
+    assert _blockerr(sp, host(x1), ref) <= 1e-10
+    assert its1 < its0, (its1, its0)
+    x2, its2 = g.stokes_step(u, out=x0.clone(), rtol=1e-12, guess=True)
+    assert its2 <= 1 and _blockerr(sp, host(x2), ref) <= 1e-12
