@@ -280,33 +280,52 @@ def stokes_section(torch, log):
     setup_s = time.time() - t0
     log(f"stokes set-up {setup_s:.1f} s ({mesh.n_elems} elements, {nx} unknowns each)")
     x, its0 = h.stokes_step(u, with_convection=True, rtol=1e-10)
-    u = h.project(x[:h.n_dof], rtol=1e-13)[0]
-    h.profile(1)
-    its, pits, ms_st, ms_pr, div = [], [], [], [], []
-    for _ in range(STOKES_STEPS):
-        x[:h.n_dof].copy_(u)
-        torch.cuda.synchronize()
-        t1 = time.time()
-        its.append(h.stokes_step(u, with_convection=True, out=x, rtol=1e-10, guess=True)[1])
-        t2 = time.time()
-        div_star = h.diagnostics(x[:h.n_dof].contiguous())[1]
-        torch.cuda.synchronize()
-        t3 = time.time()
-        u, pit = h.project(x[:h.n_dof], rtol=1e-13)
-        torch.cuda.synchronize()
-        t4 = time.time()
-        pits.append(pit)
-        ms_st.append((t2 - t1) * 1e3)
-        ms_pr.append((t4 - t3) * 1e3)
-        div.append((div_star, h.diagnostics(u)[1]))
-    nS, msS = h.profile_read("stokes_S")
-    nC, msC = h.profile_read("stokes_C")
-    h.profile(False)
+    u0 = h.project(x[:h.n_dof], rtol=1e-13)[0]
+    x0 = x.clone()
+
+    def trajectory(fp32):
+        """STOKES_STEPS timed splitting steps from u0 (PCG guess [u^n; u^ of
+        the previous step], the first from the warm-up step's solution)."""
+        u, x = u0.clone(), x0.clone()
+        h.profile(1)
+        its, pits, ms_st, ms_pr, div = [], [], [], [], []
+        for _ in range(STOKES_STEPS):
+            x[:h.n_dof].copy_(u)
+            torch.cuda.synchronize()
+            t1 = time.time()
+            its.append(h.stokes_step(u, with_convection=True, out=x, rtol=1e-10, guess=True)[1])
+            t2 = time.time()
+            div_star = h.diagnostics(x[:h.n_dof].contiguous())[1]
+            torch.cuda.synchronize()
+            t3 = time.time()
+            u, pit = h.project(x[:h.n_dof], rtol=1e-13)
+            torch.cuda.synchronize()
+            t4 = time.time()
+            pits.append(pit)
+            ms_st.append((t2 - t1) * 1e3)
+            ms_pr.append((t4 - t3) * 1e3)
+            div.append((div_star, h.diagnostics(u)[1]))
+        prof = {kk: h.profile_read(kk) for kk in ("stokes_S", "stokes_C")}
+        h.profile(False)
+        return u, its, pits, ms_st, ms_pr, div, prof
+
+    u64, its, pits, ms_st, ms_pr, div, prof = trajectory(False)
+    (nS, msS), (nC, msC) = prof["stokes_S"], prof["stokes_C"]
     ms = sum(ms_st) / len(ms_st)
-    # the packed upper triangle of S_T^-1 (padded to 8 doubles per element)
-    mat_bytes = mesh.n_elems * ((nx * (nx + 1) // 2 + 7) // 8 * 8) * 8
+    # the packed upper triangle of S_T^-1 (padded to 8 entries per element)
+    packed = mesh.n_elems * ((nx * (nx + 1) // 2 + 7) // 8 * 8)
+    mat_bytes = packed * 8
     avg_S, avg_C = msS / max(nS, 1), msC / max(nC, 1)
     ach = mat_bytes / (avg_C * 1e-3)
+    # the same trajectory with S_T^-1 in FP32
+    t0 = time.time()
+    h.stokes_setup(STOKES_NU, cfg["dt"], fp32_precond=True)
+    setup32 = time.time() - t0
+    u32, its32, _, ms_st32, _, _, prof32 = trajectory(True)
+    d = u32 - u64
+    rel32 = float(torch.sqrt(torch.dot(d, h.mass_apply(d)) / torch.dot(u64, h.mass_apply(u64))))
+    avg_C32 = prof32["stokes_C"][1] / max(prof32["stokes_C"][0], 1)
+    ms32 = sum(ms_st32) / len(ms_st32)
     out = {
         "workload": WORKLOADS[2].replace("one substep per step", "one splitting step (implicit Stokes step + "
                                          "projection) per step") + f", nu={STOKES_NU}",
@@ -323,11 +342,18 @@ def stokes_section(torch, log):
                      "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                      "frac": ach / PEAK_HBM, "traffic": traffic_from_profiles("stokes_gemv", "stokes_kernels.hip"),
                      "algorithmic_bytes_per_launch": mat_bytes},
+        "fp32_preconditioner": {
+            "setup_s": setup32, "pcg_iterations": its32, "ms_per_stokes_step": ms32,
+            "speedup_stokes_step": ms / ms32, "kernel_avg_ms_stokes_C": avg_C32,
+            "hbm_frac_stokes_C": packed * 4 / (avg_C32 * 1e-3) / PEAK_HBM,
+            "state_rel_err_vs_fp64_M_norm": rel32,
+            "protocol": f"S_T^-1 in FP32, S and the vectors FP64; the same {STOKES_STEPS}-step trajectory from "
+                        "the same state, final states compared"},
         "timing": "host clock around each hopu_stokes_step and hopu_project call (both synchronise); kernel "
                   "averages from the library's HIP events on every element-product launch",
     }
     log(f"stokes: {ms:.1f} ms per step, {its} PCG iterations, element product {avg_S:.2f} / {avg_C:.2f} ms; "
-        f"projection {out['projection_ms']:.1f} ms")
+        f"projection {out['projection_ms']:.1f} ms; FP32 preconditioner {ms32:.1f} ms per step, {its32}")
     h.close()
     return out
 

@@ -292,7 +292,10 @@ void hopu_destroy(hopu_ctx ctx);
  *
  * hopu_stokes_sizes: n_total, n_uhat and the unknowns per element of S_T
  *   (any pointer may be NULL).
- * hopu_stokes_setup: nu > 0, dt > 0.  Builds on the GPU, per element, S_T on
+ * hopu_stokes_setup: nu > 0, dt > 0; flags 0 or HOPU_STOKES_FP32_PRECOND (keep
+ *   S_T^-1 in FP32: the preconditioner's element products read half the
+ *   bytes and compute in FP64; S, the vectors and the inner products stay
+ *   FP64, so the step meets the same tolerance).  Builds on the GPU, per element, S_T on
  *   its velocity and u^ unknowns and S_T^-1, and keeps both in device memory
  *   (their upper triangles: about E nx^2 doubles, nx from hopu_stokes_sizes).  Allocates on its first
  *   call (HOPU_ENOMEM if that fails) and a set-up scratch for each call;
@@ -316,7 +319,8 @@ void hopu_destroy(hopu_ctx ctx);
  * Every Stokes call except hopu_stokes_sizes needs hopu_stokes_setup first
  * (HOPU_EINVAL otherwise). */
 hopu_status hopu_stokes_sizes(hopu_ctx ctx, int64_t* n_total, int64_t* n_uhat, int* n_elem_unknowns);
-hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt);
+enum { HOPU_STOKES_FP32_PRECOND = 1 };
+hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt, int flags);
 hopu_status hopu_stokes_apply(hopu_ctx ctx, const double* x, double* y);
 hopu_status hopu_stokes_precond(hopu_ctx ctx, const double* x, double* y);
 enum { HOPU_STOKES_CONVECTION = 1, HOPU_STOKES_GUESS = 2 };

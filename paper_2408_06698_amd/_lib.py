@@ -14,6 +14,7 @@ HOPU_OK, HOPU_EINVAL, HOPU_EMESH, HOPU_ENOMEM, HOPU_EHIP, HOPU_ENOCONV, HOPU_EUN
 FP64, FP32_MFMA, BF16X2, BF16X3 = 0, 1, 2, 3
 TERM_VOLUME, TERM_CENTRAL, TERM_UPWIND, TERM_ALL = 1, 2, 4, 7
 HOPU_STOKES_CONVECTION, HOPU_STOKES_GUESS = 1, 2
+HOPU_STOKES_FP32_PRECOND = 1
 
 STATUS_NAMES = {0: "HOPU_OK", -1: "HOPU_EINVAL", -2: "HOPU_EMESH", -3: "HOPU_ENOMEM",
                 -4: "HOPU_EHIP", -5: "HOPU_ENOCONV", -6: "HOPU_EUNSUPPORTED"}
@@ -54,7 +55,7 @@ SIGNATURES = {
     "hopu_host_mesh": (_i64, [_i, _i64, _p, _p, _i, _p, _i64]),
     "hopu_host_sizes": (_i64, [_i, _i, _i]),
     "hopu_stokes_sizes": (_i, [_p, _p, _p, _p]),
-    "hopu_stokes_setup": (_i, [_p, _d, _d]),
+    "hopu_stokes_setup": (_i, [_p, _d, _d, _i]),
     "hopu_stokes_apply": (_i, [_p, _p, _p]),
     "hopu_stokes_precond": (_i, [_p, _p, _p]),
     "hopu_stokes_step": (_i, [_p, _p, _i, _p, _d, _i, _p]),

@@ -107,7 +107,7 @@ struct hopu_ctx_s {
   // implicit Stokes step (tables and workspaces on the first hopu_stokes_setup)
   StokesDims st_sd;
   StokesDev st_dv{};
-  bool st_alloc = false, st_ready = false;
+  bool st_alloc = false, st_ready = false, st_fp32 = false;
   double st_nu = 0.0, st_dt = 0.0;
   double *st_S = nullptr, *st_Sinv = nullptr, *st_slot = nullptr;
   double *st_r = nullptr, *st_z = nullptr, *st_p = nullptr, *st_q = nullptr, *st_b = nullptr;
@@ -1417,11 +1417,12 @@ static hopu_status stokes_alloc(hopu_ctx ctx) {
   return HOPU_OK;
 }
 
-extern "C" hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt) {
+extern "C" hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt, int flags) {
   RocRange range("hopu_stokes_setup");
   if (!ctx) return HOPU_EINVAL;
   if (!(nu > 0.0) || !(dt > 0.0) || !std::isfinite(nu) || !std::isfinite(dt))
     return fail(ctx, HOPU_EINVAL, "nu and dt must be positive and finite");
+  if (flags & ~HOPU_STOKES_FP32_PRECOND) return fail(ctx, HOPU_EINVAL, "unknown flags");
   if (!stokes_supported(ctx->dim, ctx->k))
     return fail(ctx, HOPU_EUNSUPPORTED, "the Stokes step is built for 2D k <= 4 and 3D k <= 3");
   hopu_status st;
@@ -1436,7 +1437,9 @@ extern "C" hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt) {
   if (hipMalloc(&scratch, nscr * sizeof(double)) != hipSuccess)
     return fail(ctx, HOPU_ENOMEM, "hipMalloc of the Stokes set-up scratch failed");
   HCHECK(hipMemsetAsync(ctx->st_bad, 0, sizeof(int), s));
-  launch_stokes_setup(s, ctx->st_sd, ctx->st_dv, nu, dt, ctx->st_S, ctx->st_Sinv, scratch, ctx->st_bad);
+  const bool fp32 = (flags & HOPU_STOKES_FP32_PRECOND) != 0;
+  launch_stokes_setup(s, ctx->st_sd, ctx->st_dv, nu, dt, ctx->st_S, ctx->st_Sinv,
+                      fp32 ? reinterpret_cast<float*>(ctx->st_Sinv) : nullptr, scratch, ctx->st_bad);
   int bad = 0;
   hipError_t e1 = hipGetLastError();
   hipError_t e2 = hipMemcpyAsync(&bad, ctx->st_bad, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -1448,6 +1451,7 @@ extern "C" hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt) {
   if (bad) return fail(ctx, HOPU_EINVAL, "an element matrix of the Stokes step is not positive definite");
   ctx->st_nu = nu;
   ctx->st_dt = dt;
+  ctx->st_fp32 = fp32;
   ctx->st_ready = true;
   return HOPU_OK;
 }
@@ -1455,7 +1459,9 @@ extern "C" hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt) {
 // the Stokes element product (S or C^-1), timed as its own kernel kind
 static void stokes_gemv(hopu_ctx ctx, int inv, const double* x, double* y) {
   prof_begin(ctx, inv ? PROF_STOKES_C : PROF_STOKES_S);
-  launch_stokes_gemv(ctx->stream, ctx->st_sd, ctx->st_dv, inv ? ctx->st_Sinv : ctx->st_S, inv, x, y, ctx->st_slot);
+  const float* a32 = (inv && ctx->st_fp32) ? reinterpret_cast<const float*>(ctx->st_Sinv) : nullptr;
+  launch_stokes_gemv(ctx->stream, ctx->st_sd, ctx->st_dv, inv ? ctx->st_Sinv : ctx->st_S, a32, inv, x, y,
+                     ctx->st_slot);
   prof_end(ctx);
 }
 

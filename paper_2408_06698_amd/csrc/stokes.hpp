@@ -78,13 +78,15 @@ __host__ __device__ inline int64_t stokes_packed_stride(int nx) {
 // nblocks * (ng * nsf + ng * ng) doubles.
 int stokes_setup_blocks(const StokesDims& sd);
 size_t stokes_setup_scratch(const StokesDims& sd);
+// STinv32 non-null: S_T^-1 is stored in FP32 there instead of STinv.
 void launch_stokes_setup(hipStream_t s, const StokesDims& sd, const StokesDev& dv, double nu, double dt,
-                         double* ST, double* STinv, double* scratch, int* bad);
+                         double* ST, double* STinv, float* STinv32, double* scratch, int* bad);
 // y = A x with A = S (inv = 0) or C_BDDC^-1 (inv = 1): element products
 // (interior velocity rows into y, facet-side values into slot [E][d+1][nsd]),
-// then the facet rows assembled from both sides.
-void launch_stokes_gemv(hipStream_t s, const StokesDims& sd, const StokesDev& dv, const double* A, int inv,
-                        const double* x, double* y, double* slot);
+// then the facet rows assembled from both sides.  The element matrices are
+// read from A32 (FP32, FP64 arithmetic) when it is non-null, else from A.
+void launch_stokes_gemv(hipStream_t s, const StokesDims& sd, const StokesDev& dv, const double* A, const float* A32,
+                        int inv, const double* x, double* y, double* slot);
 // per-block partials of a . b over n entries (npart of them)
 int launch_stokes_dot(hipStream_t s, const double* a, const double* b, int64_t n, double* part);
 // y += a x

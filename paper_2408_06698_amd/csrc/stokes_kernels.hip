@@ -116,10 +116,11 @@ __device__ void block_cholesky(double* A, int lda, int n, int* bad) {
 
 // Upper triangle of the symmetric n x n matrix A (row stride n), packed by
 // rows: row i holds A[i][i..n-1] at offset i n - i (i - 1)/2.
-__device__ void pack_upper(const double* A, int n, double* out) {
+template <typename OT>
+__device__ void pack_upper(const double* A, int n, OT* out) {
   for (int64_t v = threadIdx.x; v < (int64_t)n * n; v += ST_THREADS) {
     const int i = (int)(v / n), j = (int)(v % n);
-    if (j >= i) out[(int64_t)i * n - (int64_t)i * (i - 1) / 2 + (j - i)] = A[v];
+    if (j >= i) out[(int64_t)i * n - (int64_t)i * (i - 1) / 2 + (j - i)] = (OT)A[v];
   }
   __syncthreads();
 }
@@ -152,7 +153,8 @@ __device__ inline int64_t gidx(const StokesDims& sd, const StokesDev& dv, int64_
 
 __global__ void __launch_bounds__(ST_THREADS)
     k_stokes_setup(StokesDims sd, StokesDev dv, double nu, double dt, double* __restrict__ ST,
-                   double* __restrict__ STinv, double* __restrict__ scratch, int* bad) {
+                   double* __restrict__ STinv, float* __restrict__ STinv32, double* __restrict__ scratch,
+                   int* bad) {
   __shared__ double As[TILE * (KCH + 1)], Bs[TILE * (KCH + 1)];
   __shared__ double H[8 * 9];   // J^-1 E_a^T J
   __shared__ double Gm[9];      // J^T J
@@ -318,7 +320,8 @@ __global__ void __launch_bounds__(ST_THREADS)
     }
     __syncthreads();
     block_gram(XT, nx, nx, nx, S, nx, 1.0, false, As, Bs);
-    pack_upper(S, nx, STinv + (size_t)e * stokes_packed_stride(nx));
+    if (STinv32) pack_upper(S, nx, STinv32 + (size_t)e * stokes_packed_stride(nx));
+    else pack_upper(S, nx, STinv + (size_t)e * stokes_packed_stride(nx));
   }
 }
 
@@ -335,9 +338,9 @@ __global__ void __launch_bounds__(ST_THREADS)
 // loads are issued before the gather of x, each later group's at the end of
 // the previous one (a second register set for a deeper prefetch halves the
 // resident waves and measured slower).
-template <int CH>
+template <int CH, typename MT>
 __global__ void __launch_bounds__(ST_THREADS)
-    k_stokes_gemv(StokesDims sd, StokesDev dv, const double* __restrict__ A, int inv, const double* __restrict__ x,
+    k_stokes_gemv(StokesDims sd, StokesDev dv, const MT* __restrict__ A, int inv, const double* __restrict__ x,
                   double* __restrict__ y, double* __restrict__ slot) {
   extern __shared__ double lds[];
   const int nx = sd.nx;
@@ -348,28 +351,21 @@ __global__ void __launch_bounds__(ST_THREADS)
   const int q = lane / 16, s16 = lane % 16;
   const int64_t e = blockIdx.x;
   const double wf = inv ? 0.5 : 1.0;
-  const double* Ae = A + (size_t)e * stokes_packed_stride(nx);
-  auto load_group = [&](int g, double* v) {
+  const MT* Ae = A + (size_t)e * stokes_packed_stride(nx);
+  // the row group's loads land in registers of the stored type; FP32
+  // matrices keep two groups in flight per wave (same register budget as
+  // one FP64 group)
+  auto load_group = [&](int g, MT* v) {
     const int i = 4 * g + q;
-    const double* row = Ae + ((int64_t)i * nx - (int64_t)i * (i - 1) / 2) - i;  // row[j] = A[i][j]
+    const MT* row = Ae + ((int64_t)i * nx - (int64_t)i * (i - 1) / 2) - i;  // row[j] = A[i][j]
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int j = i + s16 + 16 * c;
-      v[c] = (i < nx && j < nx) ? __builtin_nontemporal_load(row + j) : 0.0;
+      v[c] = (i < nx && j < nx) ? __builtin_nontemporal_load(row + j) : (MT)0;
     }
   };
-  double v[CH];
-  load_group(w, v);
-  for (int i = t; i < nx; i += ST_THREADS) {
-    int fs = -1, vs = 0;
-    const int64_t g = gidx(sd, dv, e, i, &fs, &vs);
-    xs[i] = g >= 0 ? (fs >= 0 ? wf : 1.0) * x[g] : 0.0;
-  }
-  for (int k = t; k < 16 * nx; k += ST_THREADS) yp[k] = 0.0;
-  __syncthreads();
   double* ypq = yp + (size_t)(4 * w + q) * nx;
-  for (int g = w; 4 * g < nx; g += 4) {
-
+  auto use_group = [&](int g, const MT* v) {
     const int i = 4 * g + q;
     double dot = 0.0;
     if (i < nx) {
@@ -378,14 +374,44 @@ __global__ void __launch_bounds__(ST_THREADS)
       for (int c = 0; c < CH; ++c) {
         const int j = i + s16 + 16 * c;
         if (j < nx) {
-          dot += v[c] * xs[j];
-          if (j > i) ypq[j] += v[c] * xi;
+          dot += (double)v[c] * xs[j];
+          if (j > i) ypq[j] += (double)v[c] * xi;
         }
       }
     }
     for (int off = 8; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 16);
     if (s16 == 0 && i < nx) yr[i] = dot;
-    if (4 * (g + 4) < nx) load_group(g + 4, v);
+  };
+  auto gather = [&]() {
+    for (int i = t; i < nx; i += ST_THREADS) {
+      int fs = -1, vs = 0;
+      const int64_t g = gidx(sd, dv, e, i, &fs, &vs);
+      xs[i] = g >= 0 ? (fs >= 0 ? wf : 1.0) * x[g] : 0.0;
+    }
+    for (int k = t; k < 16 * nx; k += ST_THREADS) yp[k] = 0.0;
+    __syncthreads();
+  };
+  if constexpr (sizeof(MT) == 4) {
+    MT va[CH], vb[CH];
+    load_group(w, va);
+    if (4 * (w + 4) < nx) load_group(w + 4, vb);
+    gather();
+    for (int g = w; 4 * g < nx; g += 8) {
+      use_group(g, va);
+      if (4 * (g + 8) < nx) load_group(g + 8, va);
+      if (4 * (g + 4) < nx) {
+        use_group(g + 4, vb);
+        if (4 * (g + 12) < nx) load_group(g + 12, vb);
+      }
+    }
+  } else {
+    MT v[CH];
+    load_group(w, v);
+    gather();
+    for (int g = w; 4 * g < nx; g += 4) {
+      use_group(g, v);
+      if (4 * (g + 4) < nx) load_group(g + 4, v);
+    }
   }
   __syncthreads();
   for (int i = t; i < nx; i += ST_THREADS) {
@@ -457,24 +483,32 @@ size_t stokes_setup_scratch(const StokesDims& sd) {
 }
 
 void launch_stokes_setup(hipStream_t s, const StokesDims& sd, const StokesDev& dv, double nu, double dt, double* ST,
-                         double* STinv, double* scratch, int* bad) {
+                         double* STinv, float* STinv32, double* scratch, int* bad) {
   const int nb = (int)std::min<int64_t>(stokes_setup_blocks(sd), dv.E);
   if (nb <= 0) return;
-  hipLaunchKernelGGL(k_stokes_setup, dim3(nb), dim3(ST_THREADS), 0, s, sd, dv, nu, dt, ST, STinv, scratch, bad);
+  hipLaunchKernelGGL(k_stokes_setup, dim3(nb), dim3(ST_THREADS), 0, s, sd, dv, nu, dt, ST, STinv, STinv32, scratch,
+                     bad);
 }
 
-void launch_stokes_gemv(hipStream_t s, const StokesDims& sd, const StokesDev& dv, const double* A, int inv,
-                        const double* x, double* y, double* slot) {
+template <typename MT>
+static void gemv_dispatch(hipStream_t s, const StokesDims& sd, const StokesDev& dv, const MT* A, int inv,
+                          const double* x, double* y, double* slot) {
   const size_t lds = (size_t)18 * sd.nx * sizeof(double);
   const int ch = (sd.nx + 15) / 16;
   const dim3 grid((unsigned)dv.E), blk(ST_THREADS);
+  if (ch <= 1) HOPU_LAUNCH((k_stokes_gemv<1, MT>), grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+  else if (ch <= 2) HOPU_LAUNCH((k_stokes_gemv<2, MT>), grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+  else if (ch <= 3) HOPU_LAUNCH((k_stokes_gemv<3, MT>), grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+  else if (ch <= 5) HOPU_LAUNCH((k_stokes_gemv<5, MT>), grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+  else if (ch <= 9) HOPU_LAUNCH((k_stokes_gemv<9, MT>), grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+  else HOPU_LAUNCH((k_stokes_gemv<16, MT>), grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+}
+
+void launch_stokes_gemv(hipStream_t s, const StokesDims& sd, const StokesDev& dv, const double* A, const float* A32,
+                        int inv, const double* x, double* y, double* slot) {
   if (dv.E > 0) {
-    if (ch <= 1) HOPU_LAUNCH(k_stokes_gemv<1>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
-    else if (ch <= 2) HOPU_LAUNCH(k_stokes_gemv<2>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
-    else if (ch <= 3) HOPU_LAUNCH(k_stokes_gemv<3>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
-    else if (ch <= 5) HOPU_LAUNCH(k_stokes_gemv<5>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
-    else if (ch <= 9) HOPU_LAUNCH(k_stokes_gemv<9>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
-    else HOPU_LAUNCH(k_stokes_gemv<16>, grid, blk, lds, s, sd, dv, A, inv, x, y, slot);
+    if (A32) gemv_dispatch(s, sd, dv, A32, inv, x, y, slot);
+    else gemv_dispatch(s, sd, dv, A, inv, x, y, slot);
   }
   const int64_t nv = dv.F * sd.nsd;
   if (nv > 0) hipLaunchKernelGGL(k_stokes_facets, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, sd, dv, slot, y);

@@ -201,8 +201,10 @@ class Hopu:
         check(L.lib().hopu_stokes_sizes(self.h, C.byref(nt), C.byref(nh), C.byref(nx)), self.h)
         return nt.value, nh.value, nx.value
 
-    def stokes_setup(self, nu, dt):
-        check(L.lib().hopu_stokes_setup(self.h, float(nu), float(dt)), self.h)
+    def stokes_setup(self, nu, dt, fp32_precond=False):
+        """Element Schur complements for (nu, dt); fp32_precond keeps S_T^-1 in FP32."""
+        flags = L.HOPU_STOKES_FP32_PRECOND if fp32_precond else 0
+        check(L.lib().hopu_stokes_setup(self.h, float(nu), float(dt), flags), self.h)
 
     def _stokes_vec(self, out):
         n = self.stokes_sizes()[0]

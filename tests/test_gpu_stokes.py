@@ -201,3 +201,34 @@ def test_stokes_step_initial_guess():
     assert its1 < its0, (its1, its0)
     x2, its2 = g.stokes_step(u, out=x0.clone(), rtol=1e-12, guess=True)
     assert its2 <= 1 and _blockerr(sp, host(x2), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("d,k,n,walls", [(2, 2, 4, True), (3, 2, 3, True), (3, 3, 3, False)])
+def test_stokes_fp32_preconditioner(d, k, n, walls):
+    """HOPU_STOKES_FP32_PRECOND: S_T^-1 kept in FP32 (element products in
+    FP64 arithmetic).  C^-1 x then carries the FP32 rounding of S_T^-1's
+    entries (2^-24 relative, summed over nx terms); S, the vectors and the
+    inner products stay FP64, so the step meets the FP64 tolerance."""
+    print(f"stokes fp32 preconditioner d={d} k={k} n={n} walls={walls}", flush=True)
+    m, sp = _case(d, k, n, walls)
+    nu, dt = 0.05, 0.02
+    schur = OST.schur_system(sp, nu, dt)
+    g = _gpu(m, k)
+    g.stokes_setup(nu, dt, fp32_precond=True)
+    nt = g.stokes_sizes()[0]
+    x = np.random.default_rng(5).standard_normal(nt)
+    z = host(g.stokes_precond(dev(x)))
+    zref = OST.bddc_apply(sp, schur, x)
+    ez = _blockerr(sp, z, zref)
+    print(f"  C^-1 x (FP32 S_T^-1): {ez:.2e}", flush=True)
+    assert ez <= 2e-5
+    f = (lambda xx: np.stack([np.sin(np.pi * xx[..., 1])] + [0.0 * xx[..., 0]] * (d - 1), -1)) if walls else \
+        (synth.taylor_green_2d() if d == 2 else synth.taylor_green_3d())
+    un = sp.interpolate(f) + 1e-2 * np.random.default_rng(7).standard_normal(sp.n_dof)
+    r = O.residual(sp, un, -1)
+    us, uh, _, _, _ = OST.step1(sp, un, nu, dt, r)
+    g.set_upwind(-1)
+    xs, its = g.stokes_step(dev(un), rtol=1e-13)
+    e = _blockerr(sp, host(xs), np.concatenate([us, uh]))
+    print(f"  step: {e:.2e} after {its} iterations", flush=True)
+    assert e <= TOL_STEP[k]
