@@ -43,11 +43,13 @@ Readings (the paper does not fix them):
 
 Bases inside the oracle (they do not change u*, u^, gamma or the function
 sigma): the full trace-free space is spanned by the unit matrices e_i e_j^T
-(i != j) and e_i e_i^T - e_d e_d^T, times monomials ((x - x_c)/h)^beta in
-physical coordinates (x_c the barycentre, h = |det J|^{1/d}); Sigma_T is the
-null space (scipy.linalg.null_space, a library primitive) of the facet
-constraints.  W_T uses the skew unit matrices times the same monomials up to
-degree k.
+(i != j) and e_i e_i^T - e_d e_d^T, times monomials (x^ - x^_c)^beta of the
+element's reference coordinates x^ = F_T^-1(x) (x^_c the reference
+barycentre; an affine map keeps polynomial degrees, so this spans P^{k+1}
+of the element, and it stays well conditioned on flat elements, where
+monomials of physical coordinates do not); Sigma_T is the null space
+(scipy.linalg.null_space, a library primitive) of the facet constraints.
+W_T uses the skew unit matrices times the same monomials up to degree k.
 
 Functions:
   step1(sp, un, nu, dt, r=None)        the saddle-point system of eq.
@@ -177,23 +179,24 @@ def element_blocks(sp, T, nu):
     """Blocks of eq. (MCS_step1)'s matrix form for element T, on the local
     Sigma_T basis: Mss [ns][ns], Bgs [ng][ns], Bus [n][ns], Bhs [nh][ns], the
     basis N (full trace-free monomial coefficients -> Sigma_T) and the
-    element's (centre, h).  Full-space index of E_a mono_m: a * nm + m."""
+    reference barycentre of the monomials.  Full-space index of E_a mono_m:
+    a * nm + m."""
     t = sp.topo
     d, k = sp.dim, sp.k
     Ea = tracefree_basis(d)
     Gc = skew_basis(d)
     J, detJ = t.J[T], t.detJ[T]
     x0 = t.xyz[T, 0]
-    xc = t.xyz[T].mean(0)
-    h = abs(detJ) ** (1.0 / d)
+    xc = np.full(d, 1.0 / (d + 1))            # reference barycentre
+    Jinv = np.linalg.inv(J)
     xq_ref, wq_ref, ref_vals, s_ref, ws_ref, ref_face = _ref_tabs(sp)
 
     # volume terms in physical coordinates
     xq = x0[None, :] + xq_ref @ J.T
     wq = wq_ref * abs(detJ)
-    mv, mg = _monomials(d, k + 1, (xq - xc) / h)
-    mg = mg / h                                   # physical gradients
-    gv, _ = _monomials(d, k, (xq - xc) / h)
+    mv, mg = _monomials(d, k + 1, xq_ref - xc)
+    mg = mg @ Jinv                                # physical gradients: grad^ m J^-1
+    gv, _ = _monomials(d, k, xq_ref - xc)
     phi = sp.phys_vals(np.array([T]), ref_vals)[0]  # [q][n][d]
     # a(sigma, tau) = -1/(2 nu) int sigma : tau
     Mfull = -np.kron(np.einsum("aij,bij->ab", Ea, Ea), (mv * wq[:, None]).T @ mv) / (2.0 * nu)
@@ -215,9 +218,9 @@ def element_blocks(sp, T, nu):
     for i in range(d + 1):
         nF, tang, NFn, sgn, xv = facet_frame(sp, T, i)
         nout = sgn * nF
-        xs = xv[0][None, :] + s_ref @ (xv[1:] - xv[0])
         ds = ws_ref * NFn
-        fv, _ = _monomials(d, k + 1, (xs - xc) / h)
+        o, Em, _ = B.ref_facet_map(d, i)
+        fv, _ = _monomials(d, k + 1, o[None, :] + s_ref @ Em.T - xc)
         # v . n_out of the local velocity basis on this facet
         vn = sp.phys_vals(np.array([T]), ref_face[i])[0] @ nout   # [q][n]
         # sigma_nn of E_a mono_m is (n.E_a n) mono_m
@@ -237,7 +240,7 @@ def element_blocks(sp, T, nu):
     else:
         N = np.eye(Bu_full.shape[1])
     return dict(N=N, Mss=N.T @ Mfull @ N, Bgs=Bg_full @ N, Bus=Bu_full @ N,
-                Bhs=Bh_full @ N, xc=xc, h=h)
+                Bhs=Bh_full @ N, xc=xc)
 
 
 def expected_sigma_dim(d, k, n_interior_facets):
@@ -316,8 +319,7 @@ def sigma_at(sp, blocks, sig, T, ref_pts):
     t = sp.topo
     d, k = sp.dim, sp.k
     b = blocks[T]
-    x = t.xyz[T, 0][None, :] + np.atleast_2d(ref_pts) @ t.J[T].T
-    mv, _ = _monomials(d, k + 1, (x - b["xc"]) / b["h"])
+    mv, _ = _monomials(d, k + 1, np.atleast_2d(ref_pts) - b["xc"])
     coef = (b["N"] @ sig[T]).reshape(len(tracefree_basis(d)), -1)  # [a][m]
     return np.einsum("aij,qm,am->qij", tracefree_basis(d), mv, coef)
 

@@ -38,16 +38,17 @@ def _blockerr(sp, v, ref):
 
 
 # The two sides condense sigma and gamma through different bases (the
-# oracle: monomials and a null-space reduction; the library: an orthonormal
-# basis with multipliers), so their rounding differs by the conditioning of
-# the element blocks, which grows with k: the bounds below (entry-wise,
-# relative to each block's largest entry) follow the CPU emulation of the
-# set-up against the oracle (3D k = 3: 2.40e-9 in the u^ block, which holds
-# only the viscous part; the GPU gives the same figure); C^-1 adds the
-# conditioning of S_T.  Against that emulation (same formulas, LAPACK in
-# numpy) the GPU's S x agrees to rounding (EMU_TOL): the kernel's own
-# arithmetic is pinned tighter than the two condensation routes agree.
-TOL_S = {1: 1e-11, 2: 1e-11, 3: 5e-9, 4: 1e-8}
+# oracle: reference-coordinate monomials and a null-space reduction; the
+# library: an orthonormal Dubiner basis with multipliers), so their
+# rounding differs by the conditioning of the element blocks, which grows
+# with k: the bounds below (entry-wise, relative to each block's largest
+# entry) follow the CPU emulation of the set-up against the oracle (S x:
+# 1e-14, 6e-13, 2.4e-11, 2.9e-9 at 2D k = 1..4; 1.3e-13, 6.2e-12, 3.4e-10 at
+# 3D k = 1..3); C^-1 adds the conditioning of S_T.  Against that emulation
+# (same formulas, LAPACK in numpy) the GPU's S x agrees to rounding
+# (EMU_TOL): the kernel's own arithmetic is pinned tighter than the two
+# condensation routes agree.
+TOL_S = {1: 1e-12, 2: 1e-11, 3: 1e-9, 4: 1e-8}
 TOL_C = {1: 1e-10, 2: 1e-10, 3: 5e-9, 4: 1e-7}
 EMU_TOL = 1e-12
 TOL_STEP = {1: 1e-10, 2: 1e-10, 3: 1e-9}
@@ -232,3 +233,29 @@ def test_stokes_fp32_preconditioner(d, k, n, walls):
     e = _blockerr(sp, host(xs), np.concatenate([us, uh]))
     print(f"  step: {e:.2e} after {its} iterations", flush=True)
     assert e <= TOL_STEP[k]
+
+
+def test_stokes_operator_graded_wall_mesh():
+    """S and C^-1 on wall cells of aspect ratio 167 (y nodes 0, 0.002, 0.01,
+    0.05, 0.2, 0.5, 1 under 3 x 3 periodic cubes, 5% jitter), k = 2, against
+    the oracle and the set-up emulation.  (The PCG on S with the element-wise
+    BDDC needs thousands of iterations on such flat tetrahedra, as the mass
+    PCG does; the step is not run here.)"""
+    print("stokes S/C^-1 graded wall mesh", flush=True)
+    y = np.array([0.0, 0.002, 0.01, 0.05, 0.2, 0.5, 1.0])
+    m = synth.kuhn_mesh(3, (3, 6, 3), periodic=(True, False, True), nodes=[None, y, None], jitter=0.05,
+                        jitter_seed=5)
+    sp = Space(m.elem_vid, m.elem_xyz, 2)
+    nu, dt = 1e-3, 1e-3
+    schur = OST.schur_system(sp, nu, dt)
+    g = _gpu(m, 2)
+    g.stokes_setup(nu, dt)
+    nt = g.stokes_sizes()[0]
+    x = np.random.default_rng(8).standard_normal(nt)
+    y1 = host(g.stokes_apply(dev(x)))
+    e_or = _blockerr(sp, y1, schur[0] @ x)
+    e_emu = _blockerr(sp, y1, _emulated_S(m, sp, 2, nu, dt, schur) @ x)
+    z = host(g.stokes_precond(dev(x)))
+    e_c = _blockerr(sp, z, OST.bddc_apply(sp, schur, x))
+    print(f"  S x: {e_or:.2e} (emulation {e_emu:.2e}), C^-1 x: {e_c:.2e}", flush=True)
+    assert e_or <= 1e-10 and e_emu <= EMU_TOL and e_c <= 1e-8
