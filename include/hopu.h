@@ -278,7 +278,7 @@ void hopu_destroy(hopu_ctx ctx);
  * on walls, the forms a_h and b_2h; section 2.3: eq. (MCS_step1), its matrix
  * form, the static condensation S = A - B M^-1 B^t of sigma and gamma, and
  * PCG with the element-wise BDDC preconditioner C^-1 = R S_BDDC^-1 R^t,
- * without primal constraints).  Built for 2D k <= 4 and 3D k <= 3
+ * without primal constraints).  Built for k <= 4 in 2D and 3D
  * (HOPU_EUNSUPPORTED otherwise).
  *
  * Unknown vector X (device, FP64, n_total = n_dof + n_uhat entries): the

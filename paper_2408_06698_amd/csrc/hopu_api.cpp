@@ -1372,7 +1372,7 @@ extern "C" hopu_status hopu_profile_read(hopu_ctx ctx, int kind, int64_t* launch
 // ---------------------------------------------------------------- Stokes
 // Implicit Stokes step (paper section 2.2, spaces and forms; section 2.3,
 // eq. (MCS_step1), static condensation, element-wise BDDC).
-static bool stokes_supported(int dim, int k) { return (dim == 2 && k >= 1 && k <= 4) || (dim == 3 && k >= 1 && k <= 3); }
+static bool stokes_supported(int dim, int k) { return (dim == 2 && k >= 1 && k <= 4) || (dim == 3 && k >= 1 && k <= 4); }
 
 static int64_t stokes_n_uhat(hopu_ctx ctx) { return ctx->mesh.F * (ctx->dim - 1) * ctx->sz.nf; }
 
@@ -1424,7 +1424,7 @@ extern "C" hopu_status hopu_stokes_setup(hopu_ctx ctx, double nu, double dt, int
     return fail(ctx, HOPU_EINVAL, "nu and dt must be positive and finite");
   if (flags & ~HOPU_STOKES_FP32_PRECOND) return fail(ctx, HOPU_EINVAL, "unknown flags");
   if (!stokes_supported(ctx->dim, ctx->k))
-    return fail(ctx, HOPU_EUNSUPPORTED, "the Stokes step is built for 2D k <= 4 and 3D k <= 3");
+    return fail(ctx, HOPU_EUNSUPPORTED, "the Stokes step is built for 2D and 3D k <= 4");
   hopu_status st;
   if (!ctx->st_alloc && (st = stokes_alloc(ctx))) return st;
   ctx->st_ready = false;

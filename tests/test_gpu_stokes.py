@@ -44,11 +44,13 @@ def _blockerr(sp, v, ref):
 # with k: the bounds below (entry-wise, relative to each block's largest
 # entry) follow the CPU emulation of the set-up against the oracle (S x:
 # 1e-14, 6e-13, 2.4e-11, 2.9e-9 at 2D k = 1..4; 1.3e-13, 6.2e-12, 3.4e-10 at
-# 3D k = 1..3); C^-1 adds the conditioning of S_T.  Against that emulation
+# 3D k = 1..3, 1.06e-7 at 3D k = 4, where per element the gap is 1e-9 to
+# 6e-9 and S x cancels); C^-1 adds the conditioning of S_T (3D k = 4:
+# 9.7e-9).  Against that emulation
 # (same formulas, LAPACK in numpy) the GPU's S x agrees to rounding
 # (EMU_TOL): the kernel's own arithmetic is pinned tighter than the two
 # condensation routes agree.
-TOL_S = {1: 1e-12, 2: 1e-11, 3: 1e-9, 4: 1e-8}
+TOL_S = {1: 1e-12, 2: 1e-11, 3: 1e-9, 4: 1e-8, (3, 4): 3e-7}
 TOL_C = {1: 1e-10, 2: 1e-10, 3: 5e-9, 4: 1e-7}
 EMU_TOL = 1e-12
 TOL_STEP = {1: 1e-10, 2: 1e-10, 3: 1e-9}
@@ -73,7 +75,7 @@ def _emulated_S(m, sp, k, nu, dt, schur):
 
 
 CASES = [(2, 1, 4, False), (2, 2, 4, True), (2, 3, 3, False), (2, 4, 3, True),
-         (3, 1, 3, False), (3, 2, 3, True), (3, 3, 3, False)]
+         (3, 1, 3, False), (3, 2, 3, True), (3, 3, 3, False), (3, 4, 3, False)]
 
 
 @pytest.mark.parametrize("d,k,n,walls", CASES)
@@ -91,7 +93,7 @@ def test_stokes_operator_and_preconditioner(d, k, n, walls):
     y = host(g.stokes_apply(dev(x)))
     ref = schur[0] @ x
     print(f"  S x: {_blockerr(sp, y, ref):.2e}", flush=True)
-    assert _blockerr(sp, y, ref) <= TOL_S[k]
+    assert _blockerr(sp, y, ref) <= TOL_S.get((d, k), TOL_S[k])
     yemu = _emulated_S(m, sp, k, nu, dt, schur) @ x
     print(f"  S x against the set-up emulation: {_blockerr(sp, y, yemu):.2e}", flush=True)
     assert _blockerr(sp, y, yemu) <= EMU_TOL
@@ -151,7 +153,7 @@ def test_stokes_errors_and_setup_reuse():
         ref = OST.schur_system(sp, nu, dt)[0] @ xv
         assert _blockerr(sp, y, ref) <= 1e-11
     m3 = synth.kuhn_mesh(3, (3, 3, 3), periodic=(True,) * 3)
-    g4 = _gpu(m3, 4)
+    g4 = _gpu(m3, 5)
     with pytest.raises(HopuError) as e:
         g4.stokes_setup(0.1, 0.1)
     assert e.value.status == HOPU_EUNSUPPORTED
