@@ -109,3 +109,17 @@ def test_binding_checks_buffers_before_the_library():
         _dev(torch.zeros(4, dtype=torch.float64), 4)
     with pytest.raises(ValueError, match="expected 5 entries"):
         _dev(torch.zeros(4, dtype=torch.int8), 5, torch.int8, "l_per_facet")
+
+
+def test_stokes_entry_points_reject_a_null_context():
+    """The implicit Stokes step's calls validate their context first (no HIP
+    call is made), and the host tables of every supported order build."""
+    lib = L.lib()
+    assert lib.hopu_stokes_sizes(None, None, None, None) == L.HOPU_EINVAL
+    assert lib.hopu_stokes_setup(None, 0.1, 0.1, 0) == L.HOPU_EINVAL
+    assert lib.hopu_stokes_apply(None, None, None) == L.HOPU_EINVAL
+    assert lib.hopu_stokes_precond(None, None, None) == L.HOPU_EINVAL
+    assert lib.hopu_stokes_step(None, None, 0, None, 1e-10, 10, None) == L.HOPU_EINVAL
+    for d, k in [(2, 1), (2, 4), (3, 1), (3, 4)]:
+        for which in range(20, 26):
+            assert lib.hopu_host_tables(d, k, which, None, 0) > 0
