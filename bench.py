@@ -28,7 +28,6 @@ only while they fit in --budget-s; a skipped one is named under "skipped".
 Prints one JSON line (metric in DoF-updates/s: n_dof x steps / time).
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -99,12 +98,8 @@ def traffic_from_profiles(kernel_key, source="kernels.hip"):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     summaries (profiles/*traffic*.txt), if one was taken on the current
     kernel source; else None."""
-    src = os.path.join(ROOT, "paper_2408_06698_amd", "csrc", source)
-    text = open(src).read()
-    marker = "// " + "-" * 66 + " launchers"
-    if marker in text:
-        text = text[text.index("namespace hopu {"):text.index(marker)]
-    sha = hashlib.sha256(text.encode()).hexdigest()[:16]
+    from paper_2408_06698_amd.rocpd_summary import source_sha
+    sha = source_sha(open(os.path.join(ROOT, "paper_2408_06698_amd", "csrc", source)).read())
     pdir = os.path.join(ROOT, "profiles")
     for fn in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
         if "traffic" not in fn or not fn.endswith(".txt"):

@@ -14,9 +14,10 @@
 // Wall unknowns (u^ and the multipliers on wall facets) have zero rows; their
 // diagonals are set to one so that every factorisation stays defined.
 //
-// PCG, one workgroup per element: y_T = A_T x_T with A_T = S_T or S_T^-1
-// read once from HBM (symmetric: a column is a contiguous row), facet
-// unknowns written per side and summed per facet in a fixed order.
+// The set-up stores the upper triangles of S_T and S_T^-1, packed by rows
+// (S_T^-1 optionally in FP32).  PCG, one workgroup per element: y_T = A_T x_T
+// with A_T = S_T or S_T^-1 read once from HBM, facet unknowns written per
+// side and summed per facet in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -272,7 +273,7 @@ __global__ void __launch_bounds__(ST_THREADS)
       }
     }
     __syncthreads();
-    // ---- K22 += W^t W; S_T = A_T - K22 (into ST)
+    // ---- K22 += W^t W; S_T = A_T - K22 (formed in full, then packed into ST)
     double* K22 = K + (size_t)n1 * ng + n1;
     block_gram(K + (size_t)n1 * ng, ng, nx, n1, K22, ng, 1.0, true, As, Bs);
     // S_T in full (row stride nx) in G's storage, which is free once K is formed

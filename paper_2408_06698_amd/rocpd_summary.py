@@ -9,6 +9,7 @@
         what the counters read for the largest plain device copy in the runs
 """
 import hashlib
+import re
 import sqlite3
 import statistics
 import sys
@@ -74,15 +75,22 @@ def _counter(db, name):
     return out, last
 
 
-def kernels_sha(src):
-    """SHA-256 (16 hex) of a kernel source: for kernels.hip the part from
-    'namespace hopu {' to the launchers marker, for other sources the whole
-    file."""
-    text = open(src).read()
+def source_sha(text):
+    """SHA-256 (16 hex) of a kernel source as the traffic summaries record
+    it: for kernels.hip the part from 'namespace hopu {' to the launchers
+    marker; for other sources the code with its // comments and blank lines
+    removed (a comment edit does not change what the counters measured)."""
     marker = "// " + "-" * 66 + " launchers"
     if marker in text:
         text = text[text.index("namespace hopu {"):text.index(marker)]
+    else:
+        text = re.sub(r"//[^\n]*", "", text)
+        text = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
     return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def kernels_sha(src):
+    return source_sha(open(src).read())
 
 
 def traffic(fetch_db, write_db, src):
@@ -97,7 +105,7 @@ def traffic(fetch_db, write_db, src):
           f"WRITE_SIZE {wmax:.1f} KiB")
     print(f"#   -> fetch scale {fs:.4f}, write scale {ws:.4f} (bytes = KiB * 1024 * scale)")
     print(f"# kernels_sha: SHA-256 (16 hex) of {src.split('/')[-1]} (kernels.hip: from 'namespace hopu {{' "
-          "to the launchers marker; other sources whole)")
+          "to the launchers marker; other sources without // comments and blank lines)")
     print("# per-launch medians over the launches at full size (> 80% of the kernel's largest)")
     print(f"kernels_sha = {kernels_sha(src)}")
     print(f"fetch_scale = {fs:.6f}")
