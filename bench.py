@@ -347,10 +347,34 @@ def stokes_section(torch, log):
         "timing": "host clock around each hopu_stokes_step and hopu_project call (both synchronise); kernel "
                   "averages from the library's HIP events on every element-product launch",
     }
+    out["cpu_oracle"] = stokes_cpu_oracle()
     log(f"stokes: {ms:.1f} ms per step, {its} PCG iterations, element product {avg_S:.2f} / {avg_C:.2f} ms; "
         f"projection {out['projection_ms']:.1f} ms; FP32 preconditioner {ms32:.1f} ms per step, {its32}")
     h.close()
     return out
+
+
+def stokes_cpu_oracle():
+    """The oracle's implicit Stokes step as it stands, timed on the host: the
+    same recipe (3D Taylor-Green, k = 3, nu = 1/1600, dt = 5e-4, convection
+    with l = 2) on 3^3 x 6 = 162 tets; element blocks (the stress space's
+    basis and the forms), the condensed system and its sparse direct solve,
+    all timed (the oracle forms them per step)."""
+    import numpy as np
+    import synth
+    from oracle import operator as O, stokes as OST
+    from oracle.space import Space
+    mesh, field, cfg = synth.make_config(2, n_override=(3, 3, 3))
+    sp = Space(mesh.elem_vid, mesh.elem_xyz, cfg["k"])
+    un = sp.interpolate(field)
+    r = O.residual(sp, un, cfg["l"])
+    t0 = time.perf_counter()
+    OST.step1_condensed(sp, un, STOKES_NU, cfg["dt"], r)
+    t = time.perf_counter() - t0
+    return {"value": sp.n_dof / t, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"the recipe on 3^3 x 6 = 162 tets ({sp.n_dof} velocity DoFs): one Stokes step by the "
+                      f"oracle's condensed route = {t:.1f} s (element blocks with one BLAS thread, sparse LU)",
+            "seconds": t}
 
 
 def small_latency(torch):
