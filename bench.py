@@ -354,6 +354,37 @@ def stokes_section(torch, log):
     return out
 
 
+def secondary_cpu_oracle(what):
+    """The oracle as it stands on a 3^3 x 6 = 162-tet sample of the 3D
+    Taylor-Green recipe (k = 3), on the host: the projection step (its
+    hybrid-mixed system assembled and solved by sparse LU) of the state after
+    one substep, or 10 substeps with the adaptive order re-selected before
+    the first (residuals in numpy, mass solves by a factored sparse LU)."""
+    import numpy as np
+    import synth
+    from oracle import operator as O, projection as P
+    from oracle.space import Space
+    mesh, field, cfg = synth.make_config(2, n_override=(3, 3, 3))
+    sp = Space(mesh.elem_vid, mesh.elem_xyz, cfg["k"])
+    x = sp.interpolate(field) + 1e-3 * np.random.default_rng(0).standard_normal(sp.n_dof)
+    O.mass_solve(sp, x)  # factor M (untimed, as the GPU's set-up)
+    from threadpoolctl import threadpool_limits
+    if what == "projection":
+        xs = O.substep(sp, x, cfg["dt"], cfg["l"])
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            P.project(sp, xs)
+            t = time.perf_counter() - t0
+        return {"value_ms": t * 1e3, "kind": "oracle", "cores": 1,
+                "sample": f"3^3 x 6 = 162 tets ({sp.n_dof} DoFs): one projection = {t:.2f} s, one thread"}
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        O.substeps_adaptive(sp, x, cfg["dt"], 10, [0.1, 0.2, 0.3, 0.4], every=10)
+        t = time.perf_counter() - t0
+    return {"value": sp.n_dof * 10 / t, "unit": "DoF-updates/s", "kind": "oracle", "cores": 1,
+            "sample": f"3^3 x 6 = 162 tets ({sp.n_dof} DoFs): 10 adaptive substeps = {t:.2f} s, one thread"}
+
+
 def stokes_cpu_oracle():
     """The oracle's implicit Stokes step as it stands, timed on the host: the
     same recipe (3D Taylor-Green, k = 3, nu = 1/1600, dt = 5e-4, convection
@@ -368,12 +399,14 @@ def stokes_cpu_oracle():
     sp = Space(mesh.elem_vid, mesh.elem_xyz, cfg["k"])
     un = sp.interpolate(field)
     r = O.residual(sp, un, cfg["l"])
-    t0 = time.perf_counter()
-    OST.step1_condensed(sp, un, STOKES_NU, cfg["dt"], r)
-    t = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        OST.step1_condensed(sp, un, STOKES_NU, cfg["dt"], r)
+        t = time.perf_counter() - t0
     return {"value": sp.n_dof / t, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"the recipe on 3^3 x 6 = 162 tets ({sp.n_dof} velocity DoFs): one Stokes step by the "
-                      f"oracle's condensed route = {t:.1f} s (element blocks with one BLAS thread, sparse LU)",
+                      f"oracle's condensed route = {t:.1f} s, one thread (element blocks, condensed system, sparse LU)",
             "seconds": t}
 
 
@@ -667,7 +700,27 @@ def main():
             h2.project(u2, un, rtol=1e-13)        # set-up (A^-1) and warm-up
             (_, its), ms = c2.timed(lambda: h2.project(u2, un, rtol=1e-13))
             sec["projection"] = {"ms": ms, "cg_iters": its, "rtol": 1e-13,
-                                 "div_l2_before": h2.diagnostics(u2)[1], "div_l2_after": h2.diagnostics(un)[1]}
+                                 "div_l2_before": h2.diagnostics(u2)[1], "div_l2_after": h2.diagnostics(un)[1],
+                                 "cpu_oracle": secondary_cpu_oracle("projection")}
+        if fits("adaptive", 20):
+            # the adaptive HOPU order (end of section 3.2): orders from the
+            # jump indicator before every 10th substep, the paper's k = 3
+            # thresholds, against the same substeps at the fixed order
+            ua = c2.u0.clone()
+            h2.set_warm_start(False)
+            h2.set_adaptive(10, [0.1, 0.2, 0.3, 0.4], -1)
+            h2.substeps(ua, c2.dt, 1, FP64)
+            h2.set_warm_start(True)
+            _, msa = c2.timed(lambda: h2.substeps(ua, c2.dt, steps2, FP64))
+            orders = h2.facet_orders().to(torch.int64) + 1
+            hist = torch.bincount(orders, minlength=c2.k + 2).cpu().tolist()
+            h2.set_upwind(c2.l)
+            sec["adaptive"] = {"ms_per_step": msa / steps2, "value": h2.n_dof * steps2 / (msa * 1e-3),
+                               "overhead_vs_fixed_l": msa / ms2 - 1.0,
+                               "facet_orders_histogram_from_l=-1": hist,
+                               "protocol": f"1 untimed + {steps2} timed substeps from u0 (orders re-selected "
+                                           "before substeps 0, 10, 20, ...), thresholds 0.1..0.4",
+                               "cpu_oracle": secondary_cpu_oracle("adaptive")}
         out["secondary"] = sec
         h2.close()
         log("secondary done")
