@@ -27,7 +27,7 @@ TRAFFIC_KERNELS = [
     ("elem_fp32_k5", "k_elem<float, 3, 5, 0>"),
     ("modal_k5", "k_modal<double, 3, 5>"),
     ("rupdate", "k_rupdate<2>("),
-    ("stokes_gemv", "k_stokes_gemv<"),
+    ("stokes_gemv", "k_stokes_gemv<9, double>"),
     ("xpay", "k_xpay<2>("),
     ("proj_k3", "k_proj<3, 3, 0>"),
 ]
@@ -127,7 +127,9 @@ BUSY_KERNELS = TRAFFIC_KERNELS + [("elem_bf16x2_k3", "k_elem<float, 3, 3, 2>"),
                                   ("prec_fp32_k3", "k_mass_lds<float, 3, 3, 1>"),
                                   ("elem_bf16x2_k5", "k_elem<float, 3, 5, 2>"),
                                   ("elem_bf16x3_k5", "k_elem<float, 3, 5, 3>"),
-                                  ("prec_fp32_k5", "k_mass_tiled<float, 3, 5, 1>")]
+                                  ("prec_fp32_k5", "k_mass_tiled<float, 3, 5, 1>"),
+                                  ("stokes_gemv_fp32", "k_stokes_gemv<9, float>"),
+                                  ("stokes_setup", "k_stokes_setup(")]
 N_SIMD = 256 * 4  # MI355X: 256 CUs, 4 SIMDs each
 N_XCD = 8
 
