@@ -1395,12 +1395,23 @@ static hopu_status stokes_alloc(hopu_ctx ctx) {
   std::vector<double> sgeo;
   make_stokes_geometry(ctx->dim, ctx->mesh.E, ctx->mesh.xyz, ctx->mesh.geo, ctx->mesh.fid, sgeo);
   const int64_t E = ctx->mesh.E, nX = ctx->n_dof + stokes_n_uhat(ctx);
+  // on a failure part-way, release what this call allocated, so that a later
+  // set-up starts clean instead of allocating a second copy
+  const size_t mark = ctx->allocs.size();
+  auto undo = [&](hopu_status st) {
+    (void)hipStreamSynchronize(ctx->stream);
+    while (ctx->allocs.size() > mark) {
+      (void)hipFree(ctx->allocs.back());
+      ctx->allocs.pop_back();
+    }
+    return st;
+  };
   hopu_status st;
   const double *Ea, *Gc, *MpG, *TV, *Phi, *Mref, *g;
   if ((st = upload(ctx, &Ea, tb.Ea)) || (st = upload(ctx, &Gc, tb.Gc)) || (st = upload(ctx, &MpG, tb.MpG)) ||
       (st = upload(ctx, &TV, tb.TV)) || (st = upload(ctx, &Phi, tb.Phi)) || (st = upload(ctx, &Mref, tb.Mref)) ||
       (st = upload(ctx, &g, sgeo)))
-    return st;
+    return undo(st);
   const size_t nn = (size_t)E * stokes_packed_stride(sd.nx);
   if ((st = dev_alloc(ctx, &ctx->st_S, nn)) || (st = dev_alloc(ctx, &ctx->st_Sinv, nn)) ||
       (st = dev_alloc(ctx, &ctx->st_slot, (size_t)E * (ctx->dim + 1) * sd.nsd)) ||
@@ -1409,7 +1420,7 @@ static hopu_status stokes_alloc(hopu_ctx ctx) {
       (st = dev_alloc(ctx, &ctx->st_b, (size_t)nX)) || (st = dev_alloc(ctx, &ctx->st_mu, (size_t)ctx->n_dof)) ||
       (st = dev_alloc(ctx, &ctx->st_conv, (size_t)ctx->n_dof)) || (st = dev_alloc(ctx, &ctx->st_part, 1024)) ||
       (st = dev_alloc(ctx, &ctx->st_bad, 4)))
-    return st;
+    return undo(st);
   ctx->st_sd = sd;
   ctx->st_dv = StokesDev{Ea, Gc, MpG, TV, Phi, Mref, g, ctx->dm.fid, ctx->dm.facet_elem, ctx->dm.facet_local,
                          E, ctx->mesh.F, ctx->n_dof};

@@ -261,3 +261,24 @@ def test_stokes_operator_graded_wall_mesh():
     e_c = _blockerr(sp, z, OST.bddc_apply(sp, schur, x))
     print(f"  S x: {e_or:.2e} (emulation {e_emu:.2e}), C^-1 x: {e_c:.2e}", flush=True)
     assert e_or <= 1e-10 and e_emu <= EMU_TOL and e_c <= 1e-8
+
+
+def test_stokes_setup_refused_allocation_then_retry():
+    """A refused allocation in the first set-up returns HOPU_ENOMEM and
+    leaves the context usable: the next set-up allocates and works."""
+    import os
+    from paper_2408_06698_amd._lib import HopuError, HOPU_ENOMEM
+    print("stokes set-up: refused allocation, then retry", flush=True)
+    m, sp = _case(2, 2, 3, False)
+    g = _gpu(m, 2)
+    os.environ["HOPU_TEST_FAIL_ALLOC"] = "1"
+    try:
+        with pytest.raises(HopuError) as e:
+            g.stokes_setup(0.1, 0.05)
+        assert e.value.status == HOPU_ENOMEM
+    finally:
+        del os.environ["HOPU_TEST_FAIL_ALLOC"]
+    g.stokes_setup(0.1, 0.05)
+    x = np.random.default_rng(2).standard_normal(g.stokes_sizes()[0])
+    y = host(g.stokes_apply(dev(x)))
+    assert _blockerr(sp, y, OST.schur_system(sp, 0.1, 0.05)[0] @ x) <= 1e-11
