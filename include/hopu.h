@@ -20,7 +20,11 @@
  *     R the averaging operator (section 2.3);
  *   - explicit convection substeps u <- u - dt M^-1 r(u) (the explicit part
  *     of step 1, eq. (MCS_step1));
- *   - transpose Jacobians of r and of the substep chain.
+ *   - transpose Jacobians of r and of the substep chain;
+ *   - the two steps of the operator splitting (section 2.3): the projection
+ *     of eq. (MCS_step2) (hopu_project) and the implicit Stokes step of eq.
+ *     (MCS_step1) with its static condensation and element-wise BDDC
+ *     (hopu_stokes_*).
  *
  * Coefficient vectors ("global layout"): FP64, length n_dof =
  *   [interior-facet block: facets in lexicographic order of their sorted
