@@ -282,3 +282,55 @@ def test_stokes_setup_refused_allocation_then_retry():
     x = np.random.default_rng(2).standard_normal(g.stokes_sizes()[0])
     y = host(g.stokes_apply(dev(x)))
     assert _blockerr(sp, y, OST.schur_system(sp, 0.1, 0.05)[0] @ x) <= 1e-11
+
+
+def test_stokes_full_size_sampled_columns():
+    """At the bench's size and parameters (32^3 x 6 Taylor-Green mesh, k = 3,
+    nu = 1/1600, dt = 5e-4): columns of S and C^-1 at sampled unknowns (a
+    velocity facet DoF, a u^ unknown and an interior DoF of seeded elements)
+    against the oracle's element blocks of the elements that hold them.  The
+    GPU applies S and C^-1 to unit vectors; every other entry must be zero."""
+    print("stokes full-size sampled columns", flush=True)
+    mesh, field, cfg = synth.make_config(2)
+    sp = Space(mesh.elem_vid, mesh.elem_xyz, cfg["k"])
+    nu, dt = 1.0 / 1600.0, cfg["dt"]
+    g = _gpu(mesh, cfg["k"])
+    g.stokes_setup(nu, dt)
+    nt = g.stokes_sizes()[0]
+    hg = OST.uhat_gdof(sp)
+    loc = np.concatenate([sp.gdof, np.where(hg >= 0, sp.n_dof + hg, -1)], 1)
+    nh = hg.shape[1]
+    rng = np.random.default_rng(2408)
+    elems = rng.choice(sp.topo.n_elems, 2, replace=False)
+    cache = {}
+
+    def st(T):
+        if T not in cache:
+            cache[T] = OST._schur_block(sp, OST.element_blocks(sp, T, nu), T, dt, nh)
+        return cache[T]
+
+    for T in elems:
+        for li in (1, sp.n + 2, (sp.dim + 1) * sp.nf + 3):  # facet DoF, u^, interior DoF
+            gi = int(loc[T, li])
+            owners = np.nonzero((loc == gi).any(1))[0]
+            ref_s = np.zeros(nt)
+            ref_c = np.zeros(nt)
+            for T2 in owners:
+                S_T = st(T2)
+                keep = loc[T2] >= 0
+                l2 = int(np.nonzero(loc[T2] == gi)[0][0])
+                ref_s[loc[T2][keep]] += S_T[keep, l2]
+                w = np.where(np.arange(loc.shape[1]) < (sp.dim + 1) * sp.nf, 0.5, 1.0)
+                w[sp.n:] = 0.5
+                e = np.zeros(keep.sum())
+                e[np.nonzero(keep)[0].tolist().index(l2)] = w[l2]
+                z = np.linalg.solve(S_T[np.ix_(keep, keep)], e)
+                ref_c[loc[T2][keep]] += w[keep] * z
+            x = np.zeros(nt)
+            x[gi] = 1.0
+            ys = host(g.stokes_apply(dev(x)))
+            yc = host(g.stokes_precond(dev(x)))
+            es = np.abs(ys - ref_s).max() / np.abs(ref_s).max()
+            ec = np.abs(yc - ref_c).max() / np.abs(ref_c).max()
+            print(f"  element {T} local {li} ({len(owners)} owners): S {es:.2e}, C^-1 {ec:.2e}", flush=True)
+            assert es <= 1e-9 and ec <= 1e-9
