@@ -41,3 +41,24 @@ def test_traffic_read_only_for_the_profiled_source(tmp_path, monkeypatch):
     assert bench.traffic_from_profiles("elem") is None          # no such key
     (tmp_path / "profiles" / "traffic.txt").unlink()
     assert bench.traffic_from_profiles("mass") is None          # no summary
+
+
+def test_traffic_of_other_sources_ignores_comment_edits(tmp_path, monkeypatch):
+    """Sources other than kernels.hip are keyed by their code without //
+    comments and blank lines: a comment edit keeps the recorded traffic, a
+    code edit drops it."""
+    from paper_2408_06698_amd.rocpd_summary import source_sha
+    src = tmp_path / "paper_2408_06698_amd" / "csrc"
+    src.mkdir(parents=True)
+    code = "__global__ void k(double* y) {  // one\n  y[0] = 1.0;\n}\n"
+    (src / "other.hip").write_text(code)
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "x_traffic.txt").write_text(f"kernels_sha = {source_sha(code)}\nk_bytes_per_launch = 777\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.traffic_from_profiles("k", "other.hip") == pytest.approx(777.0)
+    (src / "other.hip").write_text("// a new header comment\n\n" + code.replace("// one", "// two"))
+    assert bench.traffic_from_profiles("k", "other.hip") == pytest.approx(777.0)
+    (src / "other.hip").write_text(code.replace("1.0", "2.0"))
+    assert bench.traffic_from_profiles("k", "other.hip") is None
+
