@@ -498,7 +498,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
-                                   "(this build targets a single MI355X)", "n_gpus": args.gpus}))
+                                   "(the library and its benchmark target a single MI355X)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2408_06698_amd import FP64, FP32_MFMA, BF16X2, BF16X3
